@@ -1,0 +1,118 @@
+/*
+ * es_oracle.h -- plain CPU FP64 oracle for the entropy-stable adaptive
+ * moving-mesh finite-difference scheme of Li, Duan & Tang (arXiv 2202.07989).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously-correct
+ * reference that the GPU path is checked against.  Only the tests, the smoke
+ * check and the CPU-baseline leg of the benchmark may load it.  It shares no
+ * code, header, table or helper with the GPU library.
+ *
+ * Conventions
+ *   - Structured grid, cell-centred computational nodes, i fastest.
+ *   - Every field array is padded with g->ng ghost layers in each active
+ *     direction; padded extents np[k] = n[k] + 2 ng (k < dim), np[2] = 1 in 2D.
+ *   - A field with C components stores component c at offset c * P,
+ *     P = np[0] * np[1] * np[2].
+ *   - State JU has nc = nspec + dim + 1 components
+ *     (J rho_1..J rho_N, J rho v_1..J rho v_d, J E); J has one.
+ *   - Spatial metrics jxi_x hold dim*dim components, component (k*dim + j) is
+ *     J dxi_k/dx_j; time metrics jxi_t hold dim components (J dxi_k/dt).
+ *   - The mesh x holds dim components (x_1..x_d).
+ *   - All functions take host pointers and run synchronously.
+ *
+ * Return codes: 0 ok, -1 invalid argument, -4 non-physical state
+ * (rho_l <= 0, T <= 0 or non-finite), -5 tangled mesh (J <= 0 or Delta_tau <= 0).
+ */
+#ifndef ES_ORACLE_H
+#define ES_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int dim;           /* d = 2 or 3                                          */
+    int nspec;         /* N = 1 or 2                                          */
+    int n[3];          /* interior nodes per direction (n[2] = 1 in 2D)       */
+    int ng;            /* ghost layers (>= 3)                                  */
+    double dxi[3];     /* computational spacings Delta xi_k                    */
+    double len[3];     /* physical period lengths L_k (periodic x ghost rule)  */
+    int w;             /* EC order 2w, w in {1,2,3}                            */
+    double gamma[2];   /* Gamma_l                                              */
+    double cv[2];      /* c_{v,l}                                              */
+    double pinf[2];    /* p_{infty,l}                                          */
+    double chi[3];     /* MR-WENO linear weights                               */
+    double weno_eps;   /* MR-WENO epsilon                                      */
+    int dissipation;   /* 0: EC scheme, 1: ES scheme                           */
+} orc_grid;
+
+typedef struct {
+    int nsig;          /* number of monitor variables kappa (1..4)             */
+    int sigma[4];      /* 0: rho, 1: rho_1, 2: rho_2, 3: p                     */
+    double alpha[4];   /* alpha_k                                              */
+    int n_smooth;      /* low-pass filter passes                               */
+    int n_sweeps;      /* Jacobi iterations mu                                 */
+} orc_monitor;
+
+/* ---- pointwise pieces (exposed for the pins) ---------------------------- */
+int    orc_ncomp(const orc_grid *g);
+void   orc_alpha(int w, double alpha[3]);
+double orc_logmean(double al, double ar);
+int    orc_prim(const orc_grid *g, const double *U, double *rho, double *v,
+                double *T, double *p);
+int    orc_entropy_vars(const orc_grid *g, const double *U, double *V);
+double orc_entropy(const orc_grid *g, const double *U);
+double orc_potential(const orc_grid *g, const double *U);
+double orc_sound_speed(const orc_grid *g, const double *U);
+void   orc_phys_flux(const orc_grid *g, const double *U, int j, double *F);
+/* two-point EC flux; ml, mr = (J dxi_k/dt, J dxi_k/dx_1..x_d) at l and r */
+int    orc_ec_flux(const orc_grid *g, const double *Ul, const double *Ur,
+                   const double *ml, const double *mr, double *F);
+/* rotation matrix T (nc x nc, row-major) for an interface normal n (dim) */
+void   orc_rotation(const orc_grid *g, const double *n, double *T);
+/* interface frame: R (nc x nc, row-major) at the rotated averaged state of
+ * (Ul, Ur) for the averaged metric m = (n_t, n_1..n_d); s = max |eigenvalue| */
+int    orc_interface_frame(const orc_grid *g, const double *Ul, const double *Ur,
+                           const double *m, double *R, double *s);
+double orc_mr5(const double *q, const double *chi, double eps);
+
+/* ---- whole-grid steps ----------------------------------------------------- */
+long   orc_npoints(const orc_grid *g);
+void   orc_fill_ghosts(const orc_grid *g, double *a, int ncomp);
+void   orc_fill_ghosts_x(const orc_grid *g, double *x);
+int    orc_metrics(const orc_grid *g, const double *x_n, const double *disp,
+                   double c_s, double dt, double *jxi_x, double *jxi_t);
+int    orc_rhs(const orc_grid *g, const double *JU, const double *J,
+               const double *jxi_x, const double *jxi_t, double *dJU, double *dJ);
+int    orc_rhs_points(const orc_grid *g, const double *JU, const double *J,
+                      const double *jxi_x, const double *jxi_t, int npts,
+                      const long *pts, double *dJU, double *dJ);
+void   orc_rk_coeffs(int stage, double *a, double *b, double *c);
+int    orc_rk_stage(const orc_grid *g, int stage, double dt,
+                    const double *JU_n, const double *J_n,
+                    const double *JU_s, const double *J_s,
+                    const double *jxi_x, const double *jxi_t,
+                    double *JU_out, double *J_out);
+int    orc_max_wavespeed(const orc_grid *g, const double *JU, const double *J,
+                         const double *jxi_x, double cfl, double *lambda,
+                         double *dt);
+/* monitor Theta after the n_smooth filter passes (the Theta the Jacobi sweeps use) */
+int    orc_monitor_fn(const orc_grid *g, const orc_monitor *m, const double *JU,
+                      const double *J, double *theta);
+int    orc_mesh_redistribute(const orc_grid *g, const orc_monitor *m,
+                             const double *JU, const double *J,
+                             const double *x_n, double *disp, double *dtau,
+                             double *resid);
+double orc_total_entropy(const orc_grid *g, const double *JU, const double *J);
+double orc_entropy_rate(const orc_grid *g, const double *JU, const double *J,
+                        const double *dJU, const double *dJ);
+double orc_es_production(const orc_grid *g, const double *JU, const double *J,
+                         const double *jxi_x, const double *jxi_t);
+int    orc_step(const orc_grid *g, const orc_monitor *m, double cfl,
+                double dt_fixed, int move_mesh, double *JU, double *J,
+                double *x, double *dt_out, double *dtau_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

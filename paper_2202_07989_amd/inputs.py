@@ -1,0 +1,265 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module is shared by the tests of the CPU oracle and by the GPU path.  It
+holds no step of the scheme: it only lays out padded structure-of-arrays
+buffers and writes initial data.  Initial data given in primitive variables
+(rho_l, v, p) are turned into conserved variables with the stiffened-gas
+equation of state of the problem statement (Section 1, eq StiffenedEOS):
+T = (p + sum p_inf,l) / sum rho_l R_l and E = sum (c_vl rho_l T + p_inf,l)
++ rho |v|^2 / 2.
+
+Layout: a field with C components is a float64 array of shape
+(C, np2, np1, np0), np_k = n_k + 2 ng for the active directions (np2 = 1 in
+2D), i.e. component c starts at c * P and i is fastest.  Ghost layers are left
+at zero; filling them is a step of the scheme.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+CHI_DEFAULT = (1.0 / 111.0, 10.0 / 111.0, 100.0 / 111.0)   # Appendix A default
+CHI_SHOCK = (0.95, 0.045, 0.005)                            # Ex. 5.3 / 5.10 weights
+WATER_AIR = dict(gamma=(4.4, 1.4), cv=(1.0, 1.0), pinf=(6.0e8, 0.0))
+
+
+# --------------------------------------------------------------------------
+# workload specs
+# --------------------------------------------------------------------------
+def make_spec(dim, nspec, n, *, box=None, gamma=(1.4,), cv=(1.0,), pinf=(0.0,),
+              chi=CHI_DEFAULT, w=3, ng=3, dissipation=1, weno_eps=1e-10):
+    n = tuple(n) + (1,) * (3 - len(n))
+    box = box or (1.0,) * dim
+    box = tuple(box) + (1.0,) * (3 - len(box))
+    dxi = tuple(box[k] / n[k] if k < dim else 1.0 for k in range(3))
+    return dict(dim=dim, nspec=nspec, n=n, ng=ng, dxi=dxi, len=box, w=w,
+                gamma=tuple(gamma), cv=tuple(cv), pinf=tuple(pinf), chi=tuple(chi),
+                weno_eps=weno_eps, dissipation=dissipation)
+
+
+def spec_c1(n=64):
+    """2D single-species ideal gas (Gamma 1.4), periodic curvilinear mesh."""
+    return make_spec(2, 1, (n, n), gamma=(1.4,), cv=(1.0,), pinf=(0.0,), chi=CHI_DEFAULT)
+
+
+def spec_c2(n=512):
+    """2D two-species stiffened gas (water Gamma 4.4, p_inf 6e8; air 1.4)."""
+    return make_spec(2, 2, (n, n), chi=CHI_SHOCK, **WATER_AIR)
+
+
+def spec_c3(n=256):
+    """3D two-species stiffened gas, same materials as spec_c2."""
+    return make_spec(3, 2, (n, n, n), chi=CHI_SHOCK, **WATER_AIR)
+
+
+def monitor_spec(n_sweeps=10, n_smooth=3, sigma=(0,), alpha=(1200.0,)):
+    return dict(sigma=list(sigma), alpha=list(alpha), n_smooth=n_smooth, n_sweeps=n_sweeps)
+
+
+# --------------------------------------------------------------------------
+# layout helpers
+# --------------------------------------------------------------------------
+def padded_dims(spec):
+    ng = spec["ng"]
+    return tuple(spec["n"][k] + 2 * ng if k < spec["dim"] else 1 for k in range(3))
+
+
+def npoints(spec):
+    a, b, c = padded_dims(spec)
+    return a * b * c
+
+
+def ncomp(spec):
+    return spec["nspec"] + spec["dim"] + 1
+
+
+def zeros(spec, ncomp_):
+    np0, np1, np2 = padded_dims(spec)
+    return np.zeros((ncomp_, np2, np1, np0), dtype=np.float64)
+
+
+def interior(spec):
+    """Index tuple selecting the interior of a (C, np2, np1, np0) array."""
+    ng, d = spec["ng"], spec["dim"]
+    sl = [slice(ng, ng + spec["n"][k]) if k < d else slice(0, 1) for k in range(3)]
+    return (slice(None), sl[2], sl[1], sl[0])
+
+
+def xi_nodes(spec):
+    """Cell-centred computational coordinates of the interior nodes,
+    returned as a list of d arrays shaped (n2, n1, n0)."""
+    d = spec["dim"]
+    ax = [(np.arange(spec["n"][k]) + 0.5) * spec["dxi"][k] if k < d else np.zeros(1)
+          for k in range(3)]
+    g2, g1, g0 = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return [g0, g1, g2][:d]
+
+
+def conserved(spec, rho, v, p):
+    """Stiffened-gas EOS: (rho_l list, v list, p) -> U (C, n2, n1, n0)."""
+    N, d = spec["nspec"], spec["dim"]
+    cv, gam, pinf = spec["cv"], spec["gamma"], spec["pinf"]
+    rR = sum(rho[l] * cv[l] * (gam[l] - 1.0) for l in range(N))
+    pinf_t = sum(pinf[l] for l in range(N))
+    T = (p + pinf_t) / rR
+    rhot = sum(rho[l] for l in range(N))
+    kin = 0.5 * rhot * sum(v[m] * v[m] for m in range(d))
+    E = sum(cv[l] * rho[l] * T + pinf[l] for l in range(N)) + kin
+    comps = [rho[l] for l in range(N)] + [rhot * v[m] for m in range(d)] + [E]
+    return np.stack([np.broadcast_to(c, rho[0].shape) for c in comps])
+
+
+def assemble(spec, U, J, x):
+    """Place interior U (C,...), J (...) and x (d,...) into padded buffers
+    and return (JU, J, x) with JU = J * U."""
+    I = interior(spec)
+    nc = ncomp(spec)
+    JUp = zeros(spec, nc)
+    Jp = zeros(spec, 1)
+    xp = zeros(spec, spec["dim"])
+    JUp[I] = J[None] * U
+    Jp[I] = J[None]
+    xp[I] = np.stack(x)
+    return JUp, Jp, xp
+
+
+# --------------------------------------------------------------------------
+# C1: smooth advection on the periodic curvilinear mesh
+#   x = xi + 0.1 sin(2 pi xi) sin(2 pi eta), y = eta + (same),
+#   J = 1 + 0.2 pi sin(2 pi (xi + eta)); rho = 1 + 0.2 sin(2 pi (x + y)),
+#   v = (1, 1), p = 1.  Exact: rho(x, y, t) = 1 + 0.2 sin(2 pi (x + y - 2 t)).
+# --------------------------------------------------------------------------
+def c1_mesh(spec, amp=0.1):
+    xi, eta = xi_nodes(spec)
+    pert = amp * np.sin(2 * np.pi * xi) * np.sin(2 * np.pi * eta)
+    x, y = xi + pert, eta + pert
+    J = (1 + 2 * np.pi * amp * np.cos(2 * np.pi * xi) * np.sin(2 * np.pi * eta)) * \
+        (1 + 2 * np.pi * amp * np.sin(2 * np.pi * xi) * np.cos(2 * np.pi * eta)) - \
+        (2 * np.pi * amp) ** 2 * np.sin(2 * np.pi * xi) * np.cos(2 * np.pi * eta) * \
+        np.cos(2 * np.pi * xi) * np.sin(2 * np.pi * eta)
+    return [x, y], J
+
+
+def c1_exact_rho(x, y, t):
+    return 1.0 + 0.2 * np.sin(2 * np.pi * (x + y - 2.0 * t))
+
+
+def init_c1(spec, amp=0.1):
+    (x, y), J = c1_mesh(spec, amp)
+    rho = c1_exact_rho(x, y, 0.0)
+    one = np.ones_like(rho)
+    U = conserved(spec, [rho], [one, one], one)
+    return assemble(spec, U, J, [x, y])
+
+
+# --------------------------------------------------------------------------
+# shock-bubble data (C2, C3): water with a trace of air, an air bubble with a
+# trace of water, and a planar Mach-M_s shock in the water.
+# Post-shock state: stiffened-gas normal-shock relations for a shock moving
+# into the pre-shock state at rest (ideal-gas relations with p -> p + p_inf):
+#   rho1/rho0 = (G+1) M^2 / ((G-1) M^2 + 2),
+#   p1 + pinf = (p0 + pinf)(2 G M^2 - G + 1)/(G + 1),
+#   u1 = M c0 (1 - rho0/rho1), c0^2 = G (p0 + pinf)/rho0,
+# with the mixture Gamma and p_inf of the pre-shock water; mass fractions kept.
+# --------------------------------------------------------------------------
+def _post_shock(spec, rho0, p0, mach):
+    cv, gam, pinf = spec["cv"], spec["gamma"], spec["pinf"]
+    N = spec["nspec"]
+    G = sum(gam[l] * cv[l] * rho0[l] for l in range(N)) / sum(cv[l] * rho0[l] for l in range(N))
+    pi = sum(pinf[:N])
+    r0 = sum(rho0)
+    ratio = (G + 1) * mach ** 2 / ((G - 1) * mach ** 2 + 2)
+    p1 = (p0 + pi) * (2 * G * mach ** 2 - G + 1) / (G + 1) - pi
+    c0 = math.sqrt(G * (p0 + pi) / r0)
+    u1 = mach * c0 * (1 - 1 / ratio)
+    return [r * ratio for r in rho0], p1, u1
+
+
+def _bubble_radius_3d(n_hat, seed=2202079, modes=10, amp=0.02, r0=0.2):
+    rng = np.random.default_rng(seed)
+    e = rng.normal(size=(modes, 3))
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    l = rng.integers(2, 9, size=modes)
+    psi = rng.uniform(0, 2 * np.pi, size=modes)
+    a = rng.uniform(-1, 1, size=modes)
+    a /= np.abs(a).sum()
+    r = np.ones(n_hat.shape[1:])
+    for m in range(modes):
+        cosang = np.clip(np.tensordot(e[m], n_hat, axes=(0, 0)), -1.0, 1.0)
+        r += amp * a[m] * np.cos(l[m] * np.arccos(cosang) + psi[m])
+    return r0 * r
+
+
+def init_shock_bubble(spec, mach=1.5, shock_x=0.2, trace=1e-3, p0=1.0e5,
+                      rho_water=1000.0, rho_air=1.0, seed=2202079):
+    d = spec["dim"]
+    xi = xi_nodes(spec)
+    x = [c.copy() for c in xi]                                   # initial mesh x = xi
+    J = np.ones_like(xi[0])
+    water = [rho_water - trace, trace]
+    air = [trace, rho_air - trace]
+    centre = [0.5] * d
+    rel = np.stack([x[k] - centre[k] for k in range(d)])
+    rad = np.sqrt((rel ** 2).sum(axis=0))
+    if d == 3:
+        n_hat = rel / np.maximum(rad, 1e-300)
+        rb = _bubble_radius_3d(n_hat, seed=seed)
+    else:
+        rb = 0.2
+    in_bubble = rad < rb
+    post = x[0] < shock_x
+    rho_s, p1, u1 = _post_shock(spec, water, p0, mach)
+    rho = [np.where(in_bubble, air[l], np.where(post, rho_s[l], water[l])) for l in range(2)]
+    p = np.where(in_bubble, p0, np.where(post, p1, p0))
+    v = [np.where(post & ~in_bubble, u1, 0.0)] + [np.zeros_like(p) for _ in range(d - 1)]
+    U = conserved(spec, rho, v, p)
+    return assemble(spec, U, J, x)
+
+
+# --------------------------------------------------------------------------
+# random smooth periodic data (tests): a few Fourier modes per field
+# --------------------------------------------------------------------------
+def _smooth_field(rng, xi, modes=3):
+    f = np.zeros_like(xi[0])
+    for _ in range(modes):
+        kv = rng.integers(-2, 3, size=len(xi))
+        ph = rng.uniform(0, 2 * np.pi)
+        a = rng.uniform(-1, 1)
+        f += a * np.sin(2 * np.pi * sum(int(kv[k]) * xi[k] for k in range(len(xi))) + ph)
+    return f / modes
+
+
+def random_mesh(spec, seed, amp=0.03):
+    """x = xi + smooth periodic perturbation (a valid, untangled mesh)."""
+    rng = np.random.default_rng(seed)
+    xi = xi_nodes(spec)
+    return [xi[k] + amp * spec["len"][k] * _smooth_field(rng, xi) for k in range(spec["dim"])]
+
+
+def random_state(spec, seed, noise=0.0, rho_range=(0.5, 2.0), p_range=(0.5, 2.0), vmax=0.5):
+    """Smooth random primitive fields, optionally with white noise (tests
+    nonlinear WENO weights everywhere)."""
+    rng = np.random.default_rng(seed)
+    xi = xi_nodes(spec)
+    N, d = spec["nspec"], spec["dim"]
+
+    def fld(lo, hi):
+        f = 0.5 + 0.5 * _smooth_field(rng, xi)
+        if noise:
+            f = np.clip(f + noise * rng.uniform(-1, 1, size=f.shape), 0.0, 1.0)
+        return lo + (hi - lo) * f
+
+    rho = [fld(*rho_range) for _ in range(N)]
+    p = fld(*p_range)
+    v = [fld(-vmax, vmax) for _ in range(d)]
+    return rho, v, p
+
+
+def init_random(spec, seed, noise=0.0, mesh_amp=0.03, **kw):
+    from_mesh = random_mesh(spec, seed + 1, amp=mesh_amp)
+    rho, v, p = random_state(spec, seed, noise=noise, **kw)
+    U = conserved(spec, rho, v, p)
+    rng = np.random.default_rng(seed + 2)
+    J = 1.0 + 0.2 * _smooth_field(rng, xi_nodes(spec))
+    return assemble(spec, U, J, from_mesh)
