@@ -1,0 +1,173 @@
+/*
+ * es.h -- C-ABI of libes.so, the MI355X (gfx950) path of the entropy-stable
+ * adaptive moving-mesh finite-difference scheme of Li, Duan & Tang,
+ * arXiv 2202.07989, for 2D/3D one- and two-species compressible Euler with
+ * the stiffened equation of state.
+ *
+ * Data layout (every array is caller-owned device memory, FP64, contiguous)
+ *   - Structured grid of cell-centred computational nodes, i fastest.
+ *   - Each field is padded by g->ng ghost layers in every active direction:
+ *     np[k] = n[k] + 2 ng for k < dim, np[2] = 1 in 2D, P = np0*np1*np2.
+ *   - A field with C components stores component c at offset c*P.
+ *   - JU: nc = nspec + dim + 1 components (J rho_1..J rho_N, J rho v, J E);
+ *     J: 1 component; x, disp: dim components (mesh x_1..x_d and a mesh
+ *     displacement); jxi_x: dim*dim components, component k*dim + j is
+ *     J dxi_k/dx_j; jxi_t: dim components, J dxi_k/dt.
+ *   - Device scalars (dt, lambda, Delta_tau, entropy sums) are single FP64
+ *     values in device memory so a step needs no host synchronisation.
+ *   - The grid is periodic in every direction; ghost layers are filled by
+ *     es_fill_ghosts / es_fill_ghosts_x.
+ *
+ * Streams: every call is asynchronous on the given hipStream_t (passed as
+ * void*, NULL = default stream).  A context must not be used from two host
+ * threads at once, and two calls on one context must not overlap on
+ * different streams (they share its workspace).
+ *
+ * Errors: calls return ES_OK (0) or a negative code.  Argument errors are
+ * reported synchronously before anything is launched (ES_EINVAL,
+ * ES_EUNSUPPORTED); ES_EHIP reports a failed launch or allocation.  Data
+ * errors found inside kernels set bits of a device status word that
+ * es_status() returns (ES_ST_NONPHYS: rho_l <= 0, T <= 0 or a non-finite
+ * state; ES_ST_TANGLE: J <= 0 or Delta_tau <= 0).  Nothing is clamped or
+ * repaired.
+ */
+#ifndef ES_H
+#define ES_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ES_OK = 0,
+    ES_EINVAL = -1,        /* bad argument (null pointer, size, stage)        */
+    ES_EUNSUPPORTED = -2,  /* dim not 2/3, nspec not 1/2, w not 1..3, ng < 3  */
+    ES_EHIP = -3,          /* HIP launch or allocation failure                */
+    ES_ENONPHYS = -4,      /* returned by es_status when ES_ST_NONPHYS is set */
+    ES_ETANGLE = -5        /* returned by es_status when ES_ST_TANGLE is set  */
+};
+
+enum { ES_ST_NONPHYS = 1u, ES_ST_TANGLE = 2u };
+
+enum { ES_FP64 = 0, ES_MIXED = 1 };
+
+typedef struct {
+    int dim;           /* d = 2 or 3                                            */
+    int nspec;         /* N = 1 or 2                                            */
+    int n[3];          /* interior nodes per direction (>= ng); n[2] = 1 in 2D  */
+    int ng;            /* ghost layers, >= 3                                    */
+    double dxi[3];     /* computational spacings Delta xi_k (> 0)               */
+    double len[3];     /* physical period lengths L_k used by es_fill_ghosts_x  */
+    int w;             /* EC flux order 2w, w in {1, 2, 3}                      */
+    double gamma[2];   /* Gamma_l > 1                                           */
+    double cv[2];      /* c_{v,l} > 0                                           */
+    double pinf[2];    /* p_{infty,l} >= 0                                      */
+    double chi[3];     /* MR-WENO linear weights (positive, sum 1)              */
+    double weno_eps;   /* MR-WENO epsilon                                       */
+    int dissipation;   /* 0: entropy-conservative scheme, 1: entropy-stable     */
+    int precision;     /* ES_FP64, or ES_MIXED: FP32 flux/WENO arithmetic with  */
+                       /* FP64 log means, metrics, mesh and entropy sums        */
+} es_grid;
+
+typedef struct {
+    int nsig;          /* number of monitor variables kappa, 1..4               */
+    int sigma[4];      /* 0: rho, 1: rho_1, 2: rho_2, 3: p                      */
+    double alpha[4];   /* alpha_k >= 0                                          */
+    int n_smooth;      /* low-pass filter passes                                */
+    int n_sweeps;      /* Jacobi iterations mu (1..4096)                        */
+} es_monitor;
+
+typedef struct es_ctx es_ctx;
+
+/* Create a context for one grid (validates g, allocates reduction scratch and
+ * the status word on the current device).  Owns only its workspace. */
+int es_create(const es_grid *g, es_ctx **out);
+int es_destroy(es_ctx *c);
+
+/* Periodic ghost layers of an ncomp-component field (plain copies). */
+int es_fill_ghosts(es_ctx *c, double *a, int ncomp, void *stream);
+
+/* Periodic ghost layers of the mesh x: component k gains +-L_k when wrapped
+ * along direction k (x(xi + L e_k) = x(xi) + L_k e_k). */
+int es_fill_ghosts_x(es_ctx *c, double *x, void *stream);
+
+/* Section 3.2, eq SCLCoeff / eq VCLCoeff: metrics of the stage mesh
+ * x = x_n + c_s * disp (disp may be NULL: fixed mesh).  jxi_x gets the
+ * 2w-th order conservative cross-derivative form at interior nodes; jxi_t =
+ * -sum_j (disp_j / dt) jxi_x[k][j] when disp and dt_dev are given, else 0.
+ * Ghost layers of the outputs are filled periodically.  x_n and disp need
+ * valid ghost layers.  flags: 0, or ES_METRICS_VCL_ONLY to recompute only
+ * jxi_t from an existing jxi_x. */
+enum { ES_METRICS_VCL_ONLY = 1 };
+int es_metrics(es_ctx *c, const double *x_n, const double *disp, double c_s,
+               const double *dt_dev, double *jxi_x, double *jxi_t, int flags,
+               void *stream);
+
+/* Sections 3.1-3.4, eq semi_U / eq semi_J with the ES flux eq HOstable (or
+ * the EC flux eq ECFlux_curv_2p when dissipation = 0): the semi-discrete
+ * right-hand side d(JU)/dt, dJ/dt at interior nodes.  Inputs need valid
+ * ghost layers; jxi_t may be NULL (fixed mesh).  dJU/dJ ghost layers are
+ * not written; dJU/dJ must not alias the inputs. */
+int es_rhs(es_ctx *c, const double *JU, const double *J, const double *jxi_x,
+           const double *jxi_t, double *dJU, double *dJ, void *stream);
+
+/* Section 5, SSP-RK3 (Shu-Osher form) stage s = 0, 1, 2 on Q = (JU, J):
+ *   Q_out = a_s Q_n + b_s (Q_s + dt L(Q_s)), (a, b) = (0, 1), (3/4, 1/4),
+ *   (1/3, 2/3), fused with the right-hand side.  dt is read from dt_dev.
+ *   Q_out accumulates the direction sweeps, so it must alias neither Q_s
+ *   nor Q_n (ES_EINVAL). */
+int es_rk_stage(es_ctx *c, int stage, const double *dt_dev,
+                const double *JU_n, const double *J_n,
+                const double *JU_s, const double *J_s,
+                const double *jxi_x, const double *jxi_t,
+                double *JU_out, double *J_out, void *stream);
+
+/* Section 5, eq cfl: lambda = max_i sum_k (|v.n_k| + c |n_k|) / (J_i dxi_k)
+ * with n_k = J dxi_k/dx (zero mesh velocity), dt = cfl / lambda; both
+ * written to device scalars (either pointer may be NULL). */
+int max_wavespeed(es_ctx *c, const double *JU, const double *J,
+                  const double *jxi_x, double cfl, double *lambda_dev,
+                  double *dt_dev, void *stream);
+
+/* Section 4: monitor eq monitor from sigma = JU/J components, n_smooth
+ * passes of the low-pass filter, n_sweeps Jacobi iterations of the mesh
+ * equations, movement limiter Delta_tau and disp = Delta_tau (x^[mu] - x_n).
+ * Inputs need valid ghost layers; disp gets periodic ghost layers.
+ * dtau_dev (1 value) and resid_dev (n_sweeps values: max |x^[nu+1] -
+ * x^[nu]|) may be NULL. */
+int mesh_redistribute(es_ctx *c, const es_monitor *m, const double *JU,
+                      const double *J, const double *x_n, double *disp,
+                      double *dtau_dev, double *resid_dev, void *stream);
+
+/* Section 5, total entropy sum_i J_i eta(U_i) dxi_1..dxi_d (fixed-order
+ * FP64 sum) into one device scalar. */
+int es_entropy(es_ctx *c, const double *JU, const double *J, double *total_dev,
+               void *stream);
+
+/* entropy rate sum_i (V_i . dJU_i - phi_i dJ_i) dxi_1..dxi_d (fixed order). */
+int es_entropy_rate(es_ctx *c, const double *JU, const double *J,
+                    const double *dJU, const double *dJ, double *rate_dev,
+                    void *stream);
+
+/* One time step (Sections 4-5): ghost layers, mesh_redistribute when
+ * move_mesh, metrics of x_n, dt from max_wavespeed (or dt_fixed > 0), three
+ * RK stages on the stage meshes x_n + c_s disp (c = 0, 1, 1/2), and
+ * x_{n+1} = x_n + disp.  JU, J, x are updated in place; dt and Delta_tau
+ * are written to dt_dev / dtau_dev when given.  m may be NULL when
+ * move_mesh = 0. */
+int es_step(es_ctx *c, const es_monitor *m, double cfl, double dt_fixed,
+            int move_mesh, double *JU, double *J, double *x, double *dt_dev,
+            double *dtau_dev, void *stream);
+
+/* Synchronise the stream and return the status word (bits ES_ST_*) in
+ * *flags; returns ES_ENONPHYS / ES_ETANGLE when a bit is set, else ES_OK.
+ * reset != 0 clears the word afterwards. */
+int es_status(es_ctx *c, void *stream, unsigned *flags, int reset);
+
+/* Number of padded points P of the context's grid. */
+long es_npoints(const es_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

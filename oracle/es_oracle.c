@@ -595,6 +595,7 @@ int orc_metrics(const orc_grid *g, const double *x_n, const double *disp,
     if (!xs) return ORC_EINVAL;
     for (long t = 0; t < d * P; t++) xs[t] = x_n[t] + (disp ? c_s * disp[t] : 0.0);
 
+#pragma omp parallel for collapse(2) schedule(static)
     for (int i2 = lo_(g, 2); i2 < hi_(g, 2); i2++)
         for (int i1 = lo_(g, 1); i1 < hi_(g, 1); i1++)
             for (int i0 = lo_(g, 0); i0 < hi_(g, 0); i0++) {
@@ -641,7 +642,7 @@ int orc_metrics(const orc_grid *g, const double *x_n, const double *disp,
 /* Readings: interface metrics nbar = (m_i + m_{i+1})/2 for the dissipation; */
 /* W_j = R^T T V(U_j) for j = i-2..i+3 with R, T frozen at the interface;    */
 /* W^+ is MR5 of the mirrored sequence W_{i+3..i-1}; Y_mm = 1 only if        */
-/* [[W_m]]^WENO [[W_m]] > 0.                                                */
+/* [[W_m]]^WENO [[W_m]] > 0 and [[W_m]] is not zero to working precision.    */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     const orc_grid *g;
@@ -718,7 +719,10 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
         double Wplus = orc_mr5(qp, g->chi, g->weno_eps);
         double JW = Wplus - Wminus;
         double jump = W[3][c] - W[2][c];
-        int Y = (JW * jump > 0.0);
+        /* reading of sign(0) at working precision: a jump below 1e-12 of
+           |W_i| + |W_{i+1}| is zero (across a contact the acoustic jumps
+           vanish up to rounding), so Y_mm = 0 there */
+        int Y = (JW * jump > 0.0) && (fabs(jump) > 1.0e-12 * (fabs(W[2][c]) + fabs(W[3][c])));
         Z[c] = Y ? JW : 0.0;
         if (Y) pr += 0.5 * s * jump * JW;
     }

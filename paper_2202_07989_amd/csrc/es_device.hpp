@@ -1,0 +1,298 @@
+// es_device.hpp -- device-side building blocks of the gfx950 path.
+//
+// Li, Duan & Tang, arXiv 2202.07989.  Everything here is evaluated per node
+// or per interface inside the kernels of es_rhs.hip / es_kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace es {
+
+// --------------------------------------------------------------------------
+// parameters passed by value to every kernel
+// --------------------------------------------------------------------------
+struct Phys {
+    int nspec, dim, nc, w, dissipation;
+    double cv[2], gam[2], pinf[2], Rg[2], cvgam[2];
+    double pinf_tot;
+    double alpha[3];          // alpha_{w,m}
+    double chi[3], eps;       // MR-WENO linear weights and epsilon
+    double ichi3, c1c3, c2c3; // 1/chi_3, chi_1/chi_3, chi_2/chi_3
+};
+
+struct Geo {
+    int dim, ng;
+    int n[3];                 // interior nodes
+    int np[3];                // padded extents
+    long P;                   // points per component
+    double dxi[3], idxi[3], len[3];
+};
+
+__device__ __forceinline__ long node_index(const Geo& g, int i0, int i1, int i2)
+{
+    return ((long)i2 * g.np[1] + i1) * g.np[0] + i0;
+}
+
+__device__ __forceinline__ long dir_stride(const Geo& g, int k)
+{
+    return k == 0 ? 1L : (k == 1 ? (long)g.np[0] : (long)g.np[0] * g.np[1]);
+}
+
+// --------------------------------------------------------------------------
+// logarithmic mean [[a]]/[[ln a]] (Section 3.3.1) from precomputed node logs.
+// Near a = b the ratio is replaced by the series of ln(zeta)/(2f) in
+// u = ((a-b)/(a+b))^2 (cut-off u < 1e-4), exact to rounding there.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double logmean(double a, double b, double la, double lb)
+{
+    const double d = a - b, s = a + b;
+    if (d * d < 1.0e-4 * (s * s)) {
+        const double u = (d * d) / (s * s);
+        const double F = 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0)));
+        return s / (2.0 * F);
+    }
+    return d / (la - lb);
+}
+
+// --------------------------------------------------------------------------
+// fifth-order multi-resolution WENO (Appendix A): value at the right face of
+// the centre cell of (q_-2 .. q_2).  h_2, h_3 are the Legendre expansions
+// collapsed to their face values; beta_1 is the min of squared one-sided
+// differences; beta_2, beta_3 are the printed closed forms.
+// --------------------------------------------------------------------------
+template <typename R>
+struct Weno {
+    R chi1, chi2, chi3, eps, ichi3, c1c3, c2c3;
+    R zero_tol;   // relative size below which a jump counts as zero in the sign test
+};
+
+template <typename R>
+__device__ __forceinline__ R mr5(R qm2, R qm1, R q0, R qp1, R qp2, const Weno<R>& W)
+{
+    const R dl = q0 - qm1, dr = qp1 - q0;
+    const R b1 = fmin(dl * dl, dr * dr);
+    const R a2 = R(0.5) * (qp1 - qm1);
+    const R a3 = R(0.5) * (qm1 - R(2) * q0 + qp1);
+    const R b2 = a2 * a2 + R(13.0 / 3.0) * a3 * a3;
+    const R c2 = (R(11) * (qm2 - qp2) + R(82) * (qp1 - qm1)) * R(1.0 / 120.0);
+    const R c3 = (R(-3) * (qm2 + qp2) + R(40) * (qm1 + qp1) - R(74) * q0) * R(1.0 / 56.0);
+    const R c4 = ((qp2 - qm2) + R(2) * (qm1 - qp1)) * R(1.0 / 12.0);
+    const R c5 = ((qm2 + qp2) - R(4) * (qm1 + qp1) + R(6) * q0) * R(1.0 / 24.0);
+    const R t1 = c2 + R(0.1) * c4, t2 = c3 + R(123.0 / 455.0) * c5;
+    const R b3 = t1 * t1 + R(13.0 / 3.0) * t2 * t2 + R(781.0 / 20.0) * c4 * c4
+               + R(1421461.0 / 2275.0) * c5 * c5;
+    R tau = R(0.5) * (fabs(b3 - b1) + fabs(b3 - b2));
+    tau = tau * tau;
+    const R w1 = W.chi1 * (R(1) + tau / (W.eps + b1));
+    const R w2 = W.chi2 * (R(1) + tau / (W.eps + b2));
+    const R w3 = W.chi3 * (R(1) + tau / (W.eps + b3));
+    const R h1 = q0;
+    const R h2 = (R(-1) * qm1 + R(5) * q0 + R(2) * qp1) * R(1.0 / 6.0);
+    const R h3 = (R(2) * qm2 - R(13) * qm1 + R(47) * q0 + R(27) * qp1 - R(3) * qp2) * R(1.0 / 60.0);
+    const R hc = h3 * W.ichi3 - W.c1c3 * h1 - W.c2c3 * h2;
+    return (w1 * h1 + w2 * h2 + w3 * hc) / (w1 + w2 + w3);
+}
+
+// --------------------------------------------------------------------------
+// velocity-block rotation T (eq rotamatrix): first row n/|n|; tangential
+// rows from theta = atan2(n2, n1) (0 when n1 = n2 = 0) and phi.
+// --------------------------------------------------------------------------
+template <int D, typename R>
+struct Rot {
+    R t[D][D];
+};
+
+template <int D, typename R>
+__device__ __forceinline__ void make_rot(const R n[D], R inv_norm, Rot<D, R>& T)
+{
+    if constexpr (D == 2) {
+        const R c = n[0] * inv_norm, s = n[1] * inv_norm;
+        T.t[0][0] = c;  T.t[0][1] = s;
+        T.t[1][0] = -s; T.t[1][1] = c;
+    } else {
+        const R r12sq = n[0] * n[0] + n[1] * n[1];
+        R ct = R(1), st = R(0), cp = R(0);
+        if (r12sq > R(0)) {
+            const R r12 = sqrt(r12sq);
+            const R ir12 = R(1) / r12;
+            ct = n[0] * ir12;
+            st = n[1] * ir12;
+            cp = r12 * inv_norm;
+        }
+        const R sp = n[2] * inv_norm;
+        T.t[0][0] = cp * ct;  T.t[0][1] = cp * st;  T.t[0][2] = sp;
+        T.t[1][0] = -st;      T.t[1][1] = ct;       T.t[1][2] = R(0);
+        T.t[2][0] = -sp * ct; T.t[2][1] = -sp * st; T.t[2][2] = cp;
+    }
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void rot_apply(const Rot<D, R>& T, const R in[D], R out[D])
+{
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        R s = R(0);
+#pragma unroll
+        for (int b = 0; b < D; b++) s += T.t[a][b] * in[b];
+        out[a] = s;
+    }
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void rot_apply_t(const Rot<D, R>& T, const R in[D], R out[D])
+{
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        R s = R(0);
+#pragma unroll
+        for (int b = 0; b < D; b++) s += T.t[b][a] * in[b];
+        out[a] = s;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Scaled eigenvector frame at an interface (Section 3.4), in factored form
+// R = Rtilde * S with Rtilde the unscaled right eigenvectors of the rotated
+// averaged state and S the symmetric scaling (diagonal, plus the 2x2 species
+// block D^Y for N = 2).  Only the entries that are not structurally zero or
+// one are kept, so W = R^T (T V) and R z cost ~4 nc multiply-adds.
+// --------------------------------------------------------------------------
+template <int N, int D, typename R>
+struct Frame {
+    R vh[D];     // rotated averaged velocity
+    R c;         // averaged sound speed
+    R H;         // averaged total enthalpy
+    R K;         // |v|^2 / 2
+    R Y[2];      // N = 2: averaged mass fractions
+    R e2[2];     // N = 2: K - d_l / (Gamma - 1)
+    R sa, se, st; // N = 1: scalings of acoustic, entropy, tangential columns
+    R s2a, sq;   // N = 2: sqrt(rho/(Gamma R))/sqrt(2) and sqrt(rho/(Gamma R))
+    R d11, d12, d21, d22;  // N = 2: D^Y scaled by sqrt(rho/(Gamma R))
+};
+
+// W = R^T y  (y = T V, nc components)
+template <int N, int D, typename R>
+__device__ __forceinline__ void frame_project(const Frame<N, D, R>& F, const R* y, R* W)
+{
+    constexpr int NC = N + D + 1;
+    const R yE = y[NC - 1];
+    R vdot = R(0);
+#pragma unroll
+    for (int j = 0; j < D; j++) vdot += F.vh[j] * y[N + j];
+    if constexpr (N == 1) {
+        const R base = y[0] + vdot;
+        const R gm = base - F.c * y[1] + (F.H - F.c * F.vh[0]) * yE;
+        const R gp = base + F.c * y[1] + (F.H + F.c * F.vh[0]) * yE;
+        const R ge = base + F.K * yE;
+        W[0] = F.sa * gm;
+        W[1] = F.se * ge;
+#pragma unroll
+        for (int t = 1; t < D; t++) W[1 + t] = F.st * (y[1 + t] + F.vh[t] * yE);
+        W[NC - 1] = F.sa * gp;
+    } else {
+        const R ys = F.Y[0] * y[0] + F.Y[1] * y[1] + vdot;
+        const R gm = ys - F.c * y[2] + (F.H - F.c * F.vh[0]) * yE;
+        const R gp = ys + F.c * y[2] + (F.H + F.c * F.vh[0]) * yE;
+        const R g1 = y[0] + vdot + F.e2[0] * yE;
+        const R g2 = y[1] + vdot + F.e2[1] * yE;
+        W[0] = F.s2a * gm;
+        W[1] = F.d11 * g1 + F.d21 * g2;
+        W[2] = F.d12 * g1 + F.d22 * g2;
+#pragma unroll
+        for (int t = 1; t < D; t++) W[2 + t] = F.sq * F.c * (y[2 + t] + F.vh[t] * yE);
+        W[NC - 1] = F.s2a * gp;
+    }
+}
+
+// out = R z
+template <int N, int D, typename R>
+__device__ __forceinline__ void frame_expand(const Frame<N, D, R>& F, const R* z, R* out)
+{
+    constexpr int NC = N + D + 1;
+    if constexpr (N == 1) {
+        const R zm = F.sa * z[0], ze = F.se * z[1], zp = F.sa * z[NC - 1];
+        const R sum = zm + ze + zp;
+        out[0] = sum;
+        out[1] = F.vh[0] * sum + F.c * (zp - zm);
+        R eng = (F.H - F.c * F.vh[0]) * zm + F.K * ze + (F.H + F.c * F.vh[0]) * zp;
+#pragma unroll
+        for (int t = 1; t < D; t++) {
+            const R zt = F.st * z[1 + t];
+            out[1 + t] = F.vh[t] * sum + zt;
+            eng += F.vh[t] * zt;
+        }
+        out[NC - 1] = eng;
+    } else {
+        const R zm = F.s2a * z[0], zp = F.s2a * z[NC - 1];
+        const R z1 = F.d11 * z[1] + F.d12 * z[2];
+        const R z2 = F.d21 * z[1] + F.d22 * z[2];
+        const R sum = zm + z1 + z2 + zp;
+        out[0] = F.Y[0] * (zm + zp) + z1;
+        out[1] = F.Y[1] * (zm + zp) + z2;
+        out[2] = F.vh[0] * sum + F.c * (zp - zm);
+        R eng = (F.H - F.c * F.vh[0]) * zm + F.e2[0] * z1 + F.e2[1] * z2
+              + (F.H + F.c * F.vh[0]) * zp;
+#pragma unroll
+        for (int t = 1; t < D; t++) {
+            const R zt = F.sq * z[2 + t];
+            out[2 + t] = F.vh[t] * sum + F.c * zt;
+            eng += F.c * F.vh[t] * zt;
+        }
+        out[NC - 1] = eng;
+    }
+}
+
+// --------------------------------------------------------------------------
+// device scalar reductions (wavefront of 64 lanes, then LDS across waves)
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+enum RedOp { RED_MAX = 0, RED_MIN = 1, RED_SUM = 2 };
+
+template <int OP>
+__device__ __forceinline__ double red_combine(double a, double b)
+{
+    if constexpr (OP == RED_MAX) return fmax(a, b);
+    else if constexpr (OP == RED_MIN) return fmin(a, b);
+    else return a + b;
+}
+
+// block of 256 threads; returns the block result in thread 0
+template <int OP>
+__device__ __forceinline__ double block_reduce(double v)
+{
+    __shared__ double part[4];
+    double w;
+    if constexpr (OP == RED_MAX) w = wave_max(v);
+    else if constexpr (OP == RED_MIN) w = wave_min(v);
+    else w = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) part[wid] = w;
+    __syncthreads();
+    double r = part[0];
+    if (threadIdx.x == 0) {
+        r = red_combine<OP>(red_combine<OP>(part[0], part[1]), red_combine<OP>(part[2], part[3]));
+    }
+    __syncthreads();
+    return r;
+}
+
+}  // namespace es

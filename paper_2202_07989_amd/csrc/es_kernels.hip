@@ -1,0 +1,723 @@
+// es_kernels.hip -- the HBM-bound steps of the path on gfx950: periodic
+// ghost layers, GCL metrics (Section 3.2), the CFL wave speed (Section 5),
+// mesh redistribution (Section 4) and the FP64 entropy sums.
+#include "es_kernels.hpp"
+
+namespace es {
+
+// ---------------------------------------------------------------------------
+// periodic ghost layers: one pass per direction k over the two ghost slabs of
+// k; pass k covers the full padded range of the directions already done
+// (so edges and corners come out right) and the interior of the others.
+// ---------------------------------------------------------------------------
+__global__ void k_fill_dir(Geo g, double* __restrict__ a, int ncomp, int K, int is_x)
+{
+    const int A = (K == 0) ? 1 : 0;
+    const int B = (K == 2) ? 1 : 2;
+    // range along A and B
+    const bool fullA = A < K, fullB = B < K;
+    const int loA = fullA ? 0 : (A < g.dim ? g.ng : 0);
+    const int nA = fullA ? g.np[A] : (A < g.dim ? g.n[A] : 1);
+    const int loB = fullB ? 0 : (B < g.dim ? g.ng : 0);
+    const int nB = fullB ? g.np[B] : (B < g.dim ? g.n[B] : 1);
+    const int ng = g.ng, nK = g.n[K];
+    const long total = (long)2 * ng * nA * nB;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total;
+         t += (long)gridDim.x * blockDim.x) {
+        const int gs = (int)(t % (2 * ng));
+        const long r = t / (2 * ng);
+        const int ia = loA + (int)(r % nA);
+        const int ib = loB + (int)(r / nA);
+        const int ik = gs < ng ? gs : nK + gs;
+        const int src = gs < ng ? ik + nK : ik - nK;
+        const double shift = gs < ng ? -1.0 : 1.0;
+        int d[3], s[3];
+        d[K] = ik; s[K] = src;
+        d[A] = ia; s[A] = ia;
+        d[B] = ib; s[B] = ib;
+        const long di = node_index(g, d[0], d[1], d[2]);
+        const long si = node_index(g, s[0], s[1], s[2]);
+        for (int c = 0; c < ncomp; c++) {
+            double v = a[c * g.P + si];
+            if (is_x && c == K) v += shift * g.len[K];
+            a[c * g.P + di] = v;
+        }
+    }
+}
+
+hipError_t fill_ghosts(const Geo& g, double* a, int ncomp, int is_x, hipStream_t s)
+{
+    for (int K = 0; K < g.dim; K++) {
+        const int A = (K == 0) ? 1 : 0, B = (K == 2) ? 1 : 2;
+        const long nA = A < K ? g.np[A] : (A < g.dim ? g.n[A] : 1);
+        const long nB = B < K ? g.np[B] : (B < g.dim ? g.n[B] : 1);
+        const long total = 2L * g.ng * nA * nB;
+        const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+        hipLaunchKernelGGL(k_fill_dir, dim3(blocks), dim3(256), 0, s, g, a, ncomp, K, is_x);
+    }
+    return hipGetLastError();
+}
+
+// interior node q (0 .. nint-1) -> padded index
+__device__ __forceinline__ long interior_node(const Geo& g, long q, int& i0, int& i1, int& i2)
+{
+    i0 = (int)(q % g.n[0]) + g.ng;
+    const long r = q / g.n[0];
+    i1 = (int)(r % g.n[1]) + g.ng;
+    i2 = (int)(r / g.n[1]) + (g.dim == 3 ? g.ng : 0);
+    return node_index(g, i0, i1, i2);
+}
+
+__device__ __forceinline__ long n_interior(const Geo& g)
+{
+    return (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1);
+}
+
+__global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, long n)
+{
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+        dst[t] = src[t];
+}
+
+__global__ void k_fill_value(double* __restrict__ dst, long n, double v)
+{
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+        dst[t] = v;
+}
+
+// a += b over n values
+__global__ void k_axpy1(double* __restrict__ a, const double* __restrict__ b, long n)
+{
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+        a[t] += b[t];
+}
+
+__global__ void k_set_scalar(double* dst, double v) { if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v; }
+
+static int grid_for(long n) { return (int)std::max<long>(1, std::min<long>((n + 255) / 256, 16384)); }
+
+hipError_t copy(const double* src, double* dst, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+hipError_t fill_value(double* dst, long n, double v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_value, dim3(grid_for(n)), dim3(256), 0, s, dst, n, v);
+    return hipGetLastError();
+}
+hipError_t add_inplace(double* a, const double* b, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpy1, dim3(grid_for(n)), dim3(256), 0, s, a, b, n);
+    return hipGetLastError();
+}
+hipError_t set_scalar(double* dst, double v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, s, dst, v);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// GCL metrics (eq SCLCoeff, eq VCLCoeff).  Stage mesh xs = x_n + c_s disp.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double xs_at(const double* xn, const double* disp, double cs, long P, int p,
+                                        long i)
+{
+    double v = xn[p * P + i];
+    if (disp) v += cs * disp[p * P + i];
+    return v;
+}
+
+// 3D pass 1: G[a][p] = delta_a[xs_p] at nodes interior along a
+__global__ void k_metric_grad3(Geo g, Phys ph, const double* __restrict__ xn,
+                               const double* __restrict__ disp, double cs, double* __restrict__ G)
+{
+    const long P = g.P;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < P; t += (long)gridDim.x * blockDim.x) {
+        const int i0 = (int)(t % g.np[0]);
+        const long r = t / g.np[0];
+        const int i1 = (int)(r % g.np[1]);
+        const int i2 = (int)(r / g.np[1]);
+        const int idx[3] = {i0, i1, i2};
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            if (idx[a] < g.ng || idx[a] >= g.ng + g.n[a]) continue;
+            const long st = dir_stride(g, a);
+#pragma unroll
+            for (int p = 0; p < 3; p++) {
+                double s = 0.0;
+                for (int m = 1; m <= ph.w; m++)
+                    s += ph.alpha[m - 1] * (xs_at(xn, disp, cs, P, p, t + m * st) -
+                                            xs_at(xn, disp, cs, P, p, t - m * st));
+                G[(a * 3 + p) * P + t] = 0.5 * s;
+            }
+        }
+    }
+}
+
+// 3D pass 2: J dxi_k/dx_j = (delta_b[G_ap x_q] - delta_a[G_bp x_q]) / (dxi_a dxi_b)
+__global__ void k_metric3(Geo g, Phys ph, const double* __restrict__ xn,
+                          const double* __restrict__ disp, double cs, const double* __restrict__ G,
+                          const double* __restrict__ dt_dev, double* __restrict__ jxx,
+                          double* __restrict__ jxt)
+{
+    const long P = g.P;
+    const long nint = n_interior(g);
+    const double dt = dt_dev ? *dt_dev : 0.0;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+        double M[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const int a = (k + 1) % 3, b = (k + 2) % 3;
+            const long sa = dir_stride(g, a), sb = dir_stride(g, b);
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                const int p = (j + 1) % 3, qq = (j + 2) % 3;
+                double t1 = 0.0, t2 = 0.0;
+                for (int m = 1; m <= ph.w; m++) {
+                    const long bp = i + m * sb, bm = i - m * sb;
+                    const long ap = i + m * sa, am = i - m * sa;
+                    t1 += ph.alpha[m - 1] * (G[(a * 3 + p) * P + bp] * xs_at(xn, disp, cs, P, qq, bp) -
+                                             G[(a * 3 + p) * P + bm] * xs_at(xn, disp, cs, P, qq, bm));
+                    t2 += ph.alpha[m - 1] * (G[(b * 3 + p) * P + ap] * xs_at(xn, disp, cs, P, qq, ap) -
+                                             G[(b * 3 + p) * P + am] * xs_at(xn, disp, cs, P, qq, am));
+                }
+                M[k][j] = (0.5 * t1 - 0.5 * t2) * (g.idxi[a] * g.idxi[b]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) jxx[(k * 3 + j) * P + i] = M[k][j];
+        if (jxt) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                double nt = 0.0;
+                if (disp && dt > 0.0)
+#pragma unroll
+                    for (int j = 0; j < 3; j++) nt -= (disp[j * P + i] / dt) * M[k][j];
+                jxt[k * P + i] = nt;
+            }
+        }
+    }
+}
+
+// 2D: J dxi_1/dx = (delta_2 x_2, -delta_2 x_1)/dxi_2, J dxi_2/dx = (-delta_1 x_2, delta_1 x_1)/dxi_1
+__global__ void k_metric2(Geo g, Phys ph, const double* __restrict__ xn,
+                          const double* __restrict__ disp, double cs, const double* __restrict__ dt_dev,
+                          double* __restrict__ jxx, double* __restrict__ jxt)
+{
+    const long P = g.P;
+    const long nint = n_interior(g);
+    const double dt = dt_dev ? *dt_dev : 0.0;
+    const long s0 = 1, s1 = g.np[0];
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+        double d[2][2];   // d[a][p] = delta_a[x_p]
+#pragma unroll
+        for (int a = 0; a < 2; a++) {
+            const long st = a == 0 ? s0 : s1;
+#pragma unroll
+            for (int p = 0; p < 2; p++) {
+                double s = 0.0;
+                for (int m = 1; m <= ph.w; m++)
+                    s += ph.alpha[m - 1] * (xs_at(xn, disp, cs, P, p, i + m * st) -
+                                            xs_at(xn, disp, cs, P, p, i - m * st));
+                d[a][p] = 0.5 * s;
+            }
+        }
+        double M[2][2];
+        M[0][0] = d[1][1] / g.dxi[1];
+        M[0][1] = -d[1][0] / g.dxi[1];
+        M[1][0] = -d[0][1] / g.dxi[0];
+        M[1][1] = d[0][0] / g.dxi[0];
+#pragma unroll
+        for (int k = 0; k < 2; k++)
+#pragma unroll
+            for (int j = 0; j < 2; j++) jxx[(k * 2 + j) * P + i] = M[k][j];
+        if (jxt) {
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                double nt = 0.0;
+                if (disp && dt > 0.0)
+#pragma unroll
+                    for (int j = 0; j < 2; j++) nt -= (disp[j * P + i] / dt) * M[k][j];
+                jxt[k * P + i] = nt;
+            }
+        }
+    }
+}
+
+// jxi_t only, from an existing jxi_x
+__global__ void k_vcl(Geo g, const double* __restrict__ disp, const double* __restrict__ dt_dev,
+                      const double* __restrict__ jxx, double* __restrict__ jxt)
+{
+    const long P = g.P;
+    const int D = g.dim;
+    const long nint = n_interior(g);
+    const double dt = dt_dev ? *dt_dev : 0.0;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+        for (int k = 0; k < D; k++) {
+            double nt = 0.0;
+            if (disp && dt > 0.0)
+                for (int j = 0; j < D; j++) nt -= (disp[j * P + i] / dt) * jxx[(k * D + j) * P + i];
+            jxt[k * P + i] = nt;
+        }
+    }
+}
+
+hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double* disp, double cs,
+                   const double* dt_dev, double* jxx, double* jxt, int vcl_only, double* G,
+                   hipStream_t s)
+{
+    const long nint = (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1);
+    if (vcl_only) {
+        if (!jxt) return hipSuccess;
+        hipLaunchKernelGGL(k_vcl, dim3(grid_for(nint)), dim3(256), 0, s, g, disp, dt_dev, jxx, jxt);
+    } else if (g.dim == 2) {
+        hipLaunchKernelGGL(k_metric2, dim3(grid_for(nint)), dim3(256), 0, s, g, ph, xn, disp, cs, dt_dev,
+                           jxx, jxt);
+    } else {
+        hipLaunchKernelGGL(k_metric_grad3, dim3(grid_for(g.P)), dim3(256), 0, s, g, ph, xn, disp, cs, G);
+        hipLaunchKernelGGL(k_metric3, dim3(grid_for(nint)), dim3(256), 0, s, g, ph, xn, disp, cs, G, dt_dev,
+                           jxx, jxt);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (!vcl_only) {
+        e = fill_ghosts(g, jxx, g.dim * g.dim, 0, s);
+        if (e != hipSuccess) return e;
+    }
+    if (jxt) e = fill_ghosts(g, jxt, g.dim, 0, s);
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// reductions: per-block partials in a fixed grid, then one block folds the
+// partials in a fixed order (deterministic sums)
+// ---------------------------------------------------------------------------
+static constexpr int RED_BLOCKS = 2048;
+
+template <int OP>
+__global__ void k_finish(const double* __restrict__ part, int nparts, double* __restrict__ out,
+                         int mode, double a, unsigned* status)
+{
+    double v = (OP == RED_MAX) ? -INFINITY : (OP == RED_MIN ? INFINITY : 0.0);
+    for (int t = threadIdx.x; t < nparts; t += blockDim.x) v = red_combine<OP>(v, part[t]);
+    v = block_reduce<OP>(v);
+    if (threadIdx.x == 0) {
+        if (mode == 0) {
+            out[0] = v;
+        } else if (mode == 1) {           // CFL: out[0] = lambda, out[1] = cfl / lambda
+            out[0] = v;
+            out[1] = a / v;
+        } else if (mode == 2) {           // limiter: Delta_tau = min(1, v)
+            const double d = fmin(1.0, v);
+            out[0] = d;
+            if (!(d > 0.0)) atomicOr(status, 2u);
+        } else {                          // scaled sum
+            out[0] = v * a;
+        }
+    }
+}
+
+// thermo of one node from JU/J
+template <int N, int D>
+struct NodeState {
+    double U[N + D + 1];
+    double rho, v[D], T, p, beta;
+    bool ok;
+};
+
+template <int N, int D>
+__device__ __forceinline__ void load_state(const Phys& ph, const double* JU, const double* Jv, long P,
+                                           long i, NodeState<N, D>& s)
+{
+    constexpr int NC = N + D + 1;
+    const double Jq = Jv[i];
+#pragma unroll
+    for (int c = 0; c < NC; c++) s.U[c] = JU[c * P + i] / Jq;
+    double rt = 0.0, cvr = 0.0, rR = 0.0;
+    bool ok = Jq > 0.0;
+#pragma unroll
+    for (int l = 0; l < N; l++) {
+        rt += s.U[l];
+        cvr += ph.cv[l] * s.U[l];
+        rR += ph.Rg[l] * s.U[l];
+        ok = ok && (s.U[l] > 0.0);
+    }
+    double kin = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        s.v[j] = s.U[N + j] / rt;
+        kin += 0.5 * s.U[N + j] * s.v[j];
+    }
+    s.rho = rt;
+    s.T = (s.U[NC - 1] - kin - ph.pinf_tot) / cvr;
+    s.beta = 1.0 / s.T;
+    s.p = rR * s.T - ph.pinf_tot;
+    s.ok = ok && (s.T > 0.0) && isfinite(s.T) && isfinite(kin);
+}
+
+template <int N, int D>
+__global__ void k_wavespeed(Phys ph, Geo g, const double* __restrict__ JU, const double* __restrict__ Jv,
+                            const double* __restrict__ jxx, double* __restrict__ part,
+                            unsigned* __restrict__ status)
+{
+    const long P = g.P;
+    const long nint = n_interior(g);
+    double lam = 0.0;
+    unsigned bad = 0;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+        NodeState<N, D> s;
+        load_state<N, D>(ph, JU, Jv, P, i, s);
+        if (!s.ok) bad |= 1u;
+        double cvr = 0.0, cg = 0.0, rR = 0.0;
+#pragma unroll
+        for (int l = 0; l < N; l++) {
+            cvr += ph.cv[l] * s.U[l];
+            cg += ph.cvgam[l] * s.U[l];
+            rR += ph.Rg[l] * s.U[l];
+        }
+        const double c = sqrt((rR / s.rho) * (cg / cvr) * s.T);
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            double vn = 0.0, nn = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; j++) {
+                const double n = jxx[(k * D + j) * P + i];
+                vn += s.v[j] * n;
+                nn += n * n;
+            }
+            sum += (fabs(vn) + c * sqrt(nn)) / Jv[i] / g.dxi[k];
+        }
+        lam = fmax(lam, sum);
+    }
+    if (bad) atomicOr(status, bad);
+    lam = block_reduce<RED_MAX>(lam);
+    if (threadIdx.x == 0) part[blockIdx.x] = lam;
+}
+
+template <int N, int D>
+__global__ void k_entropy(Phys ph, Geo g, const double* __restrict__ JU, const double* __restrict__ Jv,
+                          const double* __restrict__ dJU, const double* __restrict__ dJ,
+                          double* __restrict__ part)
+{
+    constexpr int NC = N + D + 1;
+    const long P = g.P;
+    const long nint = n_interior(g);
+    double acc = 0.0;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+        NodeState<N, D> s;
+        load_state<N, D>(ph, JU, Jv, P, i, s);
+        const double lT = log(s.T);
+        if (!dJU) {   // J eta, eta = -sum rho_l (c_vl ln T - R_l ln rho_l)
+            double eta = 0.0;
+#pragma unroll
+            for (int l = 0; l < N; l++) eta -= s.U[l] * (ph.cv[l] * lT - ph.Rg[l] * log(s.U[l]));
+            acc += Jv[i] * eta;
+        } else {      // V . dJU - phi dJ
+            double v2 = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; j++) v2 += s.v[j] * s.v[j];
+            double t = 0.0, phi = 0.0;
+#pragma unroll
+            for (int l = 0; l < N; l++) {
+                const double Vl = -(ph.cv[l] * lT - ph.Rg[l] * log(s.U[l])) - v2 / (2.0 * s.T) + ph.cvgam[l];
+                t += Vl * dJU[l * P + i];
+                phi += ph.Rg[l] * s.U[l] - ph.pinf[l] / s.T;
+            }
+#pragma unroll
+            for (int j = 0; j < D; j++) t += (s.v[j] / s.T) * dJU[(N + j) * P + i];
+            t += (-1.0 / s.T) * dJU[(NC - 1) * P + i];
+            acc += t - phi * dJ[i];
+        }
+    }
+    acc = block_reduce<RED_SUM>(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+static int red_grid(long nint) { return (int)std::max<long>(1, std::min<long>((nint + 255) / 256, RED_BLOCKS)); }
+
+#define ES_DISPATCH_ND(ph, g, FN, ...)                                   \
+    do {                                                                 \
+        if (ph.nspec == 1 && g.dim == 2) FN<1, 2>(__VA_ARGS__);          \
+        else if (ph.nspec == 2 && g.dim == 2) FN<2, 2>(__VA_ARGS__);     \
+        else if (ph.nspec == 1 && g.dim == 3) FN<1, 3>(__VA_ARGS__);     \
+        else FN<2, 3>(__VA_ARGS__);                                      \
+    } while (0)
+
+template <int N, int D>
+static void launch_wavespeed(const Phys& ph, const Geo& g, const double* JU, const double* J,
+                             const double* jxx, double* part, unsigned* status, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_wavespeed<N, D>), dim3(nb), dim3(256), 0, s, ph, g, JU, J, jxx, part, status);
+}
+
+hipError_t wavespeed(const Phys& ph, const Geo& g, const double* JU, const double* J, const double* jxx,
+                     double cfl, double* part, double* out2, unsigned* status, hipStream_t s)
+{
+    const long nint = (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1);
+    const int nb = red_grid(nint);
+    ES_DISPATCH_ND(ph, g, launch_wavespeed, ph, g, JU, J, jxx, part, status, nb, s);
+    hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, part, nb, out2, 1, cfl, status);
+    return hipGetLastError();
+}
+
+template <int N, int D>
+static void launch_entropy(const Phys& ph, const Geo& g, const double* JU, const double* J,
+                           const double* dJU, const double* dJ, double* part, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_entropy<N, D>), dim3(nb), dim3(256), 0, s, ph, g, JU, J, dJU, dJ, part);
+}
+
+hipError_t entropy_sum(const Phys& ph, const Geo& g, const double* JU, const double* J, const double* dJU,
+                       const double* dJ, double* part, double* out, hipStream_t s)
+{
+    const long nint = (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1);
+    const int nb = red_grid(nint);
+    double dv = 1.0;
+    for (int k = 0; k < g.dim; k++) dv *= g.dxi[k];
+    ES_DISPATCH_ND(ph, g, launch_entropy, ph, g, JU, J, dJU, dJ, part, nb, s);
+    hipLaunchKernelGGL(k_finish<RED_SUM>, dim3(1), dim3(256), 0, s, part, nb, out, 3, dv, nullptr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// mesh redistribution (Section 4)
+// ---------------------------------------------------------------------------
+// |grad_xi sigma| by second-order central differences, for each monitor
+// variable; per-block maxima into part[s * RED_BLOCKS + block]
+template <int N, int D>
+__device__ __forceinline__ double sigma_of(const Phys& ph, const double* JU, const double* Jv, long P,
+                                           long i, int sig)
+{
+    const double Jq = Jv[i];
+    if (sig == 0) {
+        double r = 0.0;
+#pragma unroll
+        for (int l = 0; l < N; l++) r += JU[l * P + i] / Jq;
+        return r;
+    }
+    if (sig == 1) return JU[i] / Jq;
+    if (sig == 2) return JU[(N > 1 ? 1 : 0) * P + i] / Jq;
+    NodeState<N, D> s;
+    load_state<N, D>(ph, JU, Jv, P, i, s);
+    return s.p;
+}
+
+template <int N, int D>
+__global__ void k_monitor_grad(Phys ph, Geo g, MonitorP mo, const double* __restrict__ JU,
+                               const double* __restrict__ Jv, double* __restrict__ grad,
+                               double* __restrict__ part)
+{
+    const long P = g.P;
+    const long nint = n_interior(g);
+    double gm[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+        for (int s = 0; s < mo.nsig; s++) {
+            double g2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+                const long st = dir_stride(g, k);
+                const double dk = (sigma_of<N, D>(ph, JU, Jv, P, i + st, mo.sigma[s]) -
+                                   sigma_of<N, D>(ph, JU, Jv, P, i - st, mo.sigma[s])) / (2.0 * g.dxi[k]);
+                g2 += dk * dk;
+            }
+            const double gv = sqrt(g2);
+            grad[s * P + i] = gv;
+            gm[s] = fmax(gm[s], gv);
+        }
+    }
+    for (int s = 0; s < 4; s++) {
+        const double r = block_reduce<RED_MAX>(gm[s]);
+        if (threadIdx.x == 0 && s < mo.nsig) part[s * RED_BLOCKS + blockIdx.x] = r;
+    }
+}
+
+__global__ void k_theta(Geo g, MonitorP mo, const double* __restrict__ grad, const double* __restrict__ gmax,
+                        double* __restrict__ theta)
+{
+    const long P = g.P;
+    const long nint = n_interior(g);
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+        double th = 1.0;
+        for (int s = 0; s < mo.nsig; s++) {
+            const double G = gmax[s];
+            if (G > 0.0) {
+                const double r = grad[s * P + i] / G;
+                th += mo.alpha[s] * r * r;
+            }
+        }
+        theta[i] = sqrt(th);
+    }
+}
+
+// low-pass filter: sum over j in {0,+-1}^d of (1/2)^(|j|_1 + d) Theta_{i+j}
+__global__ void k_filter(Geo g, const double* __restrict__ in, double* __restrict__ out)
+{
+    const long nint = n_interior(g);
+    const long s0 = 1, s1 = g.np[0], s2 = (long)g.np[0] * g.np[1];
+    const int r2 = g.dim == 3 ? 1 : 0;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+        double s = 0.0;
+        for (int j2 = -r2; j2 <= r2; j2++)
+            for (int j1 = -1; j1 <= 1; j1++)
+                for (int j0 = -1; j0 <= 1; j0++) {
+                    const int e = abs(j0) + abs(j1) + abs(j2) + g.dim;
+                    s += ldexp(1.0, -e) * in[i + j0 * s0 + j1 * s1 + j2 * s2];
+                }
+        out[i] = s;
+    }
+}
+
+// one Jacobi sweep of the mesh equations; per-block max |x_new - x_old|
+template <int D>
+__global__ void k_jacobi(Geo g, const double* __restrict__ th, const double* __restrict__ xa,
+                         double* __restrict__ xb, double* __restrict__ part)
+{
+    const long P = g.P;
+    const long nint = n_interior(g);
+    double r = 0.0;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+        double tp[D], tm[D], ih2[D];
+        double den = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            const long st = dir_stride(g, k);
+            tp[k] = 0.5 * (th[i] + th[i + st]);
+            tm[k] = 0.5 * (th[i] + th[i - st]);
+            ih2[k] = g.dxi[k] * g.dxi[k];
+        }
+#pragma unroll
+        for (int c = 0; c < D; c++) {
+            double num = 0.0;
+            den = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+                const long st = dir_stride(g, k);
+                num += (tp[k] * xa[c * P + i + st] + tm[k] * xa[c * P + i - st]) / ih2[k];
+                den += (tp[k] + tm[k]) / ih2[k];
+            }
+            const double xn = num / den;
+            xb[c * P + i] = xn;
+            r = fmax(r, fabs(xn - xa[c * P + i]));
+        }
+    }
+    r = block_reduce<RED_MAX>(r);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+// movement limiter: per-block min of the bounds (1 if none)
+template <int D>
+__global__ void k_limiter(Geo g, const double* __restrict__ xmu, const double* __restrict__ xn,
+                          double* __restrict__ part)
+{
+    const long P = g.P;
+    const long nint = n_interior(g);
+    double b = 1.0;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            const long st = dir_stride(g, k);
+            const double dx = xmu[k * P + i] - xn[k * P + i];
+            if (dx < 0.0) b = fmin(b, -(xn[k * P + i] - xn[k * P + i - st]) / (2.0 * dx));
+            else if (dx > 0.0) b = fmin(b, (xn[k * P + i + st] - xn[k * P + i]) / (2.0 * dx));
+        }
+    }
+    b = block_reduce<RED_MIN>(b);
+    if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+__global__ void k_disp(Geo g, const double* __restrict__ xmu, const double* __restrict__ xn,
+                       const double* __restrict__ dtau, double* __restrict__ disp)
+{
+    const long P = g.P;
+    const long nint = n_interior(g);
+    const double d = *dtau;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+        for (int c = 0; c < g.dim; c++) disp[c * P + i] = d * (xmu[c * P + i] - xn[c * P + i]);
+    }
+}
+
+template <int N, int D>
+static void launch_monitor(const Phys& ph, const Geo& g, const MonitorP& mo, const double* JU,
+                           const double* J, double* grad, double* part, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_monitor_grad<N, D>), dim3(nb), dim3(256), 0, s, ph, g, mo, JU, J, grad, part);
+}
+
+hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, const double* JU,
+                             const double* J, const double* xn, double* disp, MeshWork& w,
+                             double* dtau_out, double* resid_out, unsigned* status, hipStream_t s)
+{
+    const long P = g.P;
+    const long nint = (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1);
+    const int nb = red_grid(nint);
+    const int gi = grid_for(nint);
+    // monitor and its global maxima
+    ES_DISPATCH_ND(ph, g, launch_monitor, ph, g, mo, JU, J, w.grad, w.part, nb, s);
+    for (int q = 0; q < mo.nsig; q++)
+        hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part + q * RED_BLOCKS, nb,
+                           w.scal + q, 0, 0.0, status);
+    hipLaunchKernelGGL(k_theta, dim3(gi), dim3(256), 0, s, g, mo, w.grad, w.scal, w.th0);
+    hipError_t e = fill_ghosts(g, w.th0, 1, 0, s);
+    if (e != hipSuccess) return e;
+    double* th = w.th0;
+    double* th2 = w.th1;
+    for (int q = 0; q < mo.n_smooth; q++) {
+        hipLaunchKernelGGL(k_filter, dim3(gi), dim3(256), 0, s, g, th, th2);
+        if ((e = fill_ghosts(g, th2, 1, 0, s)) != hipSuccess) return e;
+        std::swap(th, th2);
+    }
+    // Jacobi sweeps
+    if ((e = copy(xn, w.xa, g.dim * P, s)) != hipSuccess) return e;
+    double* xa = w.xa;
+    double* xb = w.xb;
+    for (int nu = 0; nu < mo.n_sweeps; nu++) {
+        if (g.dim == 2)
+            hipLaunchKernelGGL(k_jacobi<2>, dim3(nb), dim3(256), 0, s, g, th, xa, xb, w.part);
+        else
+            hipLaunchKernelGGL(k_jacobi<3>, dim3(nb), dim3(256), 0, s, g, th, xa, xb, w.part);
+        if ((e = fill_ghosts(g, xb, g.dim, 1, s)) != hipSuccess) return e;
+        if (resid_out)
+            hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part, nb, resid_out + nu, 0,
+                               0.0, status);
+        std::swap(xa, xb);
+    }
+    // limiter and displacement
+    if (g.dim == 2)
+        hipLaunchKernelGGL(k_limiter<2>, dim3(nb), dim3(256), 0, s, g, xa, xn, w.part);
+    else
+        hipLaunchKernelGGL(k_limiter<3>, dim3(nb), dim3(256), 0, s, g, xa, xn, w.part);
+    hipLaunchKernelGGL(k_finish<RED_MIN>, dim3(1), dim3(256), 0, s, w.part, nb, w.scal + 4, 2, 0.0, status);
+    if ((e = fill_value(disp, g.dim * P, 0.0, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_disp, dim3(gi), dim3(256), 0, s, g, xa, xn, w.scal + 4, disp);
+    if ((e = fill_ghosts(g, disp, g.dim, 0, s)) != hipSuccess) return e;
+    if (dtau_out && (e = copy(w.scal + 4, dtau_out, 1, s)) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+}  // namespace es

@@ -1,0 +1,58 @@
+// es_kernels.hpp -- launch interfaces shared by the translation units of libes.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <utility>
+
+#include "es_device.hpp"
+
+namespace es {
+
+struct MonitorP {
+    int nsig;
+    int sigma[4];
+    double alpha[4];
+    int n_smooth, n_sweeps;
+};
+
+struct MeshWork {
+    double* grad;   // nsig * P
+    double* th0;    // P
+    double* th1;    // P
+    double* xa;     // dim * P
+    double* xb;     // dim * P
+    double* part;   // 4 * 2048 partials
+    double* scal;   // 8 scalars: monitor maxima [0..3], Delta_tau [4]
+};
+
+struct RkArgs;
+
+hipError_t fill_ghosts(const Geo& g, double* a, int ncomp, int is_x, hipStream_t s);
+hipError_t copy(const double* src, double* dst, long n, hipStream_t s);
+hipError_t fill_value(double* dst, long n, double v, hipStream_t s);
+hipError_t add_inplace(double* a, const double* b, long n, hipStream_t s);
+hipError_t set_scalar(double* dst, double v, hipStream_t s);
+hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double* disp, double cs,
+                   const double* dt_dev, double* jxx, double* jxt, int vcl_only, double* G,
+                   hipStream_t s);
+hipError_t wavespeed(const Phys& ph, const Geo& g, const double* JU, const double* J, const double* jxx,
+                     double cfl, double* part, double* out2, unsigned* status, hipStream_t s);
+hipError_t entropy_sum(const Phys& ph, const Geo& g, const double* JU, const double* J, const double* dJU,
+                       const double* dJ, double* part, double* out, hipStream_t s);
+hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, const double* JU,
+                             const double* J, const double* xn, double* disp, MeshWork& w,
+                             double* dtau_out, double* resid_out, unsigned* status, hipStream_t s);
+
+struct RkArgs {
+    const double* JUn;
+    const double* Jn;
+    const double* dt;
+    double a, b;
+};
+
+hipError_t launch_rhs(const Phys& ph, const Geo& g, int mixed, const double* JU, const double* J,
+                      const double* jxx, const double* jxt, double* outU, double* outJ,
+                      const RkArgs* rk, unsigned* status, hipStream_t s);
+
+}  // namespace es

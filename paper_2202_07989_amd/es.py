@@ -1,0 +1,208 @@
+"""ctypes binding of libes.so (the HIP/gfx950 C-ABI declared in include/es.h).
+
+Argument marshalling only: every step of the scheme runs in the library's
+kernels.  PyTorch supplies device memory and the current stream.  Importing
+this module loads libes.so and raises if it is missing; creating a Context
+raises if no HIP device is present.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libes.so")
+
+ES_OK, ES_EINVAL, ES_EUNSUPPORTED, ES_EHIP, ES_ENONPHYS, ES_ETANGLE = 0, -1, -2, -3, -4, -5
+ES_ST_NONPHYS, ES_ST_TANGLE = 1, 2
+ES_FP64, ES_MIXED = 0, 1
+ES_METRICS_VCL_ONLY = 1
+
+
+class EsError(RuntimeError):
+    def __init__(self, name, code):
+        super().__init__(f"{name} failed with code {code}")
+        self.code = code
+
+
+class EsGrid(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("nspec", C.c_int), ("n", C.c_int * 3), ("ng", C.c_int),
+        ("dxi", C.c_double * 3), ("len", C.c_double * 3), ("w", C.c_int),
+        ("gamma", C.c_double * 2), ("cv", C.c_double * 2), ("pinf", C.c_double * 2),
+        ("chi", C.c_double * 3), ("weno_eps", C.c_double), ("dissipation", C.c_int),
+        ("precision", C.c_int),
+    ]
+
+
+class EsMonitor(C.Structure):
+    _fields_ = [
+        ("nsig", C.c_int), ("sigma", C.c_int * 4), ("alpha", C.c_double * 4),
+        ("n_smooth", C.c_int), ("n_sweeps", C.c_int),
+    ]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "es_create": [C.POINTER(EsGrid), C.POINTER(C.c_void_p)],
+    "es_destroy": [_P],
+    "es_fill_ghosts": [_P, _P, C.c_int, _P],
+    "es_fill_ghosts_x": [_P, _P, _P],
+    "es_metrics": [_P, _P, _P, C.c_double, _P, _P, _P, C.c_int, _P],
+    "es_rhs": [_P, _P, _P, _P, _P, _P, _P, _P],
+    "es_rk_stage": [_P, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+    "max_wavespeed": [_P, _P, _P, _P, C.c_double, _P, _P, _P],
+    "mesh_redistribute": [_P, C.POINTER(EsMonitor), _P, _P, _P, _P, _P, _P, _P],
+    "es_entropy": [_P, _P, _P, _P, _P],
+    "es_entropy_rate": [_P, _P, _P, _P, _P, _P, _P],
+    "es_step": [_P, C.POINTER(EsMonitor), C.c_double, C.c_double, C.c_int, _P, _P, _P, _P, _P, _P],
+    "es_status": [_P, _P, C.POINTER(C.c_uint), C.c_int],
+    "es_npoints": [_P],
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2202_07989_amd/build.py "
+                          "(there is no CPU fallback)")
+    lib = C.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_long if name == "es_npoints" else C.c_int
+    return lib
+
+
+lib = _load()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("libes takes contiguous float64 device tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check(name, rc):
+    if rc != ES_OK:
+        raise EsError(name, rc)
+
+
+def make_grid(spec, precision=ES_FP64) -> EsGrid:
+    g = EsGrid()
+    g.dim, g.nspec = spec["dim"], spec["nspec"]
+    n = list(spec["n"]) + [1] * (3 - len(spec["n"]))
+    for k in range(3):
+        g.n[k] = n[k]
+        g.dxi[k] = spec["dxi"][k] if k < len(spec["dxi"]) else 1.0
+        g.len[k] = spec["len"][k] if k < len(spec["len"]) else 1.0
+    g.ng, g.w = spec.get("ng", 3), spec.get("w", 3)
+    for l in range(2):
+        g.gamma[l] = spec["gamma"][l] if l < len(spec["gamma"]) else 1.4
+        g.cv[l] = spec["cv"][l] if l < len(spec["cv"]) else 1.0
+        g.pinf[l] = spec["pinf"][l] if l < len(spec["pinf"]) else 0.0
+    for m in range(3):
+        g.chi[m] = spec["chi"][m]
+    g.weno_eps = spec.get("weno_eps", 1e-10)
+    g.dissipation = spec.get("dissipation", 1)
+    g.precision = precision
+    return g
+
+
+def make_monitor(mon) -> EsMonitor:
+    m = EsMonitor()
+    sig, al = mon.get("sigma", [0]), mon.get("alpha", [1200.0])
+    m.nsig = len(sig)
+    for t in range(len(sig)):
+        m.sigma[t], m.alpha[t] = sig[t], al[t]
+    m.n_smooth, m.n_sweeps = mon.get("n_smooth", 3), mon.get("n_sweeps", 10)
+    return m
+
+
+class Context:
+    """One es_ctx: a grid on the current HIP device."""
+
+    def __init__(self, spec, precision=ES_FP64):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libes needs a HIP device; there is no CPU fallback")
+        self.spec = spec
+        self.grid = make_grid(spec, precision)
+        h = C.c_void_p()
+        _check("es_create", lib.es_create(C.byref(self.grid), C.byref(h)))
+        self.h = h
+        self.P = lib.es_npoints(self.h)
+        self.nc = spec["nspec"] + spec["dim"] + 1
+        self.dim = spec["dim"]
+
+    def close(self):
+        if self.h:
+            lib.es_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the C-ABI, one method per entry point --------------------------------
+    def es_fill_ghosts(self, a, ncomp, stream=None):
+        _check("es_fill_ghosts", lib.es_fill_ghosts(self.h, _ptr(a), ncomp, _stream(stream)))
+
+    def es_fill_ghosts_x(self, x, stream=None):
+        _check("es_fill_ghosts_x", lib.es_fill_ghosts_x(self.h, _ptr(x), _stream(stream)))
+
+    def es_metrics(self, x_n, disp, c_s, dt_dev, jxi_x, jxi_t, flags=0, stream=None):
+        _check("es_metrics", lib.es_metrics(self.h, _ptr(x_n), _ptr(disp), float(c_s), _ptr(dt_dev),
+                                            _ptr(jxi_x), _ptr(jxi_t), flags, _stream(stream)))
+
+    def es_rhs(self, JU, J, jxi_x, jxi_t, dJU, dJ, stream=None):
+        _check("es_rhs", lib.es_rhs(self.h, _ptr(JU), _ptr(J), _ptr(jxi_x), _ptr(jxi_t), _ptr(dJU),
+                                    _ptr(dJ), _stream(stream)))
+
+    def es_rk_stage(self, stage, dt_dev, JU_n, J_n, JU_s, J_s, jxi_x, jxi_t, JU_out, J_out,
+                    stream=None):
+        _check("es_rk_stage", lib.es_rk_stage(self.h, stage, _ptr(dt_dev), _ptr(JU_n), _ptr(J_n),
+                                              _ptr(JU_s), _ptr(J_s), _ptr(jxi_x), _ptr(jxi_t),
+                                              _ptr(JU_out), _ptr(J_out), _stream(stream)))
+
+    def max_wavespeed(self, JU, J, jxi_x, cfl, lambda_dev=None, dt_dev=None, stream=None):
+        _check("max_wavespeed", lib.max_wavespeed(self.h, _ptr(JU), _ptr(J), _ptr(jxi_x), float(cfl),
+                                                  _ptr(lambda_dev), _ptr(dt_dev), _stream(stream)))
+
+    def mesh_redistribute(self, mon, JU, J, x_n, disp, dtau_dev=None, resid_dev=None, stream=None):
+        m = make_monitor(mon)
+        _check("mesh_redistribute", lib.mesh_redistribute(self.h, C.byref(m), _ptr(JU), _ptr(J),
+                                                          _ptr(x_n), _ptr(disp), _ptr(dtau_dev),
+                                                          _ptr(resid_dev), _stream(stream)))
+
+    def es_entropy(self, JU, J, total_dev, stream=None):
+        _check("es_entropy", lib.es_entropy(self.h, _ptr(JU), _ptr(J), _ptr(total_dev), _stream(stream)))
+
+    def es_entropy_rate(self, JU, J, dJU, dJ, rate_dev, stream=None):
+        _check("es_entropy_rate", lib.es_entropy_rate(self.h, _ptr(JU), _ptr(J), _ptr(dJU), _ptr(dJ),
+                                                      _ptr(rate_dev), _stream(stream)))
+
+    def es_step(self, JU, J, x, mon=None, cfl=0.4, dt_fixed=0.0, move_mesh=False, dt_dev=None,
+                dtau_dev=None, stream=None):
+        m = make_monitor(mon) if mon is not None else None
+        _check("es_step", lib.es_step(self.h, C.byref(m) if m is not None else None, float(cfl),
+                                      float(dt_fixed), int(move_mesh), _ptr(JU), _ptr(J), _ptr(x),
+                                      _ptr(dt_dev), _ptr(dtau_dev), _stream(stream)))
+
+    def es_status(self, reset=False, stream=None):
+        flags = C.c_uint(0)
+        rc = lib.es_status(self.h, _stream(stream), C.byref(flags), int(reset))
+        if rc not in (ES_OK, ES_ENONPHYS, ES_ETANGLE):
+            raise EsError("es_status", rc)
+        return rc, flags.value

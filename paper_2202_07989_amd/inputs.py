@@ -192,7 +192,10 @@ def _bubble_radius_3d(n_hat, seed=2202079, modes=10, amp=0.02, r0=0.2):
 
 
 def init_shock_bubble(spec, mach=1.5, shock_x=0.2, trace=1e-3, p0=1.0e5,
-                      rho_water=1000.0, rho_air=1.0, seed=2202079):
+                      rho_water=1000.0, rho_air=1.0, seed=2202079, width=2.0):
+    """Water/air shock-bubble data.  width > 0 spreads the bubble interface
+    and the shock over a tanh profile of that many cells (a smoothed
+    initial condition; the scheme has no positivity limiter)."""
     d = spec["dim"]
     xi = xi_nodes(spec)
     x = [c.copy() for c in xi]                                   # initial mesh x = xi
@@ -207,12 +210,17 @@ def init_shock_bubble(spec, mach=1.5, shock_x=0.2, trace=1e-3, p0=1.0e5,
         rb = _bubble_radius_3d(n_hat, seed=seed)
     else:
         rb = 0.2
-    in_bubble = rad < rb
-    post = x[0] < shock_x
+    h = min(spec["dxi"][:d])
+    if width > 0:
+        fb = 0.5 * (1.0 - np.tanh((rad - rb) / (width * h)))           # 1 inside the bubble
+        fs = 0.5 * (1.0 - np.tanh((x[0] - shock_x) / (width * h)))     # 1 behind the shock
+    else:
+        fb = (rad < rb).astype(float)
+        fs = (x[0] < shock_x).astype(float)
     rho_s, p1, u1 = _post_shock(spec, water, p0, mach)
-    rho = [np.where(in_bubble, air[l], np.where(post, rho_s[l], water[l])) for l in range(2)]
-    p = np.where(in_bubble, p0, np.where(post, p1, p0))
-    v = [np.where(post & ~in_bubble, u1, 0.0)] + [np.zeros_like(p) for _ in range(d - 1)]
+    rho = [fb * air[l] + (1 - fb) * (fs * rho_s[l] + (1 - fs) * water[l]) for l in range(2)]
+    p = fb * p0 + (1 - fb) * (fs * p1 + (1 - fs) * p0)
+    v = [(1 - fb) * fs * u1] + [np.zeros_like(p) for _ in range(d - 1)]
     U = conserved(spec, rho, v, p)
     return assemble(spec, U, J, x)
 

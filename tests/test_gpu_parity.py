@@ -1,0 +1,246 @@
+"""GPU path (libes.so through its C-ABI) against the CPU FP64 oracle.
+
+Bar: per component, max |gpu - oracle| / S_c <= 1e-11 with S_c = max|JU_c| *
+lambda for right-hand sides (a CFL-1 increment, lambda the CFL wave speed),
+and S_c = max|Q_c| for states, metrics and meshes.  Ghost layers are compared
+bit for bit.  Sizes are ragged against the 16 x 16 tiles."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_07989_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_2202_07989_amd import es  # noqa: E402
+from gpu_util import TOL_FP64, dev, host, ghosts, parity, rhs_scale, state_scale, moving_metrics, say  # noqa: E402
+
+from cases import CASES, WATER, case_spec, prepared  # noqa: E402
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("dissipation", [1, 0])
+def test_rhs_parity(name, dissipation):
+    say(f"[rhs parity] {name} dissipation={dissipation}")
+    sp, o, JU, J, x, disp, jx, jt = prepared(name, dissipation)
+    rc, dU, dJ = o.rhs(JU, J, jx, jt)
+    assert rc == 0
+    _, lam, _ = o.max_wavespeed(JU, J, jx, 1.0)
+    ctx = es.Context(sp)
+    gU = torch.zeros_like(dev(JU))
+    gJ = torch.zeros_like(dev(J))
+    ctx.es_rhs(dev(JU), dev(J), dev(jx), dev(jt), gU, gJ)
+    hU, hJ = host(gU), host(gJ)
+    Iin = I.interior(sp)
+    sU, sJ = rhs_scale(JU, J, lam, Iin, sp)
+    worst = 0.0
+    for c in range(o.nc):
+        e = parity(hU[c][Iin[1:]], dU[c][Iin[1:]], sU[c])
+        worst = max(worst, e)
+        assert e <= TOL_FP64, (name, c, e)
+    e = parity(hJ[Iin], dJ[Iin], sJ)
+    assert e <= TOL_FP64, (name, "J", e)
+    assert ctx.es_status()[0] == es.ES_OK
+    say(f"    worst component parity {worst:.2e}")
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_metrics_parity(dim):
+    say(f"[metrics parity] dim={dim}")
+    name = "2d-n2-bubble" if dim == 2 else "3d-n2-bubble"
+    sp, o, JU, J, x, disp, jx, jt = prepared(name)
+    dt = 0.01
+    ctx = es.Context(sp)
+    gx, gjt = torch.zeros_like(dev(jx)), torch.zeros_like(dev(jt))
+    dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    ctx.es_metrics(dev(x), dev(disp), 0.5, dt_dev, gx, gjt)
+    hx, ht = host(gx), host(gjt)
+    mscale = np.abs(jx).max()                 # metric magnitude (off-diagonals are small)
+    for c in range(dim * dim):
+        assert parity(hx[c], jx[c], mscale) <= 1e-13, c
+    tscale = np.abs(jt).max()
+    for c in range(dim):
+        assert parity(ht[c], jt[c], tscale) <= 1e-13, c
+    # VCL-only refresh reproduces jxi_t
+    gjt2 = torch.zeros_like(gjt)
+    ctx.es_metrics(None, dev(disp), 0.5, dt_dev, gx, gjt2, flags=es.ES_METRICS_VCL_ONLY)
+    np.testing.assert_array_equal(host(gjt2), ht)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_ghost_fill_bitwise(dim):
+    say(f"[ghost fill] dim={dim}")
+    sp = I.make_spec(dim, 2, (13, 11, 9)[:dim], box=(1.0, 2.0, 3.0)[:dim], **WATER)
+    o = oracle.Oracle(sp)
+    rng = np.random.default_rng(3)
+    a = I.zeros(sp, 5)
+    a[I.interior(sp)] = rng.uniform(size=a[I.interior(sp)].shape)
+    x = I.zeros(sp, dim)
+    x[I.interior(sp)] = np.stack(I.random_mesh(sp, seed=4))
+    ctx = es.Context(sp)
+    ga, gx = dev(a), dev(x)
+    ctx.es_fill_ghosts(ga, 5)
+    ctx.es_fill_ghosts_x(gx)
+    o.fill_ghosts(a, 5)
+    o.fill_ghosts_x(x)
+    np.testing.assert_array_equal(host(ga), a)
+    np.testing.assert_array_equal(host(gx), x)
+
+
+@pytest.mark.parametrize("name", ["2d-n1", "2d-n2-bubble", "3d-n2-bubble"])
+def test_wavespeed_parity(name):
+    say(f"[wavespeed parity] {name}")
+    sp, o, JU, J, x, disp, jx, jt = prepared(name)
+    _, lam, dt = o.max_wavespeed(JU, J, jx, 0.3)
+    ctx = es.Context(sp)
+    l_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    d_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.max_wavespeed(dev(JU), dev(J), dev(jx), 0.3, l_dev, d_dev)
+    assert host(l_dev)[0] == pytest.approx(lam, rel=1e-13)
+    assert host(d_dev)[0] == pytest.approx(dt, rel=1e-13)
+
+
+@pytest.mark.parametrize("name,mon", [("2d-n2-bubble", dict(sigma=[0], alpha=[1200.0], n_smooth=3, n_sweeps=10)),
+                                      ("2d-n1", dict(sigma=[0, 3], alpha=[50.0, 20.0], n_smooth=5, n_sweeps=7)),
+                                      ("3d-n2-bubble", dict(sigma=[0], alpha=[1200.0], n_smooth=3, n_sweeps=5)),
+                                      ("3d-n2-random", dict(sigma=[1, 2], alpha=[300.0, 300.0], n_smooth=2, n_sweeps=6))])
+def test_mesh_redistribute_parity(name, mon):
+    say(f"[mesh parity] {name} {mon}")
+    sp, o, JU, J, x, disp, jx, jt = prepared(name)
+    rc, d_ref, tau_ref, res_ref = o.mesh_redistribute(mon, JU, J, x)
+    assert rc == 0
+    ctx = es.Context(sp)
+    gd = torch.zeros_like(dev(x))
+    tau = torch.zeros(1, dtype=torch.float64, device="cuda")
+    res = torch.zeros(mon["n_sweeps"], dtype=torch.float64, device="cuda")
+    ctx.mesh_redistribute(mon, dev(JU), dev(J), dev(x), gd, tau, res)
+    hd = host(gd)
+    assert host(tau)[0] == pytest.approx(tau_ref, rel=1e-12)
+    np.testing.assert_allclose(host(res), res_ref, rtol=1e-10, atol=1e-14 * np.abs(x).max())
+    for c in range(sp["dim"]):
+        assert parity(hd[c], d_ref[c], np.abs(x[c]).max()) <= TOL_FP64, c
+
+
+@pytest.mark.parametrize("name", ["2d-n1", "3d-n2-random"])
+def test_entropy_parity(name):
+    say(f"[entropy parity] {name}")
+    sp, o, JU, J, x, disp, jx, jt = prepared(name)
+    _, dU, dJ = o.rhs(JU, J, jx, jt)
+    tot = o.total_entropy(JU, J)
+    rate = o.entropy_rate(JU, J, dU, dJ)
+    ctx = es.Context(sp)
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ctx.es_entropy(dev(JU), dev(J), out[0:1])
+    ctx.es_entropy_rate(dev(JU), dev(J), dev(dU), dev(dJ), out[1:2])
+    h = host(out)
+    assert h[0] == pytest.approx(tot, rel=1e-12)
+    # the rate is a sum of cancelling terms: compare on the scale of its terms
+    Iin = I.interior(sp)
+    scale = np.abs(dU[Iin]).sum() * 50 * np.prod(sp["dxi"][: sp["dim"]])
+    assert abs(h[1] - rate) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("name", ["2d-n1", "2d-n2-bubble", "3d-n2-bubble"])
+def test_rk_stage_parity(name):
+    say(f"[rk stage parity] {name}")
+    sp, o, JU, J, x, disp, jx, jt = prepared(name)
+    _, lam, dt = o.max_wavespeed(JU, J, jx, 0.3)
+    rng = np.random.default_rng(5)
+    JUn = JU * (1 + 1e-3 * rng.uniform(-1, 1, JU.shape[1:]))[None]
+    Jn = J * (1 + 1e-3 * rng.uniform(-1, 1, J.shape[1:]))[None]
+    ctx = es.Context(sp)
+    dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    Iin = I.interior(sp)
+    sc = state_scale(JU, sp, lam)
+    for stage in range(3):
+        rc, oU, oJ = o.rk_stage(stage, dt, JUn, Jn, JU, J, jx, jt)
+        gU, gJ = torch.zeros_like(dev(JU)), torch.zeros_like(dev(J))
+        ctx.es_rk_stage(stage, dt_dev, dev(JUn), dev(Jn), dev(JU), dev(J), dev(jx), dev(jt), gU, gJ)
+        hU, hJ = host(gU), host(gJ)
+        for c in range(o.nc):
+            assert parity(hU[c][Iin[1:]], oU[c][Iin[1:]], sc[c]) <= TOL_FP64, (stage, c)
+        assert parity(hJ[Iin], oJ[Iin], np.abs(J).max()) <= TOL_FP64
+
+
+@pytest.mark.parametrize("name,move,nsteps,tol", [("2d-n1", False, 3, TOL_FP64),
+                                                  ("2d-n2-bubble", True, 3, TOL_FP64),
+                                                  ("3d-n2-bubble", True, 2, TOL_FP64)])
+def test_step_parity(name, move, nsteps, tol):
+    say(f"[step parity] {name} move={move} steps={nsteps}")
+    sp, o, JU, J, x, disp, jx, jt = prepared(name)
+    mon = dict(sigma=[0], alpha=[1200.0], n_smooth=3, n_sweeps=5)
+    ctx = es.Context(sp)
+    gU, gJ, gx = dev(JU), dev(J), dev(x)
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    tau_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for n in range(nsteps):
+        rc, dt, tau = o.step(JU, J, x, mon=mon, cfl=0.3, move_mesh=move)
+        assert rc == 0
+        ctx.es_step(gU, gJ, gx, mon=mon, cfl=0.3, move_mesh=move, dt_dev=dt_dev, dtau_dev=tau_dev)
+        assert host(dt_dev)[0] == pytest.approx(dt, rel=1e-12), n
+        if move:
+            assert host(tau_dev)[0] == pytest.approx(tau, rel=1e-12), n
+    hU, hJ, hx = host(gU), host(gJ), host(gx)
+    Iin = I.interior(sp)
+    _, lam, _ = o.max_wavespeed(JU, J, o.metrics(x)[0], 1.0)
+    sc = state_scale(JU, sp, lam)
+    worst = 0.0
+    for c in range(o.nc):
+        e = parity(hU[c][Iin[1:]], JU[c][Iin[1:]], sc[c])
+        worst = max(worst, e)
+        assert e <= tol, (c, e)
+    assert parity(hJ[Iin], J[Iin], np.abs(J).max()) <= tol
+    for c in range(sp["dim"]):
+        assert parity(hx[c], x[c], np.abs(x[c]).max()) <= tol
+    assert ctx.es_status()[0] == es.ES_OK
+    say(f"    worst state parity after {nsteps} steps: {worst:.2e}")
+
+
+def test_nonphysical_state_is_flagged():
+    say("[status] non-physical state")
+    sp, o, JU, J, x, disp, jx, jt = prepared("2d-n1", moving=False)
+    bad = JU.copy()
+    bad[0][0, 3 + 3, 4 + 3] = -1.0            # a negative density at an interior node
+    ctx = es.Context(sp)
+    gU, gJ = torch.zeros_like(dev(JU)), torch.zeros_like(dev(J))
+    ctx.es_rhs(dev(JU), dev(J), dev(jx), dev(jt), gU, gJ)
+    assert ctx.es_status()[0] == es.ES_OK
+    ctx.es_rhs(dev(bad), dev(J), dev(jx), dev(jt), gU, gJ)
+    rc, flags = ctx.es_status(reset=True)
+    assert rc == es.ES_ENONPHYS and flags & es.ES_ST_NONPHYS
+    assert ctx.es_status()[0] == es.ES_OK
+    badJ = J.copy()
+    badJ[0, 0, 5, 5] = -0.5
+    ctx.es_rhs(dev(JU), dev(badJ), dev(jx), dev(jt), gU, gJ)
+    rc, flags = ctx.es_status(reset=True)
+    assert flags & es.ES_ST_TANGLE
+
+
+def test_aliasing_rejected():
+    sp, o, JU, J, x, disp, jx, jt = prepared("2d-n1", moving=False)
+    ctx = es.Context(sp)
+    gU, gJ = dev(JU), dev(J)
+    with pytest.raises(es.EsError):
+        ctx.es_rhs(gU, gJ, dev(jx), dev(jt), gU, torch.zeros_like(gJ))
+    dt_dev = torch.ones(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(es.EsError):
+        ctx.es_rk_stage(0, dt_dev, gU, gJ, gU, gJ, dev(jx), dev(jt), gU, gJ)
+
+
+def test_step_is_deterministic():
+    say("[determinism] two identical steps")
+    sp, o, JU, J, x, disp, jx, jt = prepared("3d-n2-bubble")
+    mon = dict(sigma=[0], alpha=[1200.0], n_smooth=3, n_sweeps=5)
+    outs = []
+    for _ in range(2):
+        ctx = es.Context(sp)
+        gU, gJ, gx = dev(JU), dev(J), dev(x)
+        ctx.es_step(gU, gJ, gx, mon=mon, cfl=0.3, move_mesh=True)
+        outs.append((host(gU), host(gJ), host(gx)))
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
