@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Benchmark: cell-stage updates/s of the entropy-stable moving-mesh step on
+the 3D two-species 256^3 shock-bubble workload (water/air, stiffened gas).
+
+One step = mesh redistribution (monitor, 3 filter passes, 5 Jacobi sweeps,
+limiter) + GCL metrics + CFL step + three fused SSP-RK3 stages (ES flux:
+2w = 6 EC flux + MR-WENO dissipation) + ghost layers + the FP64 total
+entropy.  value = 256^3 * 3 / (seconds per step).
+
+Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
+PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector (FMA = 2 flops)
+PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (packed)
+
+# Algorithmic work of one cell-stage of the fused RK stage, 3D, N = 2 (the
+# counts are derived in the design notes): flops with add/mul/div/sqrt/log = 1
+# and FMA = 2; bytes = JU (6) + J + 9 spatial + 3 time metrics + JU_n (6) + J_n
+# read, JU_out (6) + J_out written, FP64.
+FLOPS_PER_CELL_STAGE = {(3, 2): 7337, (3, 1): 5804, (2, 2): 4040, (2, 1): 3029}
+BYTES_PER_CELL_STAGE = {(3, 2): 33 * 8, (3, 1): 29 * 8, (2, 2): 23 * 8, (2, 1): 19 * 8}
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("es_rhs.hip", "es_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2202_07989_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per fused stage measured with rocprofv3 counters (FETCH_SIZE,
+    WRITE_SIZE, calibrated on a copy kernel), if taken on the current kernel."""
+    p = os.path.join(ROOT, "profiles", "rk_stage_c3_256_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        t = json.load(fh)
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_stage")
+
+
+def cpu_baseline(sp, JU, J, x, n):
+    """The CPU oracle (never tuned) on a bounded sample of the same workload:
+    one fused RK stage on a 64^3 box of the same shock-bubble data, all host
+    cores (OpenMP)."""
+    import numpy as np
+
+    import oracle
+    from paper_2202_07989_amd import inputs as I
+    m = 64 if n >= 64 else n
+    sps = I.spec_c3(m)
+    o = oracle.Oracle(sps)
+    JUs, Js, xs = I.init_shock_bubble(sps)
+    o.fill_ghosts(JUs, o.nc)
+    o.fill_ghosts(Js, 1)
+    o.fill_ghosts_x(xs)
+    jx, jt = o.metrics(xs)
+    _, lam, dt = o.max_wavespeed(JUs, Js, jx, 0.3)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        o.rk_stage(1, dt, JUs, Js, JUs, Js, jx, jt)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > 10.0 or reps >= 20:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rate = m ** 3 * reps / el
+    return {"value": rate, "unit": "cell-stage updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} fused RK stage(s) of the oracle on a {m}^3 box of the same "
+                      f"3D two-species shock-bubble data ({el:.1f} s)"}
+
+
+def stage_inputs(ctx, mon, cfl, gU, gJ, gx, dt_dev):
+    """Moving-mesh metrics, dt and stage buffers of the current state."""
+    import torch
+    d = 3
+    jx = torch.empty((d * d,) + tuple(gJ.shape[1:]), dtype=torch.float64, device="cuda")
+    jt = torch.empty((d,) + tuple(gJ.shape[1:]), dtype=torch.float64, device="cuda")
+    disp = torch.empty_like(gx)
+    ctx.mesh_redistribute(mon, gU, gJ, gx, disp)
+    ctx.es_metrics(gx, None, 0.0, None, jx, None)
+    ctx.max_wavespeed(gU, gJ, jx, cfl, None, dt_dev)
+    ctx.es_metrics(gx, disp, 0.5, dt_dev, jx, jt)
+    JUo, Jo = torch.empty_like(gU), torch.empty_like(gJ)
+    JUn, Jn = gU.clone(), gJ.clone()
+    return jx, jt, JUo, Jo, JUn, Jn
+
+
+def run_stage_only(ctx, mon, cfl, gU, gJ, gx, dt_dev, reps):
+    import torch
+    jx, jt, JUo, Jo, JUn, Jn = stage_inputs(ctx, mon, cfl, gU, gJ, gx, dt_dev)
+    for _ in range(reps):
+        ctx.es_rk_stage(1, dt_dev, JUn, Jn, gU, gJ, jx, jt, JUo, Jo)
+    a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")     # 2 GiB
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "stage", "reps": reps, "copy_bytes_each_way": a.numel() * 8}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stage-reps", type=int, default=10)
+    ap.add_argument("--mode", choices=["step", "stage"], default="step",
+                    help="stage: only the fused-RK-stage loop and a 2 GiB device copy (for "
+                         "rocprofv3 counter runs; the copy calibrates FETCH_SIZE/WRITE_SIZE)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2202_07989_amd import es
+    from paper_2202_07989_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    n = args.n
+    sp = I.spec_c3(n)
+    prec = es.ES_MIXED if args.precision == "mixed" else es.ES_FP64
+    JU, J, x = I.init_shock_bubble(sp)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    gU, gJ, gx = dev(JU), dev(J), dev(x)
+    ctx = es.Context(sp, precision=prec)
+    mon = I.monitor_spec(n_sweeps=5, n_smooth=3, sigma=(0,), alpha=(1200.0,))
+    cfl = 0.3
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    tau_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ent = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    def step():
+        ctx.es_step(gU, gJ, gx, mon=mon, cfl=cfl, move_mesh=True, dt_dev=dt_dev, dtau_dev=tau_dev)
+        ctx.es_entropy(gU, gJ, ent)
+
+    stream = torch.cuda.current_stream()
+    if args.mode == "stage":
+        run_stage_only(ctx, mon, cfl, gU, gJ, gx, dt_dev, args.stage_reps)
+        return
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    rc, flags = ctx.es_status()
+    cells = n ** 3
+    value = cells * 3 / (ms_step / 1e3)
+
+    # dominant kernel, timed live: the fused RK stage (three direction sweeps)
+    # on the benchmark's own state and moving-mesh metrics
+    jx, jt, JUo, Jo, JUn, Jn = stage_inputs(ctx, mon, cfl, gU, gJ, gx, dt_dev)
+    ctx.es_rk_stage(1, dt_dev, JUn, Jn, gU, gJ, jx, jt, JUo, Jo)
+    torch.cuda.synchronize()
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record(stream)
+    for _ in range(args.stage_reps):
+        ctx.es_rk_stage(1, dt_dev, JUn, Jn, gU, gJ, jx, jt, JUo, Jo)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    ms_stage = s0.elapsed_time(s1) / args.stage_reps
+    key = (3, 2)
+    flops = FLOPS_PER_CELL_STAGE[key] * cells
+    achieved = flops / (ms_stage / 1e3) / 1e12
+    peak = PEAK_FP64_TFLOPS if prec == es.ES_FP64 else PEAK_FP32_TFLOPS
+    traffic = load_traffic()
+    hbm_gbs = BYTES_PER_CELL_STAGE[key] * cells / (ms_stage / 1e3) / 1e9
+
+    out = {
+        "metric": "cell-stage updates/s, 3D 256^3 two-species, FP64 vs mixed FP32; % HBM peak",
+        "value": value,
+        "unit": "cell-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == es.ES_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D two-species stiffened-gas shock-bubble {n}^3, moving mesh "
+                               "(5 Jacobi sweeps, 3 filter passes, alpha 1200), CFL 0.3, "
+                               "6th-order EC + MR-WENO5 ES flux, SSP-RK3",
+                   "grid": [n, n, n], "species": 2, "precision": args.precision},
+        "hbm_frac_of_peak_step": BYTES_PER_CELL_STAGE[key] * value / 1e9 / PEAK_HBM_GBS,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "es_rk_stage (k_rhs_dir x3 directions, fused stage epilogue)",
+                     "ms_per_launch": ms_stage, "algorithmic_hbm_GBs": hbm_gbs,
+                     "algorithmic_hbm_frac": hbm_gbs / PEAK_HBM_GBS},
+        "status": rc,
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sp, JU, J, x, n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

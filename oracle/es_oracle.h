@@ -20,6 +20,14 @@
  *   - The mesh x holds dim components (x_1..x_d).
  *   - All functions take host pointers and run synchronously.
  *
+ * Pins: every function is checked by the CPU tests against what the paper
+ * and the mathematics fix (identities, closed forms, exactness, symmetry,
+ * convergence), except one reading that is parity unpinned: the averaged
+ * interface state used to build R for two species when the left and right
+ * states differ (the paper leaves Y_l, H and d_l of the average open).  Any
+ * symmetric positive choice keeps the scheme entropy stable, so only the
+ * agreement with the GPU path fixes it.
+ *
  * Return codes: 0 ok, -1 invalid argument, -4 non-physical state
  * (rho_l <= 0, T <= 0 or non-finite), -5 tangled mesh (J <= 0 or Delta_tau <= 0).
  */

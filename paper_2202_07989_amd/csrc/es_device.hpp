@@ -19,6 +19,7 @@ struct Phys {
     double alpha[3];          // alpha_{w,m}
     double chi[3], eps;       // MR-WENO linear weights and epsilon
     double ichi3, c1c3, c2c3; // 1/chi_3, chi_1/chi_3, chi_2/chi_3
+    double r21;               // R_2 / R_1 (N = 2)
 };
 
 struct Geo {
@@ -55,6 +56,18 @@ __device__ __forceinline__ double logmean(double a, double b, double la, double 
     return d / (la - lb);
 }
 
+// 1 / {a}^ln with one division: [[ln a]]/[[a]], or 2F/(a+b) on the series branch
+__device__ __forceinline__ double inv_logmean(double a, double b, double la, double lb)
+{
+    const double d = a - b, s = a + b;
+    if (d * d < 1.0e-4 * (s * s)) {
+        const double u = (d * d) / (s * s);
+        const double F = 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0)));
+        return (2.0 * F) / s;
+    }
+    return (la - lb) / d;
+}
+
 // --------------------------------------------------------------------------
 // fifth-order multi-resolution WENO (Appendix A): value at the right face of
 // the centre cell of (q_-2 .. q_2).  h_2, h_3 are the Legendre expansions
@@ -84,13 +97,20 @@ __device__ __forceinline__ R mr5(R qm2, R qm1, R q0, R qp1, R qp2, const Weno<R>
                + R(1421461.0 / 2275.0) * c5 * c5;
     R tau = R(0.5) * (fabs(b3 - b1) + fabs(b3 - b2));
     tau = tau * tau;
-    const R w1 = W.chi1 * (R(1) + tau / (W.eps + b1));
-    const R w2 = W.chi2 * (R(1) + tau / (W.eps + b2));
-    const R w3 = W.chi3 * (R(1) + tau / (W.eps + b3));
     const R h1 = q0;
     const R h2 = (R(-1) * qm1 + R(5) * q0 + R(2) * qp1) * R(1.0 / 6.0);
     const R h3 = (R(2) * qm2 - R(13) * qm1 + R(47) * q0 + R(27) * qp1 - R(3) * qp2) * R(1.0 / 60.0);
     const R hc = h3 * W.ichi3 - W.c1c3 * h1 - W.c2c3 * h2;
+    // weights chi_m (1 + tau/d_m), d_m = eps + beta_m, taken over the common
+    // denominator d_1 d_2 d_3 so that the normalised sum needs one division
+    R d1 = W.eps + b1, d2 = W.eps + b2, d3 = W.eps + b3;
+    if constexpr (sizeof(R) == 4) {   // keep the products in float range
+        const R dm = R(1) / fmax(fmax(d1, d2), d3);
+        d1 *= dm; d2 *= dm; d3 *= dm; tau *= dm;
+    }
+    const R w1 = W.chi1 * (d1 + tau) * (d2 * d3);
+    const R w2 = W.chi2 * (d2 + tau) * (d1 * d3);
+    const R w3 = W.chi3 * (d3 + tau) * (d1 * d2);
     return (w1 * h1 + w2 * h2 + w3 * hc) / (w1 + w2 + w3);
 }
 

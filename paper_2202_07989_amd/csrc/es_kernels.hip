@@ -128,9 +128,10 @@ __device__ __forceinline__ double xs_at(const double* xn, const double* disp, do
     return v;
 }
 
-// 3D pass 1: G[a][p] = delta_a[xs_p] at nodes interior along a
-__global__ void k_metric_grad3(Geo g, Phys ph, const double* __restrict__ xn,
-                               const double* __restrict__ disp, double cs, double* __restrict__ G)
+// 3D pass 1: the products Pr[a][j] = delta_a[xs_p] xs_q, (p, q) = (j+1, j+2)
+// mod 3, at every node interior along a (the ones pass 2 differences)
+__global__ void k_metric_prod3(Geo g, Phys ph, const double* __restrict__ xn,
+                               const double* __restrict__ disp, double cs, double* __restrict__ Pr)
 {
     const long P = g.P;
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < P; t += (long)gridDim.x * blockDim.x) {
@@ -139,25 +140,30 @@ __global__ void k_metric_grad3(Geo g, Phys ph, const double* __restrict__ xn,
         const int i1 = (int)(r % g.np[1]);
         const int i2 = (int)(r / g.np[1]);
         const int idx[3] = {i0, i1, i2};
+        const double x3[3] = {xs_at(xn, disp, cs, P, 0, t), xs_at(xn, disp, cs, P, 1, t),
+                              xs_at(xn, disp, cs, P, 2, t)};
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             if (idx[a] < g.ng || idx[a] >= g.ng + g.n[a]) continue;
             const long st = dir_stride(g, a);
+            double dx[3];
 #pragma unroll
             for (int p = 0; p < 3; p++) {
                 double s = 0.0;
                 for (int m = 1; m <= ph.w; m++)
                     s += ph.alpha[m - 1] * (xs_at(xn, disp, cs, P, p, t + m * st) -
                                             xs_at(xn, disp, cs, P, p, t - m * st));
-                G[(a * 3 + p) * P + t] = 0.5 * s;
+                dx[p] = 0.5 * s;
             }
+#pragma unroll
+            for (int j = 0; j < 3; j++) Pr[(a * 3 + j) * P + t] = dx[(j + 1) % 3] * x3[(j + 2) % 3];
         }
     }
 }
 
-// 3D pass 2: J dxi_k/dx_j = (delta_b[G_ap x_q] - delta_a[G_bp x_q]) / (dxi_a dxi_b)
-__global__ void k_metric3(Geo g, Phys ph, const double* __restrict__ xn,
-                          const double* __restrict__ disp, double cs, const double* __restrict__ G,
+// 3D pass 2: J dxi_k/dx_j = (delta_b[Pr[a][j]] - delta_a[Pr[b][j]]) / (dxi_a dxi_b),
+// (k, a, b) cyclic
+__global__ void k_metric3(Geo g, Phys ph, const double* __restrict__ disp, const double* __restrict__ Pr,
                           const double* __restrict__ dt_dev, double* __restrict__ jxx,
                           double* __restrict__ jxt)
 {
@@ -174,15 +180,12 @@ __global__ void k_metric3(Geo g, Phys ph, const double* __restrict__ xn,
             const long sa = dir_stride(g, a), sb = dir_stride(g, b);
 #pragma unroll
             for (int j = 0; j < 3; j++) {
-                const int p = (j + 1) % 3, qq = (j + 2) % 3;
+                const double* Pa = Pr + (a * 3 + j) * P;
+                const double* Pb = Pr + (b * 3 + j) * P;
                 double t1 = 0.0, t2 = 0.0;
                 for (int m = 1; m <= ph.w; m++) {
-                    const long bp = i + m * sb, bm = i - m * sb;
-                    const long ap = i + m * sa, am = i - m * sa;
-                    t1 += ph.alpha[m - 1] * (G[(a * 3 + p) * P + bp] * xs_at(xn, disp, cs, P, qq, bp) -
-                                             G[(a * 3 + p) * P + bm] * xs_at(xn, disp, cs, P, qq, bm));
-                    t2 += ph.alpha[m - 1] * (G[(b * 3 + p) * P + ap] * xs_at(xn, disp, cs, P, qq, ap) -
-                                             G[(b * 3 + p) * P + am] * xs_at(xn, disp, cs, P, qq, am));
+                    t1 += ph.alpha[m - 1] * (Pa[i + m * sb] - Pa[i - m * sb]);
+                    t2 += ph.alpha[m - 1] * (Pb[i + m * sa] - Pb[i - m * sa]);
                 }
                 M[k][j] = (0.5 * t1 - 0.5 * t2) * (g.idxi[a] * g.idxi[b]);
             }
@@ -283,9 +286,8 @@ hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double*
         hipLaunchKernelGGL(k_metric2, dim3(grid_for(nint)), dim3(256), 0, s, g, ph, xn, disp, cs, dt_dev,
                            jxx, jxt);
     } else {
-        hipLaunchKernelGGL(k_metric_grad3, dim3(grid_for(g.P)), dim3(256), 0, s, g, ph, xn, disp, cs, G);
-        hipLaunchKernelGGL(k_metric3, dim3(grid_for(nint)), dim3(256), 0, s, g, ph, xn, disp, cs, G, dt_dev,
-                           jxx, jxt);
+        hipLaunchKernelGGL(k_metric_prod3, dim3(grid_for(g.P)), dim3(256), 0, s, g, ph, xn, disp, cs, G);
+        hipLaunchKernelGGL(k_metric3, dim3(grid_for(nint)), dim3(256), 0, s, g, ph, disp, G, dt_dev, jxx, jxt);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -24,6 +24,8 @@ struct NodeTile {
     double rho[N][NN];     // species densities
     double lrho[N][NN];    // their logs
     double lrt[NN];        // log of total density (N = 2)
+    double gm[N == 2 ? NN : 1];   // mixture Gamma (N = 2)
+    double rm[N == 2 ? NN : 1];   // mixture gas constant (N = 2)
     double v[D][NN];       // velocity
     double b[NN];          // beta = 1/T
     double lb[NN];         // log beta
@@ -55,9 +57,8 @@ __device__ __forceinline__ void ec_pair(const Phys& ph, const NodeTile<N, D, NN>
         vn += vm[j] * n[j];
     }
     v2 *= R(0.5);
-    const R bln = R(logmean(S.b[ia], S.b[ib], S.lb[ia], S.lb[ib]));
-    const R ibln = R(1) / bln;
-    const R bm = R(0.5) * (R(S.b[ia]) + R(S.b[ib]));
+    const R ibln = R(inv_logmean(S.b[ia], S.b[ib], S.lb[ia], S.lb[ib]));
+    const R bsum = R(S.b[ia]) + R(S.b[ib]);
     R Mt = R(0), Rr = R(0), eng = R(0);
 #pragma unroll
     for (int l = 0; l < N; l++) {
@@ -68,7 +69,7 @@ __device__ __forceinline__ void ec_pair(const Phys& ph, const NodeTile<N, D, NN>
         Rr += R(ph.Rg[l]) * (R(S.rho[l][ia]) + R(S.rho[l][ib]));
         eng += Ml * (R(ph.cv[l]) * ibln - R(0.5) * v2);
     }
-    const R phat = R(0.5) * Rr / bm - R(ph.pinf_tot);
+    const R phat = Rr / bsum - R(ph.pinf_tot);   // sum R_l {rho_l} / {beta} - p_inf
 #pragma unroll
     for (int j = 0; j < D; j++) {
         const R fm = vm[j] * Mt + phat * n[j];
@@ -121,8 +122,7 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
 #pragma unroll
     for (int j = 0; j < D; j++) vv += F.vh[j] * F.vh[j];
     F.K = R(0.5) * vv;
-    const double Tbar_d = 1.0 / logmean(S.b[iL], S.b[iR], S.lb[iL], S.lb[iR]);
-    const R Tbar = R(Tbar_d);
+    const R Tbar = R(inv_logmean(S.b[iL], S.b[iR], S.lb[iL], S.lb[iR]));   // 1/{beta}^ln
     if constexpr (N == 1) {
         const R G = R(ph.gam[0]), Rg = R(ph.Rg[0]), cv = R(ph.cv[0]);
         const R rho = R(logmean(S.rho[0][iL], S.rho[0][iR], S.lrho[0][iL], S.lrho[0][iR]));
@@ -132,16 +132,9 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
         F.se = sqrt(rho / (cv * G));
         F.st = sqrt(rho * Tbar);
     } else {
-        R rl[2], Rm[2], Gm[2];
-        const int ends[2] = {iL, iR};
-#pragma unroll
-        for (int s = 0; s < 2; s++) {
-            const int q = ends[s];
-            const R r1 = R(S.rho[0][q]), r2 = R(S.rho[1][q]);
-            const R cr = R(ph.cv[0]) * r1 + R(ph.cv[1]) * r2;
-            Gm[s] = (R(ph.cvgam[0]) * r1 + R(ph.cvgam[1]) * r2) / cr;
-            Rm[s] = (R(ph.Rg[0]) * r1 + R(ph.Rg[1]) * r2) / (r1 + r2);
-        }
+        R rl[2];
+        const R Rm[2] = {R(S.rm[iL]), R(S.rm[iR])};
+        const R Gm[2] = {R(S.gm[iL]), R(S.gm[iR])};
 #pragma unroll
         for (int l = 0; l < 2; l++)
             rl[l] = R(logmean(S.rho[l][iL], S.rho[l][iR], S.lrho[l][iL], S.lrho[l][iR]));
@@ -165,7 +158,7 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
         F.s2a = F.sq * R(0.70710678118654752440);
         const R yy = sqrt(F.Y[0] * F.Y[1]);
         const R sg = sqrt(Gb - R(1));
-        const R r21 = R(ph.Rg[1]) / R(ph.Rg[0]);
+        const R r21 = R(ph.r21);
         F.d11 = -F.sq * yy * sqrt(Gb * r21);
         F.d12 = F.sq * F.Y[0] * sg;
         F.d21 = F.sq * yy * sqrt(Gb / r21);
@@ -301,7 +294,14 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
             S.lrho[s][li] = log(U[s]);
             ok = ok && (U[s] > 0.0);
         }
-        if constexpr (N == 2) S.lrt[li] = log(rt);
+        if constexpr (N == 2) {
+            double cg = 0.0;
+#pragma unroll
+            for (int q = 0; q < N; q++) cg += ph.cvgam[q] * U[q];
+            S.lrt[li] = log(rt);
+            S.gm[li] = cg / cvr;
+            S.rm[li] = rR * ir;
+        }
         if (!ok) bad |= 1u;
         if (!(Jq > 0.0)) bad |= 2u;
         S.m[0][li] = jxt ? jxt[(long)K * P + gi] : 0.0;
