@@ -20,6 +20,7 @@ struct Phys {
     double chi[3], eps;       // MR-WENO linear weights and epsilon
     double ichi3, c1c3, c2c3; // 1/chi_3, chi_1/chi_3, chi_2/chi_3
     double r21;               // R_2 / R_1 (N = 2)
+    double sr21, isr21;       // sqrt(R_2 / R_1) and its reciprocal
 };
 
 struct Geo {
@@ -42,28 +43,31 @@ __device__ __forceinline__ long dir_stride(const Geo& g, int k)
 
 // --------------------------------------------------------------------------
 // logarithmic mean [[a]]/[[ln a]] (Section 3.3.1) from precomputed node logs.
-// Near a = b the ratio is replaced by the series of ln(zeta)/(2f) in
-// u = ((a-b)/(a+b))^2 (cut-off u < 1e-4), exact to rounding there.
+// Near a = b (f = (a-b)/(a+b), u = f^2 < 1e-4) the ratio is evaluated from
+// series in u instead: {a}^ln = (a+b)/2 * f/atanh(f) and
+// 1/{a}^ln = 2/(a+b) * atanh(f)/f, each truncated after u^3 (the dropped
+// terms are below 1e-17 relative there).  One division on either branch.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ double logmean(double a, double b, double la, double lb)
 {
     const double d = a - b, s = a + b;
     if (d * d < 1.0e-4 * (s * s)) {
-        const double u = (d * d) / (s * s);
-        const double F = 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0)));
-        return s / (2.0 * F);
+        const double is = 1.0 / s;
+        const double f = d * is, u = f * f;
+        const double G = 1.0 - u * (1.0 / 3.0 + u * (4.0 / 45.0 + u * (44.0 / 945.0)));
+        return 0.5 * s * G;
     }
     return d / (la - lb);
 }
 
-// 1 / {a}^ln with one division: [[ln a]]/[[a]], or 2F/(a+b) on the series branch
 __device__ __forceinline__ double inv_logmean(double a, double b, double la, double lb)
 {
     const double d = a - b, s = a + b;
     if (d * d < 1.0e-4 * (s * s)) {
-        const double u = (d * d) / (s * s);
+        const double is = 1.0 / s;
+        const double f = d * is, u = f * f;
         const double F = 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0)));
-        return (2.0 * F) / s;
+        return 2.0 * F * is;
     }
     return (la - lb) / d;
 }
@@ -80,8 +84,10 @@ struct Weno {
     R zero_tol;   // relative size below which a jump counts as zero in the sign test
 };
 
+// numerator and denominator of the normalised weighted sum
 template <typename R>
-__device__ __forceinline__ R mr5(R qm2, R qm1, R q0, R qp1, R qp2, const Weno<R>& W)
+__device__ __forceinline__ void mr5_nd(R qm2, R qm1, R q0, R qp1, R qp2, const Weno<R>& W, R& num,
+                                       R& den)
 {
     const R dl = q0 - qm1, dr = qp1 - q0;
     const R b1 = fmin(dl * dl, dr * dr);
@@ -111,7 +117,30 @@ __device__ __forceinline__ R mr5(R qm2, R qm1, R q0, R qp1, R qp2, const Weno<R>
     const R w1 = W.chi1 * (d1 + tau) * (d2 * d3);
     const R w2 = W.chi2 * (d2 + tau) * (d1 * d3);
     const R w3 = W.chi3 * (d3 + tau) * (d1 * d2);
-    return (w1 * h1 + w2 * h2 + w3 * hc) / (w1 + w2 + w3);
+    num = w1 * h1 + w2 * h2 + w3 * hc;
+    den = w1 + w2 + w3;
+}
+
+template <typename R>
+__device__ __forceinline__ R mr5(R qm2, R qm1, R q0, R qp1, R qp2, const Weno<R>& W)
+{
+    R n, d;
+    mr5_nd<R>(qm2, qm1, q0, qp1, qp2, W, n, d);
+    return n / d;
+}
+
+// jump of the two one-sided reconstructions at an interface, wp - wm, from
+// the stencils (q_-2..q_3) seen from the left and from the right.  FP64 takes
+// both quotients over one denominator (the weights stay far inside the FP64
+// range); FP32 divides separately.
+template <typename R>
+__device__ __forceinline__ R mr5_jump(R q0, R q1, R q2, R q3, R q4, R q5, const Weno<R>& W)
+{
+    R nm, dm, np, dp;
+    mr5_nd<R>(q0, q1, q2, q3, q4, W, nm, dm);
+    mr5_nd<R>(q5, q4, q3, q2, q1, W, np, dp);
+    if constexpr (sizeof(R) == 8) return (np * dm - nm * dp) / (dp * dm);
+    else return np / dp - nm / dm;
 }
 
 // --------------------------------------------------------------------------

@@ -1,18 +1,21 @@
 // es_rhs.hip -- the semi-discrete right-hand side (Sections 3.1-3.4) and the
 // fused SSP-RK3 stage (Section 5) on gfx950.
 //
-// One launch per direction k.  A block owns a tile of TL nodes along k by
-// TC lines across it (lines adjacent along the fastest other index, so
-// global loads are coalesced), stages the node quantities of the tile plus a
-// 3-node halo along k in LDS, and then
-//   phase 2: one thread per interface i+1/2 builds the ES dissipation
-//            1/2 s T^T R Y [[W]]^WENO (eq HOstable) and parks it in LDS;
-//   phase 3: one thread per node forms the 2w-order EC flux difference in
-//            flux-differencing form sum_m alpha_m [F(i,i+m) - F(i-m,i)]
-//            (the telescoped eq ECFlux_curv_2p), the GCL term delta_k[n_t]
-//            (eq GCL_flux), subtracts the dissipation difference and
-//            accumulates -(...)/dxi_k into the output.
-// The last direction's epilogue can apply the Shu-Osher stage combination.
+// One launch per direction k.  A block of 256 threads owns a tile of TL
+// nodes along k on TC grid lines (consecutive in the line ordering, so the
+// fastest other index runs along the lines and global loads coalesce),
+// stages the node quantities of the tile plus a 3-node halo along k in LDS,
+// and builds the full numerical flux at each of the TL + 1 interfaces of
+// every line, one thread per interface:
+//   F_{i+1/2} = sum_m alpha_m sum_{s<m} F(i-s, i-s+m)  -  D_{i+1/2}
+// (the interface form of eq ECFlux_curv_2p minus the ES dissipation
+// 1/2 s T^T R Y [[W]]^WENO of eq HOstable).  Each two-point flux
+// F(a, a+m) is evaluated once, by the thread whose interface has left node
+// a; the m interfaces that use it collect it through an LDS exchange in
+// three barrier-separated steps.  The node update is then the interface
+// difference plus the GCL term delta_k[n_t] (eq GCL_flux), times -1/dxi_k,
+// accumulated into the output; the last direction's epilogue can apply the
+// Shu-Osher stage combination.
 #include "es_kernels.hpp"
 
 namespace es {
@@ -23,15 +26,25 @@ template <int N, int D, int NN>
 struct NodeTile {
     double rho[N][NN];     // species densities
     double lrho[N][NN];    // their logs
-    double lrt[NN];        // log of total density (N = 2)
-    double gm[N == 2 ? NN : 1];   // mixture Gamma (N = 2)
-    double rm[N == 2 ? NN : 1];   // mixture gas constant (N = 2)
+    double lrt[N == 2 ? NN : 1];  // log of the total density (N = 2)
     double v[D][NN];       // velocity
     double b[NN];          // beta = 1/T
     double lb[NN];         // log beta
-    double p[NN];          // pressure
     double m[D + 1][NN];   // metrics of direction k: n_t, n_1..n_D
 };
+
+// mixture Gamma, gas constant and pressure of tile node q (N = 2)
+template <int N, int D, int NN>
+__device__ __forceinline__ void mixture(const Phys& ph, const NodeTile<N, D, NN>& S, int q,
+                                        double& gm, double& rm, double& p)
+{
+    const double r0 = S.rho[0][q], r1 = S.rho[1][q];
+    const double cvr = ph.cv[0] * r0 + ph.cv[1] * r1;
+    const double rR = ph.Rg[0] * r0 + ph.Rg[1] * r1;
+    gm = (ph.cvgam[0] * r0 + ph.cvgam[1] * r1) / cvr;
+    rm = rR / (r0 + r1);
+    p = rR / S.b[q] - ph.pinf_tot;
+}
 
 // two-point EC flux between tile nodes ia, ib (eq ECfluxMM), written in the
 // direction-generic form n_t Utilde + sum_j n_j Ftilde_j:
@@ -133,8 +146,11 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
         F.st = sqrt(rho * Tbar);
     } else {
         R rl[2];
-        const R Rm[2] = {R(S.rm[iL]), R(S.rm[iR])};
-        const R Gm[2] = {R(S.gm[iL]), R(S.gm[iR])};
+        double gmL, gmR, rmL, rmR, pL, pR;
+        mixture<N, D, NN>(ph, S, iL, gmL, rmL, pL);
+        mixture<N, D, NN>(ph, S, iR, gmR, rmR, pR);
+        const R Rm[2] = {R(rmL), R(rmR)};
+        const R Gm[2] = {R(gmL), R(gmR)};
 #pragma unroll
         for (int l = 0; l < 2; l++)
             rl[l] = R(logmean(S.rho[l][iL], S.rho[l][iR], S.lrho[l][iL], S.lrho[l][iR]));
@@ -143,7 +159,7 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
         const R Rb = R(0.5) * (Rm[0] + Rm[1]);
         const R Gb = R(0.5) * (Gm[0] + Gm[1]);
         const R irho = R(1) / rho;
-        R rhoh = R(0.5) * (R(S.p[iL]) + R(S.p[iR]));
+        R rhoh = R(0.5) * (R(pL) + R(pR));
 #pragma unroll
         for (int l = 0; l < 2; l++) rhoh += R(ph.cv[l]) * rl[l] * Tbar + R(ph.pinf[l]);
         F.H = rhoh * irho + F.K;
@@ -158,10 +174,10 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
         F.s2a = F.sq * R(0.70710678118654752440);
         const R yy = sqrt(F.Y[0] * F.Y[1]);
         const R sg = sqrt(Gb - R(1));
-        const R r21 = R(ph.r21);
-        F.d11 = -F.sq * yy * sqrt(Gb * r21);
+        const R syg = F.sq * yy * sqrt(Gb);
+        F.d11 = -syg * R(ph.sr21);
         F.d12 = F.sq * F.Y[0] * sg;
-        F.d21 = F.sq * yy * sqrt(Gb / r21);
+        F.d21 = syg * R(ph.isr21);
         F.d22 = F.sq * F.Y[1] * sg;
     }
     const R s = fabs(nt + vn) + nn * F.c;
@@ -194,9 +210,7 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
     R Z[NC];
 #pragma unroll
     for (int c = 0; c < NC; c++) {
-        const R wm = mr5<R>(W[0][c], W[1][c], W[2][c], W[3][c], W[4][c], Wc);
-        const R wp = mr5<R>(W[5][c], W[4][c], W[3][c], W[2][c], W[1][c], Wc);
-        const R jw = wp - wm;
+        const R jw = mr5_jump<R>(W[0][c], W[1][c], W[2][c], W[3][c], W[4][c], W[5][c], Wc);
         const R jump = W[3][c] - W[2][c];
         // sign matrix Y: the WENO jump and the jump agree in sign, and the jump
         // is not zero to working precision (across a contact the acoustic
@@ -225,53 +239,60 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
           double* __restrict__ accU, double* __restrict__ accJ, RkArgs rk,
           unsigned* __restrict__ status)
 {
+    constexpr int NT = 256;
     constexpr int NC = N + D + 1;
-    constexpr int NL = TL + 6;
+    constexpr int NL = TL + 6;          // nodes per line: tile + 3-node halo on each side
     constexpr int NN = NL * TC;
-    constexpr int NI = (TL + 1) * TC;
+    constexpr int NI = (TL + 1) * TC;   // interfaces (one thread each)
+    constexpr int NS = TL + 4;          // exchange slots per line
+    constexpr int NX = NS * TC;
+    static_assert(NI <= NT && 3 * TC <= 64 && TL * TC <= NT, "tile does not fit the block");
     constexpr int FA = (K == 0) ? 1 : 0;   // across index that runs fastest
     constexpr int SA = (K == 2) ? 1 : 2;   // slowest across index
     __shared__ NodeTile<N, D, NN> S;
-    __shared__ R sD[NC][NI];
+    __shared__ R X[NC][NX];
 
     const long P = g.P;
     const int nK = g.n[K];
     const int nF = g.n[FA];
+    const long nlines = (long)nF * ((SA < D) ? g.n[SA] : 1);
     const int nseg = (nK + TL - 1) / TL;
-    const int seg = blockIdx.x % nseg;
-    const int fc = blockIdx.x / nseg;
-    const int seg0 = seg * TL, c0 = fc * TC;
-    const int slow = (SA < D) ? (int)blockIdx.y + g.ng : 0;
+    const int seg0 = (int)(blockIdx.x % nseg) * TL;
+    const long line0 = (long)(blockIdx.x / nseg) * TC;
+    const long sK = dir_stride(g, K);
+    const int t = threadIdx.x;
 
     auto lidx = [](int l, int c) { return (K == 0) ? (l + NL * c) : (c + TC * l); };
-    auto gidx = [&](int along, int fast) -> long {
+    auto xidx = [](int s, int c) { return (K == 0) ? (s + NS * c) : (c + TC * s); };
+    // padded index of the node at along-index 0 of line c of the block
+    auto line_base = [&](int c) -> long {
+        const long L = line0 + c;
         int i[3];
-        i[K] = along;
-        i[FA] = fast;
-        i[SA] = slow;
+        i[K] = 0;
+        i[FA] = g.ng + (int)(L % nF);
+        i[SA] = (SA < D) ? g.ng + (int)(L / nF) : 0;
         return node_index(g, i[0], i[1], i[2]);
     };
 
     // ---- phase 1: node quantities of the tile (+ halo) into LDS ----------
     unsigned bad = 0;
-    for (int t = threadIdx.x; t < NN; t += blockDim.x) {
-        const int l = (K == 0) ? (t % NL) : (t / TC);
-        const int c = (K == 0) ? (t / NL) : (t % TC);
+    for (int q = t; q < NN; q += NT) {
+        const int l = (K == 0) ? (q % NL) : (q / TC);
+        const int c = (K == 0) ? (q / NL) : (q % TC);
         const int along = g.ng + seg0 + l - 3;
-        if (along >= g.np[K] || c0 + c >= nF) continue;
-        const long gi = gidx(along, g.ng + c0 + c);
+        if (along >= g.np[K] || line0 + c >= nlines) continue;
+        const long gi = line_base(c) + along * sK;
         const int li = lidx(l, c);
         const double Jq = Jv[gi];
         const double iJ = 1.0 / Jq;
         double U[NC];
 #pragma unroll
         for (int cc = 0; cc < NC; cc++) U[cc] = JU[cc * P + gi] * iJ;
-        double rt = 0.0, cvr = 0.0, rR = 0.0;
+        double rt = 0.0, cvr = 0.0;
 #pragma unroll
-        for (int s = 0; s < N; s++) {
-            rt += U[s];
-            cvr += ph.cv[s] * U[s];
-            rR += ph.Rg[s] * U[s];
+        for (int sp = 0; sp < N; sp++) {
+            rt += U[sp];
+            cvr += ph.cv[sp] * U[sp];
         }
         const double ir = 1.0 / rt;
         double kin = 0.0;
@@ -282,26 +303,17 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
             kin += 0.5 * U[N + j] * vj;
         }
         const double e = U[NC - 1] - kin - ph.pinf_tot;
-        const double T = e / cvr;
         const double beta = cvr / e;
         S.b[li] = beta;
         S.lb[li] = log(beta);
-        S.p[li] = rR * T - ph.pinf_tot;
-        bool ok = (T > 0.0) && isfinite(T) && isfinite(kin);
+        bool ok = (beta > 0.0) && isfinite(beta) && isfinite(kin);
 #pragma unroll
-        for (int s = 0; s < N; s++) {
-            S.rho[s][li] = U[s];
-            S.lrho[s][li] = log(U[s]);
-            ok = ok && (U[s] > 0.0);
+        for (int sp = 0; sp < N; sp++) {
+            S.rho[sp][li] = U[sp];
+            S.lrho[sp][li] = log(U[sp]);
+            ok = ok && (U[sp] > 0.0);
         }
-        if constexpr (N == 2) {
-            double cg = 0.0;
-#pragma unroll
-            for (int q = 0; q < N; q++) cg += ph.cvgam[q] * U[q];
-            S.lrt[li] = log(rt);
-            S.gm[li] = cg / cvr;
-            S.rm[li] = rR * ir;
-        }
+        if constexpr (N == 2) S.lrt[li] = log(rt);
         if (!ok) bad |= 1u;
         if (!(Jq > 0.0)) bad |= 2u;
         S.m[0][li] = jxt ? jxt[(long)K * P + gi] : 0.0;
@@ -311,82 +323,143 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
     if (bad) atomicOr(status, bad);
     __syncthreads();
 
-    // ---- phase 2: interface dissipation --------------------------------
-    if (ph.dissipation) {
-        Weno<R> Wc;
-        Wc.chi1 = R(ph.chi[0]); Wc.chi2 = R(ph.chi[1]); Wc.chi3 = R(ph.chi[2]);
-        Wc.eps = R(ph.eps); Wc.ichi3 = R(ph.ichi3); Wc.c1c3 = R(ph.c1c3); Wc.c2c3 = R(ph.c2c3);
-        Wc.zero_tol = sizeof(R) == 8 ? R(1e-12) : R(4e-6);
-        for (int t = threadIdx.x; t < NI; t += blockDim.x) {
-            const int li = (K == 0) ? (t % (TL + 1)) : (t / TC);   // interface slot 0..TL
-            const int c = (K == 0) ? (t / (TL + 1)) : (t % TC);
-            const int l = li + 2;                                   // left node of the interface
-            if (g.ng + seg0 + l >= g.np[K] || c0 + c >= nF) continue;  // node l+3 not loaded
+    // ---- phase 2: interface fluxes --------------------------------------
+    // Interface slot f = 0..TL of a line has left node l = f + 2 (tile node
+    // l - 3 is the first node of the tile).  Its thread evaluates
+    // P_m = F(l, l+m), m = 1..3, and with B(f) = a3 P_3,
+    // H(f) = a2 P_2 + B(f) the flux is
+    //   F_f = a1 P_1 - D_f + H(f) + H(f-1) + B(f-2).
+    // X slot f+2 carries B(f), then H(f), then slot f+1 the final F_f.  The
+    // pairs F(0,3), F(1,4), F(1,3) left of the first interface (B(-2),
+    // B(-1), H(-1)) are taken by 3 TC lanes of one wave, rotated over the
+    // blocks so that no SIMD carries them all.
+    const R a1 = R(ph.alpha[0]), a2 = R(ph.alpha[1]), a3 = R(ph.alpha[2]);
+    {
+        const int hw = (int)(blockIdx.x & 3) * 64;
+        const int hid = t - hw;
+        if (hid >= 0 && hid < 3 * TC) {
+            const int h = hid / TC, c = hid % TC;
+            const R am = (h == 2) ? a2 : a3;
+            const int slot = (h == 0) ? 0 : ((h == 1) ? 1 : TL + 3);
+            R F[NC];
+            if (line0 + c < nlines && am != R(0)) {
+                ec_pair<N, D, NN, R>(ph, S, lidx(h == 0 ? 0 : 1, c), lidx(h == 1 ? 4 : 3, c), F);
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < NC; cc++) F[cc] = R(0);
+            }
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) X[cc][xidx(slot, c)] = am * F[cc];
+        }
+    }
+    const int fi = (K == 0) ? (t % (TL + 1)) : (t / TC);
+    const int fc = (K == 0) ? (t / (TL + 1)) : (t % TC);
+    const int fl = fi + 2;
+    // node fl + 3 must be inside the padded grid (ragged last segment)
+    const bool f_ok = (t < NI) && (line0 + fc < nlines) && (g.ng + seg0 + fl < g.np[K]);
+    R G[NC], A2[NC];
+    if (f_ok) {
+        R F[NC];
+        if (a3 != R(0)) {
+            ec_pair<N, D, NN, R>(ph, S, lidx(fl, fc), lidx(fl + 3, fc), F);
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) F[cc] = R(0);
+        }
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) X[cc][xidx(fi + 2, fc)] = a3 * F[cc];
+        if (ph.dissipation) {
+            Weno<R> Wc;
+            Wc.chi1 = R(ph.chi[0]); Wc.chi2 = R(ph.chi[1]); Wc.chi3 = R(ph.chi[2]);
+            Wc.eps = R(ph.eps); Wc.ichi3 = R(ph.ichi3); Wc.c1c3 = R(ph.c1c3); Wc.c2c3 = R(ph.c2c3);
+            Wc.zero_tol = sizeof(R) == 8 ? R(1e-12) : R(4e-6);
             int st[6];
 #pragma unroll
-            for (int q = 0; q < 6; q++) st[q] = lidx(l - 2 + q, c);
-            R Dv[NC];
-            dissipation<N, D, NN, R>(ph, S, st, Wc, Dv);
-            const int di = (K == 0) ? (li + (TL + 1) * c) : (c + TC * li);
+            for (int q = 0; q < 6; q++) st[q] = lidx(fl - 2 + q, fc);
+            dissipation<N, D, NN, R>(ph, S, st, Wc, G);
+        } else {
 #pragma unroll
-            for (int cc = 0; cc < NC; cc++) sD[cc][di] = Dv[cc];
+            for (int cc = 0; cc < NC; cc++) G[cc] = R(0);
         }
-        __syncthreads();
+        ec_pair<N, D, NN, R>(ph, S, lidx(fl, fc), lidx(fl + 1, fc), F);
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) G[cc] = a1 * F[cc] - G[cc];
+        if (a2 != R(0)) {
+            ec_pair<N, D, NN, R>(ph, S, lidx(fl, fc), lidx(fl + 2, fc), F);
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) F[cc] = R(0);
+        }
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) A2[cc] = a2 * F[cc];
     }
-
-    // ---- phase 3: flux differences at the tile's nodes -------------------
-    const double dt = (MODE == MODE_RK) ? *rk.dt : 0.0;
-    for (int t = threadIdx.x; t < TL * TC; t += blockDim.x) {
-        const int lo = (K == 0) ? (t % TL) : (t / TC);
-        const int c = (K == 0) ? (t / TL) : (t % TC);
-        if (seg0 + lo >= nK || c0 + c >= nF) continue;
-        const int l = lo + 3;
-        const int me = lidx(l, c);
-        R acc[NC];
-#pragma unroll
-        for (int cc = 0; cc < NC; cc++) acc[cc] = R(0);
-        double gcl = 0.0;
-#pragma unroll
-        for (int m = 1; m <= 3; m++) {
-            if (m > ph.w) break;
-            const R am = R(ph.alpha[m - 1]);
-            const int ip = lidx(l + m, c), imn = lidx(l - m, c);
-            R Fp[NC], Fm[NC];
-            ec_pair<N, D, NN, R>(ph, S, me, ip, Fp);
-            ec_pair<N, D, NN, R>(ph, S, imn, me, Fm);
-#pragma unroll
-            for (int cc = 0; cc < NC; cc++) acc[cc] += am * (Fp[cc] - Fm[cc]);
-            gcl += ph.alpha[m - 1] * (S.m[0][ip] - S.m[0][imn]);
-        }
-        if (ph.dissipation) {
-            const int dr = (K == 0) ? (lo + 1 + (TL + 1) * c) : (c + TC * (lo + 1));
-            const int dl = (K == 0) ? (lo + (TL + 1) * c) : (c + TC * lo);
-#pragma unroll
-            for (int cc = 0; cc < NC; cc++) acc[cc] -= sD[cc][dr] - sD[cc][dl];
-        }
-        const long gi = gidx(g.ng + seg0 + lo, g.ng + c0 + c);
-        const double h = g.idxi[K];
-        const double dJ = -0.5 * gcl * h;
+    __syncthreads();
+    R Hf[NC], Hm[NC];
+    if (f_ok) {
 #pragma unroll
         for (int cc = 0; cc < NC; cc++) {
-            const double d = -(double)acc[cc] * h;
-            double* o = accU + cc * P + gi;
-            if constexpr (MODE == MODE_WRITE) {
-                *o = d;
-            } else if constexpr (MODE == MODE_ADD) {
-                *o += d;
-            } else {
-                const double L = *o + d;
-                *o = rk.a * rk.JUn[cc * P + gi] + rk.b * (JU[cc * P + gi] + dt * L);
-            }
+            G[cc] += X[cc][xidx(fi, fc)];                   // + B(f-2)
+            Hf[cc] = A2[cc] + X[cc][xidx(fi + 2, fc)];      // H(f)
         }
-        if constexpr (MODE == MODE_WRITE) {
-            accJ[gi] = dJ;
-        } else if constexpr (MODE == MODE_ADD) {
-            accJ[gi] += dJ;
-        } else {
-            const double L = accJ[gi] + dJ;
-            accJ[gi] = rk.a * rk.Jn[gi] + rk.b * (Jv[gi] + dt * L);
+        if (fi == 0) {
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) Hm[cc] = X[cc][xidx(TL + 3, fc)] + X[cc][xidx(1, fc)];
+        }
+    }
+    __syncthreads();
+    if (f_ok) {
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) X[cc][xidx(fi + 2, fc)] = Hf[cc];
+        if (fi == 0) {
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) X[cc][xidx(1, fc)] = Hm[cc];
+        }
+    }
+    __syncthreads();
+    if (f_ok) {
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) {
+            const int xi = xidx(fi + 1, fc);
+            X[cc][xi] = G[cc] + (Hf[cc] + X[cc][xi]);     // F_f into slot f+1
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 3: interface differences at the tile's nodes --------------
+    const double dt = (MODE == MODE_RK) ? *rk.dt : 0.0;
+    if (t < TL * TC) {
+        const int lo = (K == 0) ? (t % TL) : (t / TC);
+        const int c = (K == 0) ? (t / TL) : (t % TC);
+        if (seg0 + lo < nK && line0 + c < nlines) {
+            const int l = lo + 3;
+            double gcl = 0.0;
+#pragma unroll
+            for (int m = 1; m <= 3; m++)
+                gcl += ph.alpha[m - 1] * (S.m[0][lidx(l + m, c)] - S.m[0][lidx(l - m, c)]);
+            const long gi = line_base(c) + (g.ng + seg0 + lo) * sK;
+            const double h = g.idxi[K];
+            const double dJ = -0.5 * gcl * h;
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) {
+                const double d = -(double)(X[cc][xidx(lo + 2, c)] - X[cc][xidx(lo + 1, c)]) * h;
+                double* o = accU + cc * P + gi;
+                if constexpr (MODE == MODE_WRITE) {
+                    *o = d;
+                } else if constexpr (MODE == MODE_ADD) {
+                    *o += d;
+                } else {
+                    const double L = *o + d;
+                    *o = rk.a * rk.JUn[cc * P + gi] + rk.b * (JU[cc * P + gi] + dt * L);
+                }
+            }
+            if constexpr (MODE == MODE_WRITE) {
+                accJ[gi] = dJ;
+            } else if constexpr (MODE == MODE_ADD) {
+                accJ[gi] += dJ;
+            } else {
+                const double L = accJ[gi] + dJ;
+                accJ[gi] = rk.a * rk.Jn[gi] + rk.b * (Jv[gi] + dt * L);
+            }
         }
     }
 }
@@ -399,13 +472,14 @@ static hipError_t launch_dir(const Phys& ph, const Geo& g, const double* JU, con
                              const double* jxx, const double* jxt, double* accU, double* accJ,
                              const RkArgs& rk, unsigned* status, hipStream_t s)
 {
-    constexpr int TL = 16, TC = 16;
+    constexpr int TL = 16, TC = 15;
     constexpr int FA = (K == 0) ? 1 : 0;
     constexpr int SA = (K == 2) ? 1 : 2;
-    const int nseg = (g.n[K] + TL - 1) / TL;
-    const int nfc = (g.n[FA] + TC - 1) / TC;
-    const int nslow = (SA < D) ? g.n[SA] : 1;
-    dim3 grid(nseg * nfc, nslow);
+    const long nseg = (g.n[K] + TL - 1) / TL;
+    const long nlines = (long)g.n[FA] * ((SA < D) ? g.n[SA] : 1);
+    const long nblk = nseg * ((nlines + TC - 1) / TC);
+    if (nblk > 0x7fffffffL) return hipErrorInvalidConfiguration;
+    dim3 grid((unsigned)nblk);
     hipLaunchKernelGGL((k_rhs_dir<N, D, K, TL, TC, MODE, R>), grid, dim3(256), 0, s, ph, g, JU, J,
                        jxx, jxt, accU, accJ, rk, status);
     return hipGetLastError();
