@@ -128,82 +128,194 @@ __device__ __forceinline__ double xs_at(const double* xn, const double* disp, do
     return v;
 }
 
-// 3D pass 1: the products Pr[a][j] = delta_a[xs_p] xs_q, (p, q) = (j+1, j+2)
-// mod 3, at every node interior along a (the ones pass 2 differences)
-__global__ void k_metric_prod3(Geo g, Phys ph, const double* __restrict__ xn,
-                               const double* __restrict__ disp, double cs, double* __restrict__ Pr)
+// 3D metrics in two z-marching passes.  Pass 1 forms the products
+//   Pr[a][j] = delta_a[xs_p] xs_q,  (p, q) = (j+1, j+2) mod 3,
+// at every node interior along a; pass 2 differences them,
+//   J dxi_k/dx_j = (delta_b[Pr[a][j]] - delta_a[Pr[b][j]]) / (dxi_a dxi_b),  (k, a, b) cyclic.
+// A block owns an MT x MT column of (x, y) nodes and walks up a chunk of z
+// planes: z-differences come from a 7-plane ring in registers (each value is
+// loaded once), x/y-differences from the current plane staged in LDS with a
+// 3-node halo.  delta is the 2w-order central difference
+// 1/2 sum_m alpha_m (f_{+m} - f_{-m}) (alpha_m = 0 for m > w).
+constexpr int MT = 16;
+constexpr int MH = MT + 6;
+
+__device__ __forceinline__ double cdiff(const double* al, double p1, double m1, double p2, double m2,
+                                        double p3, double m3)
 {
+    double s = al[0] * (p1 - m1);
+    s += al[1] * (p2 - m2);
+    s += al[2] * (p3 - m3);
+    return 0.5 * s;
+}
+
+__global__ void __launch_bounds__(MT * MT)
+k_metric_prod3(Geo g, Phys ph, const double* __restrict__ xn, const double* __restrict__ disp,
+               double cs, double* __restrict__ Pr, int zchunk)
+{
+    __shared__ double T[3][MH][MH];
     const long P = g.P;
-    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < P; t += (long)gridDim.x * blockDim.x) {
-        const int i0 = (int)(t % g.np[0]);
-        const long r = t / g.np[0];
-        const int i1 = (int)(r % g.np[1]);
-        const int i2 = (int)(r / g.np[1]);
-        const int idx[3] = {i0, i1, i2};
-        const double x3[3] = {xs_at(xn, disp, cs, P, 0, t), xs_at(xn, disp, cs, P, 1, t),
-                              xs_at(xn, disp, cs, P, 2, t)};
+    const int np0 = g.np[0], np1 = g.np[1], np2 = g.np[2];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int x0 = blockIdx.x * MT, y0 = blockIdx.y * MT;
+    const int x = x0 + tx, y = y0 + ty;
+    const int zc0 = blockIdx.z * zchunk, zc1 = min(zc0 + zchunk, np2);
+    const bool in = x < np0 && y < np1;
+    const bool xin = x >= g.ng && x < g.ng + g.n[0];
+    const bool yin = y >= g.ng && y < g.ng + g.n[1];
+    const double al[3] = {ph.alpha[0], ph.alpha[1], ph.alpha[2]};
+    double ring[3][7];
 #pragma unroll
-        for (int a = 0; a < 3; a++) {
-            if (idx[a] < g.ng || idx[a] >= g.ng + g.n[a]) continue;
-            const long st = dir_stride(g, a);
-            double dx[3];
+    for (int p = 0; p < 3; p++)
 #pragma unroll
-            for (int p = 0; p < 3; p++) {
-                double s = 0.0;
-                for (int m = 1; m <= ph.w; m++)
-                    s += ph.alpha[m - 1] * (xs_at(xn, disp, cs, P, p, t + m * st) -
-                                            xs_at(xn, disp, cs, P, p, t - m * st));
-                dx[p] = 0.5 * s;
+        for (int r = 0; r < 7; r++) ring[p][r] = 0.0;
+    const int zs = max(zc0 - 3, 0), ze = min(zc1 + 3, np2);
+    for (int zl = zs; zl < ze; zl++) {
+        for (int q = ty * MT + tx; q < MH * MH; q += MT * MT) {
+            const int hx = q % MH, hy = q / MH;
+            const int gx = x0 + hx - 3, gy = y0 + hy - 3;
+            if (gx >= 0 && gx < np0 && gy >= 0 && gy < np1) {
+                const long i = ((long)zl * np1 + gy) * np0 + gx;
+#pragma unroll
+                for (int p = 0; p < 3; p++) {
+                    double v = xn[p * P + i];
+                    if (disp) v += cs * disp[p * P + i];
+                    T[p][hy][hx] = v;
+                }
             }
-#pragma unroll
-            for (int j = 0; j < 3; j++) Pr[(a * 3 + j) * P + t] = dx[(j + 1) % 3] * x3[(j + 2) % 3];
         }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < 3; p++) {
+#pragma unroll
+            for (int r = 0; r < 6; r++) ring[p][r] = ring[p][r + 1];
+            ring[p][6] = in ? T[p][ty + 3][tx + 3] : 0.0;
+        }
+        if (in && zl >= zc0 && zl < zc1) {
+            const long i = ((long)zl * np1 + y) * np0 + x;
+            const int cx = tx + 3, cy = ty + 3;
+            if (xin) {
+                double d[3];
+#pragma unroll
+                for (int p = 0; p < 3; p++)
+                    d[p] = cdiff(al, T[p][cy][cx + 1], T[p][cy][cx - 1], T[p][cy][cx + 2],
+                                 T[p][cy][cx - 2], T[p][cy][cx + 3], T[p][cy][cx - 3]);
+#pragma unroll
+                for (int j = 0; j < 3; j++) Pr[(0 * 3 + j) * P + i] = d[(j + 1) % 3] * T[(j + 2) % 3][cy][cx];
+            }
+            if (yin) {
+                double d[3];
+#pragma unroll
+                for (int p = 0; p < 3; p++)
+                    d[p] = cdiff(al, T[p][cy + 1][cx], T[p][cy - 1][cx], T[p][cy + 2][cx],
+                                 T[p][cy - 2][cx], T[p][cy + 3][cx], T[p][cy - 3][cx]);
+#pragma unroll
+                for (int j = 0; j < 3; j++) Pr[(1 * 3 + j) * P + i] = d[(j + 1) % 3] * T[(j + 2) % 3][cy][cx];
+            }
+        }
+        const int zp = zl - 3;   // ring slot 3 holds plane zp
+        if (in && zp >= zc0 && zp < zc1 && zp >= g.ng && zp < g.ng + g.n[2]) {
+            const long i = ((long)zp * np1 + y) * np0 + x;
+            double d[3];
+#pragma unroll
+            for (int p = 0; p < 3; p++)
+                d[p] = cdiff(al, ring[p][4], ring[p][2], ring[p][5], ring[p][1], ring[p][6], ring[p][0]);
+#pragma unroll
+            for (int j = 0; j < 3; j++) Pr[(2 * 3 + j) * P + i] = d[(j + 1) % 3] * ring[(j + 2) % 3][3];
+        }
+        __syncthreads();
     }
 }
 
-// 3D pass 2: J dxi_k/dx_j = (delta_b[Pr[a][j]] - delta_a[Pr[b][j]]) / (dxi_a dxi_b),
-// (k, a, b) cyclic
-__global__ void k_metric3(Geo g, Phys ph, const double* __restrict__ disp, const double* __restrict__ Pr,
-                          const double* __restrict__ dt_dev, double* __restrict__ jxx,
-                          double* __restrict__ jxt)
+__global__ void __launch_bounds__(MT * MT)
+k_metric3(Geo g, Phys ph, const double* __restrict__ disp, const double* __restrict__ Pr,
+          const double* __restrict__ dt_dev, double* __restrict__ jxx, double* __restrict__ jxt,
+          int zchunk)
 {
+    __shared__ double T[9][MH][MH];   // Pr[a][j] of the current plane, tile + halo
     const long P = g.P;
-    const long nint = n_interior(g);
+    const int np0 = g.np[0], np1 = g.np[1];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int x0 = g.ng + blockIdx.x * MT, y0 = g.ng + blockIdx.y * MT;
+    const int x = x0 + tx, y = y0 + ty;
+    const int zc0 = g.ng + blockIdx.z * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
+    const bool in = x < g.ng + g.n[0] && y < g.ng + g.n[1];
     const double dt = dt_dev ? *dt_dev : 0.0;
-    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
-        int i0, i1, i2;
-        const long i = interior_node(g, q, i0, i1, i2);
-        double M[3][3];
+    const double al[3] = {ph.alpha[0], ph.alpha[1], ph.alpha[2]};
+    const double s01 = g.idxi[0] * g.idxi[1], s12 = g.idxi[1] * g.idxi[2], s20 = g.idxi[2] * g.idxi[0];
+    double ring[6][7];   // Pr[0][j] (0..2) and Pr[1][j] (3..5) at the own node, planes zl-6..zl
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            const int a = (k + 1) % 3, b = (k + 2) % 3;
-            const long sa = dir_stride(g, a), sb = dir_stride(g, b);
+    for (int c = 0; c < 6; c++)
+#pragma unroll
+        for (int r = 0; r < 7; r++) ring[c][r] = 0.0;
+    for (int zl = zc0 - 3; zl < zc1 + 3; zl++) {
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+#pragma unroll
+            for (int r = 0; r < 6; r++) ring[c][r] = ring[c][r + 1];
+            ring[c][6] = in ? Pr[(long)c * P + ((long)zl * np1 + y) * np0 + x] : 0.0;
+        }
+        const int z = zl - 3;
+        if (z < zc0) continue;   // uniform over the block
+        // stage plane z: Pr[0] needs the y-halo, Pr[1] the x-halo, Pr[2] both
+        for (int q = ty * MT + tx; q < MH * MH; q += MT * MT) {
+            const int hx = q % MH, hy = q / MH;
+            const int gx = x0 + hx - 3, gy = y0 + hy - 3;
+            const bool xc = hx >= 3 && hx < 3 + MT, yc = hy >= 3 && hy < 3 + MT;
+            if (gx >= np0 || gy >= np1 || !(xc || yc)) continue;
+            const long i = ((long)z * np1 + gy) * np0 + gx;
 #pragma unroll
             for (int j = 0; j < 3; j++) {
-                const double* Pa = Pr + (a * 3 + j) * P;
-                const double* Pb = Pr + (b * 3 + j) * P;
-                double t1 = 0.0, t2 = 0.0;
-                for (int m = 1; m <= ph.w; m++) {
-                    t1 += ph.alpha[m - 1] * (Pa[i + m * sb] - Pa[i - m * sb]);
-                    t2 += ph.alpha[m - 1] * (Pb[i + m * sa] - Pb[i - m * sa]);
-                }
-                M[k][j] = (0.5 * t1 - 0.5 * t2) * (g.idxi[a] * g.idxi[b]);
+                if (xc) T[j][hy][hx] = Pr[(long)j * P + i];
+                if (yc) T[3 + j][hy][hx] = Pr[(long)(3 + j) * P + i];
+                T[6 + j][hy][hx] = Pr[(long)(6 + j) * P + i];
             }
         }
+        __syncthreads();
+        if (in) {
+            const long i = ((long)z * np1 + y) * np0 + x;
+            const int cx = tx + 3, cy = ty + 3;
+            double M[3][3];
 #pragma unroll
-        for (int k = 0; k < 3; k++)
+            for (int j = 0; j < 3; j++) {
+                // k = 0 (a = 1, b = 2): delta_2 Pr[1][j] - delta_1 Pr[2][j]
+                const double* r1 = ring[3 + j];
+                const double t1 = cdiff(al, r1[4], r1[2], r1[5], r1[1], r1[6], r1[0]);
+                const double t2 = cdiff(al, T[6 + j][cy + 1][cx], T[6 + j][cy - 1][cx], T[6 + j][cy + 2][cx],
+                                        T[6 + j][cy - 2][cx], T[6 + j][cy + 3][cx], T[6 + j][cy - 3][cx]);
+                M[0][j] = (t1 - t2) * s12;
+                // k = 1 (a = 2, b = 0): delta_0 Pr[2][j] - delta_2 Pr[0][j]
+                const double* r0 = ring[j];
+                const double u1 = cdiff(al, T[6 + j][cy][cx + 1], T[6 + j][cy][cx - 1], T[6 + j][cy][cx + 2],
+                                        T[6 + j][cy][cx - 2], T[6 + j][cy][cx + 3], T[6 + j][cy][cx - 3]);
+                const double u2 = cdiff(al, r0[4], r0[2], r0[5], r0[1], r0[6], r0[0]);
+                M[1][j] = (u1 - u2) * s20;
+                // k = 2 (a = 0, b = 1): delta_1 Pr[0][j] - delta_0 Pr[1][j]
+                const double v1 = cdiff(al, T[j][cy + 1][cx], T[j][cy - 1][cx], T[j][cy + 2][cx],
+                                        T[j][cy - 2][cx], T[j][cy + 3][cx], T[j][cy - 3][cx]);
+                const double v2 = cdiff(al, T[3 + j][cy][cx + 1], T[3 + j][cy][cx - 1], T[3 + j][cy][cx + 2],
+                                        T[3 + j][cy][cx - 2], T[3 + j][cy][cx + 3], T[3 + j][cy][cx - 3]);
+                M[2][j] = (v1 - v2) * s01;
+            }
 #pragma unroll
-            for (int j = 0; j < 3; j++) jxx[(k * 3 + j) * P + i] = M[k][j];
-        if (jxt) {
+            for (int k = 0; k < 3; k++)
 #pragma unroll
-            for (int k = 0; k < 3; k++) {
-                double nt = 0.0;
+                for (int j = 0; j < 3; j++) jxx[(k * 3 + j) * P + i] = M[k][j];
+            if (jxt) {
+                double w[3] = {0.0, 0.0, 0.0};
                 if (disp && dt > 0.0)
 #pragma unroll
-                    for (int j = 0; j < 3; j++) nt -= (disp[j * P + i] / dt) * M[k][j];
-                jxt[k * P + i] = nt;
+                    for (int j = 0; j < 3; j++) w[j] = disp[j * P + i] / dt;
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    double nt = 0.0;
+#pragma unroll
+                    for (int j = 0; j < 3; j++) nt -= w[j] * M[k][j];
+                    jxt[k * P + i] = nt;
+                }
             }
         }
+        __syncthreads();
     }
 }
 
@@ -286,8 +398,18 @@ hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double*
         hipLaunchKernelGGL(k_metric2, dim3(grid_for(nint)), dim3(256), 0, s, g, ph, xn, disp, cs, dt_dev,
                            jxx, jxt);
     } else {
-        hipLaunchKernelGGL(k_metric_prod3, dim3(grid_for(g.P)), dim3(256), 0, s, g, ph, xn, disp, cs, G);
-        hipLaunchKernelGGL(k_metric3, dim3(grid_for(nint)), dim3(256), 0, s, g, ph, disp, G, dt_dev, jxx, jxt);
+        // z chunks: enough blocks to fill the chip, chunks long against the
+        // 6-plane ring start-up
+        const int bx1 = (g.np[0] + MT - 1) / MT, by1 = (g.np[1] + MT - 1) / MT;
+        const int nc1 = std::max(1, std::min(g.np[2] / 32, (1024 + bx1 * by1 - 1) / (bx1 * by1)));
+        const int zc1 = (g.np[2] + nc1 - 1) / nc1;
+        hipLaunchKernelGGL(k_metric_prod3, dim3(bx1, by1, (g.np[2] + zc1 - 1) / zc1), dim3(MT, MT), 0, s,
+                           g, ph, xn, disp, cs, G, zc1);
+        const int bx2 = (g.n[0] + MT - 1) / MT, by2 = (g.n[1] + MT - 1) / MT;
+        const int nc2 = std::max(1, std::min(g.n[2] / 16, (4096 + bx2 * by2 - 1) / (bx2 * by2)));
+        const int zc2 = (g.n[2] + nc2 - 1) / nc2;
+        hipLaunchKernelGGL(k_metric3, dim3(bx2, by2, (g.n[2] + zc2 - 1) / zc2), dim3(MT, MT), 0, s, g, ph,
+                           disp, G, dt_dev, jxx, jxt, zc2);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
