@@ -114,34 +114,16 @@ def run_stage_only(ctx, mon, cfl, gU, gJ, gx, dt_dev, reps):
     print(json.dumps({"mode": "stage", "reps": reps, "copy_bytes_each_way": a.numel() * 8}), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--stage-reps", type=int, default=10)
-    ap.add_argument("--mode", choices=["step", "stage"], default="step",
-                    help="stage: only the fused-RK-stage loop and a 2 GiB device copy (for "
-                         "rocprofv3 counter runs; the copy calibrates FETCH_SIZE/WRITE_SIZE)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
-              "multi-GPU path", file=sys.stderr)
-        sys.exit(2)
-
+def run_precision(args, prec_name, n, steps, warmup, stage_reps):
+    """Time whole steps and the fused stage of one precision; returns a dict."""
     import numpy as np
     import torch
 
     from paper_2202_07989_amd import es
     from paper_2202_07989_amd import inputs as I
 
-    torch.cuda.set_device(0)
-    n = args.n
     sp = I.spec_c3(n)
-    prec = es.ES_MIXED if args.precision == "mixed" else es.ES_FP64
+    prec = es.ES_MIXED if prec_name == "mixed" else es.ES_FP64
     JU, J, x = I.init_shock_bubble(sp)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     gU, gJ, gx = dev(JU), dev(J), dev(x)
@@ -157,21 +139,18 @@ def main():
         ctx.es_entropy(gU, gJ, ent)
 
     stream = torch.cuda.current_stream()
-    if args.mode == "stage":
-        run_stage_only(ctx, mon, cfl, gU, gJ, gx, dt_dev, args.stage_reps)
-        return
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     wall0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    ms_step = e0.elapsed_time(e1) / args.steps
+    ms_step = e0.elapsed_time(e1) / steps
     rc, flags = ctx.es_status()
     cells = n ** 3
     value = cells * 3 / (ms_step / 1e3)
@@ -183,46 +162,193 @@ def main():
     torch.cuda.synchronize()
     s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     s0.record(stream)
-    for _ in range(args.stage_reps):
+    for _ in range(stage_reps):
         ctx.es_rk_stage(1, dt_dev, JUn, Jn, gU, gJ, jx, jt, JUo, Jo)
     s1.record(stream)
     torch.cuda.synchronize()
-    ms_stage = s0.elapsed_time(s1) / args.stage_reps
+    ms_stage = s0.elapsed_time(s1) / stage_reps
     key = (3, 2)
-    flops = FLOPS_PER_CELL_STAGE[key] * cells
-    achieved = flops / (ms_stage / 1e3) / 1e12
+    achieved = FLOPS_PER_CELL_STAGE[key] * cells / (ms_stage / 1e3) / 1e12
     peak = PEAK_FP64_TFLOPS if prec == es.ES_FP64 else PEAK_FP32_TFLOPS
-    traffic = load_traffic()
     hbm_gbs = BYTES_PER_CELL_STAGE[key] * cells / (ms_stage / 1e3) / 1e9
+    del ctx
+    torch.cuda.empty_cache()
+    return dict(value=value, ms_step=ms_step, wall=wall, status=rc, ms_stage=ms_stage,
+                achieved=achieved, peak=peak, hbm_gbs=hbm_gbs, sp=sp, JU=JU, J=J, x=x)
 
+
+def accuracy_study(args):
+    """FP64 and mixed GPU runs of the same workload side by side: per
+    component of U = JU/J and for rho and p, l1 = mean|a-b|/mean|b| and
+    linf = max|a-b|/max|b| over the interior after --steps steps (mixed vs
+    FP64 GPU), and, when --oracle-ref names a file written by the oracle's
+    reference script, both GPU runs against the FP64 oracle on its
+    subsample of nodes."""
+    import numpy as np
+    import torch
+
+    from paper_2202_07989_amd import es
+    from paper_2202_07989_amd import inputs as I
+
+    n = args.n
+    sp = I.spec_c3(n)
+    ng = sp["ng"]
+    N = sp["nspec"]
+    JU, J, x = I.init_shock_bubble(sp)
+    mon = I.monitor_spec(n_sweeps=5, n_smooth=3, sigma=(0,), alpha=(1200.0,))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    inner = (slice(None),) + tuple(slice(ng, ng + n) for _ in range(3))
+    cv = [float(c) for c in sp["cv"][:N]]
+    Rg = [float(c) * (float(g) - 1.0) for c, g in zip(sp["cv"][:N], sp["gamma"][:N])]
+    pinf_tot = float(sum(sp["pinf"][:N]))
+
+    def prims(U):
+        """rho and p of conserved states U (components first), stiffened EOS."""
+        rho = sum(U[l] for l in range(N))
+        kin = 0.5 * sum(U[N + j] ** 2 for j in range(3)) / rho
+        cvr = sum(cv[l] * U[l] for l in range(N))
+        T = (U[N + 3] - kin - pinf_tot) / cvr
+        p = sum(Rg[l] * U[l] for l in range(N)) * T - pinf_tot
+        return rho, p
+
+    finals, dts = {}, {}
+    for prec_name, prec in (("fp64", es.ES_FP64), ("mixed", es.ES_MIXED)):
+        ctx = es.Context(sp, precision=prec)
+        gU, gJ, gx = dev(JU), dev(J), dev(x)
+        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        seq = []
+        for s in range(args.steps):
+            ctx.es_step(gU, gJ, gx, mon=mon, cfl=0.3, move_mesh=True, dt_dev=dt_dev)
+            seq.append(dt_dev)
+            dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        rc, _ = ctx.es_status()
+        print(json.dumps({"accuracy_run": prec_name, "steps": args.steps, "status": rc}), flush=True)
+        dts[prec_name] = torch.cat(seq).cpu().numpy()
+        finals[prec_name] = (gU[inner].contiguous(), gJ[inner].contiguous())
+        del ctx, gx
+        torch.cuda.empty_cache()
+
+    def fields(JUi, Ji):
+        U = JUi / Ji
+        rho, p = prims(U)
+        return [U[c] for c in range(U.shape[0])] + [rho, p]
+
+    names = [f"U{c}" for c in range(N + 4)] + ["rho", "p"]
+    a = fields(*finals["mixed"])
+    b = fields(*finals["fp64"])
+    mixed_vs_fp64 = {nm: {"l1": float((x_ - y_).abs().mean() / y_.abs().mean()),
+                          "linf": float((x_ - y_).abs().max() / y_.abs().max())}
+                     for nm, x_, y_ in zip(names, a, b)}
+    out = {"mode": "accuracy", "workload": f"3D two-species shock-bubble {n}^3, {args.steps} moving-mesh "
+           "steps (5 Jacobi sweeps, 3 filter passes, alpha 1200), CFL 0.3",
+           "mixed_vs_fp64_gpu": mixed_vs_fp64,
+           "dt_rel_diff_max": float(np.abs(dts["mixed"] - dts["fp64"]).max() / np.abs(dts["fp64"]).max())}
+    if args.oracle_ref:
+        ref = np.load(args.oracle_ref)
+        assert int(ref["n"]) == n and int(ref["step"]) == args.steps, "reference of another run"
+        s0, ss = int(ref["sub0"]), int(ref["substep"])
+        sub = (slice(None),) + tuple(slice(s0, None, ss) for _ in range(3))
+        rf = fields(torch.from_numpy(ref["JU"]).cuda(), torch.from_numpy(ref["J"]).cuda())
+        for prec_name in ("fp64", "mixed"):
+            JUi, Ji = finals[prec_name]
+            gf = fields(JUi[sub].contiguous(), Ji[sub].contiguous())
+            out[f"{prec_name}_gpu_vs_oracle_sampled"] = {
+                nm: {"l1": float((x_ - y_).abs().mean() / y_.abs().mean()),
+                     "linf": float((x_ - y_).abs().max() / y_.abs().max())}
+                for nm, x_, y_ in zip(names, gf, rf)}
+        out["oracle_sample"] = (f"every {ss}th interior node per direction from node {s0} "
+                                f"({rf[0].numel()} nodes)")
+        out["dt_rel_diff_vs_oracle_max"] = float(np.abs(dts["fp64"] - ref["dts"]).max()
+                                                 / np.abs(ref["dts"]).max())
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both",
+                    help="both: FP64 gives the reported value, the mixed form is timed beside it")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stage-reps", type=int, default=10)
+    ap.add_argument("--mode", choices=["step", "stage", "accuracy"], default="step",
+                    help="stage: only the fused-RK-stage loop and a 2 GiB device copy (for "
+                         "rocprofv3 counter runs; the copy calibrates FETCH_SIZE/WRITE_SIZE); "
+                         "accuracy: FP64 vs mixed (and vs an oracle reference file) after --steps steps")
+    ap.add_argument("--oracle-ref", default=None,
+                    help="accuracy mode: .npz written by the oracle's reference script")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2202_07989_amd import es
+    from paper_2202_07989_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    n = args.n
+    if args.mode == "accuracy":
+        accuracy_study(args)
+        return
+    if args.mode == "stage":
+        sp = I.spec_c3(n)
+        prec = es.ES_MIXED if args.precision == "mixed" else es.ES_FP64
+        JU, J, x = I.init_shock_bubble(sp)
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        gU, gJ, gx = dev(JU), dev(J), dev(x)
+        ctx = es.Context(sp, precision=prec)
+        mon = I.monitor_spec(n_sweeps=5, n_smooth=3, sigma=(0,), alpha=(1200.0,))
+        dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        run_stage_only(ctx, mon, 0.3, gU, gJ, gx, dt_dev, args.stage_reps)
+        return
+
+    main_prec = "mixed" if args.precision == "mixed" else "fp64"
+    r = run_precision(args, main_prec, n, args.steps, args.warmup, args.stage_reps)
+    traffic = load_traffic() if main_prec == "fp64" else None
+    cells = n ** 3
+    key = (3, 2)
     out = {
         "metric": "cell-stage updates/s, 3D 256^3 two-species, FP64 vs mixed FP32; % HBM peak",
-        "value": value,
+        "value": r["value"],
         "unit": "cell-stage updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == es.ES_FP64 else "f32+f64",
+        "dtype": "f64" if main_prec == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"3D two-species stiffened-gas shock-bubble {n}^3, moving mesh "
                                "(5 Jacobi sweeps, 3 filter passes, alpha 1200), CFL 0.3, "
                                "6th-order EC + MR-WENO5 ES flux, SSP-RK3",
-                   "grid": [n, n, n], "species": 2, "precision": args.precision},
-        "hbm_frac_of_peak_step": BYTES_PER_CELL_STAGE[key] * value / 1e9 / PEAK_HBM_GBS,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic,
+                   "grid": [n, n, n], "species": 2, "precision": main_prec},
+        "hbm_frac_of_peak_step": BYTES_PER_CELL_STAGE[key] * r["value"] / 1e9 / PEAK_HBM_GBS,
+        "roofline": {"bound": "alu", "achieved": r["achieved"], "peak": r["peak"], "unit": "TFLOP/s",
+                     "frac": r["achieved"] / r["peak"], "traffic": traffic,
                      "kernel": "es_rk_stage (k_rhs_dir x3 directions, fused stage epilogue)",
-                     "ms_per_launch": ms_stage, "algorithmic_hbm_GBs": hbm_gbs,
-                     "algorithmic_hbm_frac": hbm_gbs / PEAK_HBM_GBS},
-        "status": rc,
-        "wall_s": wall,
+                     "ms_per_launch": r["ms_stage"], "algorithmic_hbm_GBs": r["hbm_gbs"],
+                     "algorithmic_hbm_frac": r["hbm_gbs"] / PEAK_HBM_GBS},
+        "status": r["status"],
+        "wall_s": r["wall"],
     }
+    if args.precision == "both":
+        m = run_precision(args, "mixed", n, args.steps, args.warmup, args.stage_reps)
+        out["mixed"] = {"dtype": "f32+f64", "value": m["value"], "ms_per_step": m["ms_step"],
+                        "speedup_vs_fp64": m["value"] / r["value"],
+                        "stage_ms_per_launch": m["ms_stage"],
+                        "stage_achieved_TFLOPs": m["achieved"], "peak_fp32_TFLOPs": m["peak"],
+                        "stage_frac": m["achieved"] / m["peak"], "status": m["status"]}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sp, JU, J, x, n)
+        out["cpu_baseline"] = cpu_baseline(r["sp"], r["JU"], r["J"], r["x"], n)
     print(json.dumps(out), flush=True)
 
 

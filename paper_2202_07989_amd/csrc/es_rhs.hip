@@ -48,11 +48,13 @@ __device__ __forceinline__ void mixture(const Phys& ph, const NodeTile<N, D, NN>
 
 // two-point EC flux between tile nodes ia, ib (eq ECfluxMM), written in the
 // direction-generic form n_t Utilde + sum_j n_j Ftilde_j:
-//   M_l = {rho_l}^ln ({v}.n + n_t),  p^ = sum R_l {rho_l} / {beta} - p_inf,
+//   M_l = {rho_l}^ln ({v}.n + n_t),  p^ = Pi - p_inf with Pi = sum R_l {rho_l} / {beta},
 //   momentum = {v} sum M_l + p^ n,
-//   energy = sum M_l (c_vl/{beta}^ln - {|v|^2}/2) + {v}.momentum
-//            + p_inf ({v}.n + n_t),
-// with {|v|^2} the mean of squares.
+//   energy = sum M_l (c_vl/{beta}^ln - {|v|^2}/2) + |{v}|^2 sum M_l + Pi {v}.n + p_inf n_t,
+// with {|v|^2} the mean of squares.  The energy line is {v}.momentum +
+// p_inf ({v}.n + n_t) with the two p_inf {v}.n terms cancelled by hand, and
+// Pi is formed in FP64 in both precisions: with a stiffened gas Pi and
+// p_inf are both ~p_inf, so neither difference may be left to FP32.
 template <int N, int D, int NN, typename R>
 __device__ __forceinline__ void ec_pair(const Phys& ph, const NodeTile<N, D, NN>& S, int ia, int ib,
                                         R* F)
@@ -60,36 +62,39 @@ __device__ __forceinline__ void ec_pair(const Phys& ph, const NodeTile<N, D, NN>
     constexpr int NC = N + D + 1;
     const R nt = R(0.5) * (R(S.m[0][ia]) + R(S.m[0][ib]));
     R n[D], vm[D];
-    R vn = nt, v2 = R(0);
+    R vdn = R(0), v2 = R(0);
 #pragma unroll
     for (int j = 0; j < D; j++) {
         n[j] = R(0.5) * (R(S.m[1 + j][ia]) + R(S.m[1 + j][ib]));
         const R va = R(S.v[j][ia]), vb = R(S.v[j][ib]);
         vm[j] = R(0.5) * (va + vb);
         v2 += va * va + vb * vb;
-        vn += vm[j] * n[j];
+        vdn += vm[j] * n[j];
     }
     v2 *= R(0.5);
+    const R vn = vdn + nt;
     const R ibln = R(inv_logmean(S.b[ia], S.b[ib], S.lb[ia], S.lb[ib]));
-    const R bsum = R(S.b[ia]) + R(S.b[ib]);
-    R Mt = R(0), Rr = R(0), eng = R(0);
+    double Rr = 0.0;
+#pragma unroll
+    for (int l = 0; l < N; l++) Rr += ph.Rg[l] * (S.rho[l][ia] + S.rho[l][ib]);
+    const double Pi = Rr / (S.b[ia] + S.b[ib]);
+    const R phat = R(Pi - ph.pinf_tot);
+    R Mt = R(0), eng = R(0);
 #pragma unroll
     for (int l = 0; l < N; l++) {
         const R rln = R(logmean(S.rho[l][ia], S.rho[l][ib], S.lrho[l][ia], S.lrho[l][ib]));
         const R Ml = rln * vn;
         F[l] = Ml;
         Mt += Ml;
-        Rr += R(ph.Rg[l]) * (R(S.rho[l][ia]) + R(S.rho[l][ib]));
         eng += Ml * (R(ph.cv[l]) * ibln - R(0.5) * v2);
     }
-    const R phat = Rr / bsum - R(ph.pinf_tot);   // sum R_l {rho_l} / {beta} - p_inf
+    R vv = R(0);
 #pragma unroll
     for (int j = 0; j < D; j++) {
-        const R fm = vm[j] * Mt + phat * n[j];
-        F[N + j] = fm;
-        eng += vm[j] * fm;
+        F[N + j] = vm[j] * Mt + phat * n[j];
+        vv += vm[j] * vm[j];
     }
-    F[NC - 1] = eng + R(ph.pinf_tot) * vn;
+    F[NC - 1] = eng + vv * Mt + R(Pi) * vdn + R(ph.pinf_tot) * nt;
 }
 
 // ES dissipation 1/2 s T^T R Y [[W]]^WENO at the interface between tile

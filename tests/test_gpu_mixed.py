@@ -1,0 +1,118 @@
+"""Mixed-precision GPU path (ES_MIXED) against the CPU FP64 oracle.
+
+In ES_MIXED the state, mesh, metrics, node primitives, log means, the
+pressure average and every reduction stay FP64; the two-point fluxes, the
+frame, the projections, MR-WENO and the interface sums run in FP32.  The
+bar is the FP32 rounding of that arithmetic: an interface flux F is formed
+with relative error c u |F| (u = 2^-24, c a few tens of operations), and
+the node update differences two of them, so per component
+    max |gpu - oracle| / S_c  <=  TOL_MIXED = 2e-5
+with the same scale S_c = max|JU_c| * lambda as the FP64 bar (the flux
+magnitude per unit length is bounded by |U| times the wave speed)."""
+import numpy as np
+import pytest
+
+from paper_2202_07989_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_2202_07989_amd import es  # noqa: E402
+from gpu_util import dev, host, parity, rhs_scale, state_scale, say  # noqa: E402
+
+from cases import CASES, prepared  # noqa: E402
+
+TOL_MIXED = 2e-5
+
+
+def _rhs(ctx, JU, J, jx, jt):
+    gU, gJ = torch.zeros_like(dev(JU)), torch.zeros_like(dev(J))
+    ctx.es_rhs(dev(JU), dev(J), dev(jx), dev(jt), gU, gJ)
+    return host(gU), host(gJ)
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("dissipation", [1, 0])
+def test_rhs_mixed(name, dissipation):
+    say(f"[mixed rhs] {name} dissipation={dissipation}")
+    sp, o, JU, J, x, disp, jx, jt = prepared(name, dissipation)
+    rc, dU, dJ = o.rhs(JU, J, jx, jt)
+    assert rc == 0
+    _, lam, _ = o.max_wavespeed(JU, J, jx, 1.0)
+    ctx = es.Context(sp, precision=es.ES_MIXED)
+    hU, hJ = _rhs(ctx, JU, J, jx, jt)
+    Iin = I.interior(sp)
+    sU, sJ = rhs_scale(JU, J, lam, Iin, sp)
+    errs = [parity(hU[c][Iin[1:]], dU[c][Iin[1:]], sU[c]) for c in range(o.nc)]
+    say(f"    per-component error / S_c: {' '.join(f'{e:.1e}' for e in errs)}")
+    for c, e in enumerate(errs):
+        assert e <= TOL_MIXED, (name, c, e)
+    # dJ is the GCL term, FP64 in both paths
+    assert parity(hJ[Iin], dJ[Iin], sJ) <= 1e-11
+    assert ctx.es_status()[0] == es.ES_OK
+
+
+def test_mixed_really_rounds_in_fp32():
+    """The mixed path is not the FP64 path under another name: it differs
+    from the FP64 GPU result by more than FP64 rounding."""
+    sp, o, JU, J, x, disp, jx, jt = prepared("3d-n2-bubble")
+    h64, _ = _rhs(es.Context(sp), JU, J, jx, jt)
+    h32, _ = _rhs(es.Context(sp, precision=es.ES_MIXED), JU, J, jx, jt)
+    _, lam, _ = o.max_wavespeed(JU, J, jx, 1.0)
+    Iin = I.interior(sp)
+    sU, _ = rhs_scale(JU, J, lam, Iin, sp)
+    d = max(parity(h32[c][Iin[1:]], h64[c][Iin[1:]], sU[c]) for c in range(o.nc))
+    assert 1e-9 < d <= TOL_MIXED, d
+
+
+@pytest.mark.parametrize("name", ["2d-n2-bubble", "3d-n2-random"])
+def test_rk_stage_mixed(name):
+    say(f"[mixed rk stage] {name}")
+    sp, o, JU, J, x, disp, jx, jt = prepared(name)
+    _, lam, dt = o.max_wavespeed(JU, J, jx, 0.3)
+    rng = np.random.default_rng(5)
+    JUn = JU * (1 + 1e-3 * rng.uniform(-1, 1, JU.shape[1:]))[None]
+    Jn = J * (1 + 1e-3 * rng.uniform(-1, 1, J.shape[1:]))[None]
+    ctx = es.Context(sp, precision=es.ES_MIXED)
+    dt_dev = torch.tensor([dt], dtype=torch.float64, device="cuda")
+    Iin = I.interior(sp)
+    sc = state_scale(JU, sp, lam)
+    for stage in range(3):
+        rc, oU, oJ = o.rk_stage(stage, dt, JUn, Jn, JU, J, jx, jt)
+        gU, gJ = torch.zeros_like(dev(JU)), torch.zeros_like(dev(J))
+        ctx.es_rk_stage(stage, dt_dev, dev(JUn), dev(Jn), dev(JU), dev(J), dev(jx), dev(jt), gU, gJ)
+        hU, hJ = host(gU), host(gJ)
+        for c in range(o.nc):
+            # a stage adds dt L (dt lambda = CFL 0.3) to FP64 states
+            assert parity(hU[c][Iin[1:]], oU[c][Iin[1:]], sc[c]) <= 0.3 * TOL_MIXED, (stage, c)
+        assert parity(hJ[Iin], oJ[Iin], np.abs(J).max()) <= 1e-11
+
+
+@pytest.mark.parametrize("name,nsteps", [("2d-n2-bubble", 3), ("3d-n2-bubble", 2)])
+def test_step_mixed(name, nsteps):
+    """Whole moving-mesh steps: mesh adaptation, metrics and dt stay FP64;
+    each stage adds at most CFL * TOL_MIXED relative error."""
+    say(f"[mixed step] {name} steps={nsteps}")
+    sp, o, JU, J, x, disp, jx, jt = prepared(name)
+    mon = dict(sigma=[0], alpha=[1200.0], n_smooth=3, n_sweeps=5)
+    ctx = es.Context(sp, precision=es.ES_MIXED)
+    gU, gJ, gx = dev(JU), dev(J), dev(x)
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(nsteps):
+        rc, dt, tau = o.step(JU, J, x, mon=mon, cfl=0.3, move_mesh=True)
+        assert rc == 0
+        ctx.es_step(gU, gJ, gx, mon=mon, cfl=0.3, move_mesh=True, dt_dev=dt_dev)
+    hU, hx = host(gU), host(gx)
+    Iin = I.interior(sp)
+    _, lam, _ = o.max_wavespeed(JU, J, o.metrics(x)[0], 1.0)
+    sc = state_scale(JU, sp, lam)
+    errs = [parity(hU[c][Iin[1:]], JU[c][Iin[1:]], sc[c]) for c in range(o.nc)]
+    say(f"    state error / scale after {nsteps} steps: {' '.join(f'{e:.1e}' for e in errs)}")
+    for c, e in enumerate(errs):
+        assert e <= 3 * nsteps * 0.3 * TOL_MIXED, (c, e)
+    for c in range(sp["dim"]):
+        assert parity(hx[c], x[c], np.abs(x[c]).max()) <= 1e-6
+    assert ctx.es_status()[0] == es.ES_OK
