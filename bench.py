@@ -264,6 +264,123 @@ def accuracy_study(args):
     print(json.dumps(out), flush=True)
 
 
+def batch_study(args):
+    """The batched form: 64 independent 2D two-species instances of uneven
+    size (seeded, 128^2..1024^2, 4-quadrant Riemann data, fixed uniform
+    mesh, CFL 0.4 per instance).  One step is the per-instance wave speed and
+    three stages, one launch each, captured once in a hipGraph and replayed
+    --steps times; FP64 and mixed, after the autotuner has picked the region
+    size.  The same steps done instance by instance with the single-instance
+    calls (64 x (wave speed + 3 x (stage + 2 ghost fills))) are timed as the
+    unbatched baseline."""
+    import numpy as np
+    import torch
+
+    from paper_2202_07989_amd import es
+    from paper_2202_07989_amd import inputs as I
+
+    insts = I.init_c5(count=args.count)
+    cells = sum(sp["n"][0] * sp["n"][1] for sp, _, _, _ in insts)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    U0 = [dev(JU) for _, JU, _, _ in insts]
+    J0 = [dev(J) for _, _, J, _ in insts]
+    jx = []
+    for (sp, JU, J, x) in insts:
+        ctx = es.Context(sp)
+        gxm = dev(x)
+        ctx.es_fill_ghosts_x(gxm)
+        m = torch.empty((4,) + tuple(J.shape[1:]), dtype=torch.float64, device="cuda")
+        ctx.es_metrics(gxm, None, 0.0, None, m, None)
+        ctx.es_fill_ghosts(U0[len(jx)], sp["nspec"] + 3)
+        ctx.es_fill_ghosts(J0[len(jx)], 1)
+        jx.append(m)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    out = {"mode": "batch", "instances": len(insts), "cells": cells,
+           "sizes_min_max": [min(sp["n"][0] for sp, _, _, _ in insts), max(sp["n"][0] for sp, _, _, _ in insts)],
+           "steps": args.steps}
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for prec_name, prec in (("fp64", es.ES_FP64), ("mixed", es.ES_MIXED)):
+        b = es.Batch([sp for sp, _, _, _ in insts], precision=prec)
+        gU, gJ = [t.clone() for t in U0], [t.clone() for t in J0]
+        tU, tJ, tx = es.PtrTable(gU), es.PtrTable(gJ), es.PtrTable(jx)
+        dt = torch.zeros(len(insts), dtype=torch.float64, device="cuda")
+        b.max_wavespeed_batched(tU, tJ, tx, 0.4, None, dt)
+        region, pers = b.es_batch_autotune(tU, tJ, tx, None, dt, reps=3)
+        # one stage alone (the dominant kernel), timed on the stream it runs on
+        oU, oJ = es.PtrTable([torch.empty_like(t) for t in gU]), es.PtrTable([torch.empty_like(t) for t in gJ])
+        stage = lambda: b.es_rk_stage_batched(1, dt, tU, tJ, tU, tJ, tx, None, oU, oJ)
+        stage()
+        ms_stage = timed(stage, 10)
+        # whole steps through a graph
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            b.es_step_batched(0.4, tU, tJ, tx, None, dt)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        for a, c in zip(gU + gJ, U0 + J0):
+            a.copy_(c)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            b.es_step_batched(0.4, tU, tJ, tx, None, dt)
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, c in zip(gU + gJ, U0 + J0):
+            a.copy_(c)
+        torch.cuda.synchronize()
+        ms_step = timed(graph.replay, args.steps)
+        rc, _ = b.es_batch_status()
+        flops = FLOPS_PER_CELL_STAGE[(2, 2)] * cells / (ms_stage / 1e3) / 1e12
+        peak = PEAK_FP64_TFLOPS if prec == es.ES_FP64 else PEAK_FP32_TFLOPS
+        out[prec_name] = {"value": cells * 3 / (ms_step / 1e3), "unit": "cell-stage updates/s",
+                          "ms_per_step": ms_step, "stage_ms": ms_stage, "region": region,
+                          "persistent": pers, "stage_achieved_TFLOPs": flops, "peak_TFLOPs": peak,
+                          "stage_frac": flops / peak,
+                          "stage_algorithmic_hbm_frac": BYTES_PER_CELL_STAGE[(2, 2)] * cells
+                          / (ms_stage / 1e3) / 1e9 / PEAK_HBM_GBS,
+                          "status": rc}
+        del graph, b
+        torch.cuda.empty_cache()
+
+    # unbatched baseline: the same FP64 steps, instance by instance
+    ctxs = [es.Context(sp) for sp, _, _, _ in insts]
+    gU, gJ = [t.clone() for t in U0], [t.clone() for t in J0]
+    bufs = [[torch.empty_like(u), torch.empty_like(j), torch.empty_like(u), torch.empty_like(j)]
+            for u, j in zip(gU, gJ)]
+    dts = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in insts]
+
+    def seq_step():
+        for k, c in enumerate(ctxs):
+            c.max_wavespeed(gU[k], gJ[k], jx[k], 0.4, None, dts[k])
+            A, AJ, B, BJ = bufs[k]
+            for st, (sU, sJ, oU_, oJ_) in enumerate(((gU[k], gJ[k], A, AJ), (A, AJ, B, BJ), (B, BJ, A, AJ))):
+                c.es_rk_stage(st, dts[k], gU[k], gJ[k], sU, sJ, jx[k], None, oU_, oJ_)
+                c.es_fill_ghosts(oU_, 5)
+                c.es_fill_ghosts(oJ_, 1)
+            gU[k].copy_(A)
+            gJ[k].copy_(AJ)
+
+    seq_step()
+    torch.cuda.synchronize()
+    ms_seq = timed(seq_step, max(1, args.steps // 4))
+    out["fp64_sequential"] = {"value": cells * 3 / (ms_seq / 1e3), "ms_per_step": ms_seq,
+                              "note": "per instance: max_wavespeed, 3 x (es_rk_stage + 2 ghost fills), "
+                                      "state copy; not graph-captured"}
+    out["batched_speedup_vs_sequential"] = out["fp64"]["value"] / out["fp64_sequential"]["value"]
+    out["mixed_speedup_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,10 +391,12 @@ def main():
                     help="both: FP64 gives the reported value, the mixed form is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=10)
-    ap.add_argument("--mode", choices=["step", "stage", "accuracy"], default="step",
+    ap.add_argument("--mode", choices=["step", "stage", "accuracy", "batch"], default="step",
                     help="stage: only the fused-RK-stage loop and a 2 GiB device copy (for "
                          "rocprofv3 counter runs; the copy calibrates FETCH_SIZE/WRITE_SIZE); "
-                         "accuracy: FP64 vs mixed (and vs an oracle reference file) after --steps steps")
+                         "accuracy: FP64 vs mixed (and vs an oracle reference file) after --steps steps; "
+                         "batch: the 64-instance batched 2D form, FP64 and mixed, vs sequential launches")
+    ap.add_argument("--count", type=int, default=64, help="batch mode: number of instances")
     ap.add_argument("--oracle-ref", default=None,
                     help="accuracy mode: .npz written by the oracle's reference script")
     args = ap.parse_args()
@@ -296,6 +415,9 @@ def main():
     n = args.n
     if args.mode == "accuracy":
         accuracy_study(args)
+        return
+    if args.mode == "batch":
+        batch_study(args)
         return
     if args.mode == "stage":
         sp = I.spec_c3(n)

@@ -167,6 +167,81 @@ int es_status(es_ctx *c, void *stream, unsigned *flags, int reset);
 /* Number of padded points P of the context's grid. */
 long es_npoints(const es_ctx *c);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent 2D instances of uneven size advanced together,
+ * one launch per SSP-RK3 stage.  Each instance is the scheme above on its
+ * own periodic grid (its own n, dxi, len); all share nspec, ng, w, the
+ * species (gamma, cv, p_inf), chi, weno_eps, dissipation and precision.
+ *
+ * Per-instance arrays keep the single-instance layouts.  A batched call
+ * takes, per argument, a device array of `count` device pointers (entry b
+ * for instance b), so a captured graph can be replayed with the same
+ * arguments; the tables and the arrays they point to stay caller-owned and
+ * must outlive any graph that captured the call.  dt_dev / lambda_dev hold
+ * one value per instance.
+ * ------------------------------------------------------------------------ */
+typedef struct es_batch es_batch;
+
+/* Check the grids (dim must be 2; every field of es_grid that is not an
+ * extent, spacing or length must agree with grids[0]) and allocate the
+ * batch: work lists of three region sizes (10, 15, 21 nodes square), the
+ * wave-speed partials and two stage buffers per instance for
+ * es_step_batched.  The region size defaults to 15, persistent grid. */
+int es_batch_create(const es_grid *grids, int count, es_batch **out);
+int es_batch_destroy(es_batch *b);
+
+typedef struct {
+    const double *const *JU_n;   /* Q_n (state at t_n)                         */
+    const double *const *J_n;
+    const double *const *JU_s;   /* Q_s (stage input), ghost layers filled     */
+    const double *const *J_s;
+    const double *const *jxi_x;  /* metrics of the (fixed) mesh, ghosts filled */
+    const double *const *jxi_t;  /* NULL table: J dxi_k/dt = 0                  */
+    double *const *JU_out;       /* Q_{s+1}                                    */
+    double *const *J_out;
+} es_batch_stage_args;
+
+/* Stage `stage` of Section 5 for every instance (es_rk_stage per instance,
+ * with dt_dev[b]).  Writes every interior node of JU_out/J_out and its
+ * periodic ghost images, so the output can feed the next stage directly.
+ * JU_out/J_out may be the JU_n/J_n arrays (each node's Q_n is read by the
+ * thread that then overwrites it) but must not be JU_s/J_s (ES_EINVAL when
+ * the tables are the same). */
+int es_rk_stage_batched(es_batch *b, int stage, const double *dt_dev,
+                        const es_batch_stage_args *a, void *stream);
+
+/* Per-instance CFL wave speed and dt_dev[b] = cfl / lambda_b (eq cfl);
+ * lambda_dev may be NULL. */
+int max_wavespeed_batched(es_batch *b, const double *const *JU,
+                          const double *const *J, const double *const *jxi_x,
+                          double cfl, double *lambda_dev, double *dt_dev,
+                          void *stream);
+
+/* One fixed-mesh step of every instance: dt_dev[b] from
+ * max_wavespeed_batched, then the three stages (buffers owned by the
+ * batch); JU, J are advanced in place, ghost layers included.  Four
+ * launches plus one wave-speed reduction; nothing synchronises the host, so
+ * the call can be captured in a graph. */
+int es_step_batched(es_batch *b, double cfl, double *const *JU,
+                    double *const *J, const double *const *jxi_x,
+                    const double *const *jxi_t, double *dt_dev, void *stream);
+
+/* Autotuner: times stage 0 (output into the batch's own buffers) `reps`
+ * times for every region size (10, 15, 21) with a persistent grid and with
+ * one block per region, keeps the fastest, and returns it in
+ * region_out[0] (size) and region_out[1] (1 = persistent).  Synchronises
+ * the stream; call it before capturing a graph. */
+int es_batch_autotune(es_batch *b, const double *const *JU,
+                      const double *const *J, const double *const *jxi_x,
+                      const double *const *jxi_t, const double *dt_dev,
+                      int reps, void *stream, int *region_out);
+
+/* Select a region size (10, 15 or 21) and grid kind by hand. */
+int es_batch_set_tiling(es_batch *b, int region, int persistent);
+
+/* es_status for the batch's status word. */
+int es_batch_status(es_batch *b, void *stream, unsigned *flags, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libes.so")
-SOURCES = ["es_api.hip", "es_rhs.hip", "es_kernels.hip"]
+SOURCES = ["es_api.hip", "es_rhs.hip", "es_kernels.hip", "es_batch.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

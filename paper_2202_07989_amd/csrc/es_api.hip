@@ -4,6 +4,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/es.h"
 #include "es_kernels.hpp"
@@ -25,6 +26,34 @@ struct es_ctx {
     int mesh_nsig = 0;
     double *JUn = nullptr, *Jn = nullptr, *bufA = nullptr, *bufB = nullptr;
     double *jxx = nullptr, *jxt = nullptr, *disp = nullptr;
+};
+
+// a batch of independent 2D instances advanced together
+struct es_batch {
+    int count = 0;
+    es_grid grid0{};              // shared physics and scheme (instance 0's grid)
+    Phys ph{};
+    int device = 0;
+    int ncu = 0;
+    std::vector<Geo> geo_h;
+    Geo* geos = nullptr;          // device copy of geo_h
+    unsigned* status = nullptr;
+    // work lists of the batched stage, one per region size
+    static constexpr int NVAR = 3;
+    int T[NVAR] = {10, 15, 21};
+    int4* tiles[NVAR] = {nullptr, nullptr, nullptr};
+    int ntiles[NVAR] = {0, 0, 0};
+    int occ[NVAR] = {0, 0, 0};    // resident blocks per CU
+    int var = 1;                  // chosen region size (index into T)
+    int persistent = 1;           // grid = resident capacity (1) or one block per region (0)
+    // wave-speed work list and partials
+    int4* wl = nullptr;
+    int nwl = 0;
+    int* wfirst = nullptr;
+    double* part = nullptr;
+    // es_step_batched workspace: two stage buffers per instance and their tables
+    double* ws = nullptr;
+    double** tab = nullptr;       // 4 device tables of count pointers: A_U, A_J, B_U, B_J
 };
 
 namespace {
@@ -370,6 +399,268 @@ int es_status(es_ctx* c, void* stream, unsigned* flags, int reset)
     if (hipStreamSynchronize(s) != hipSuccess) return ES_EHIP;
     if (reset) {
         if (hipMemsetAsync(c->status, 0, sizeof(unsigned), s) != hipSuccess) return ES_EHIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return ES_EHIP;
+    }
+    if (flags) *flags = h;
+    if (h & ES_ST_NONPHYS) return ES_ENONPHYS;
+    if (h & ES_ST_TANGLE) return ES_ETANGLE;
+    return ES_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched 2D instances
+// ---------------------------------------------------------------------------
+namespace {
+
+bool same_scheme(const es_grid& a, const es_grid& b)
+{
+    if (a.dim != b.dim || a.nspec != b.nspec || a.ng != b.ng || a.w != b.w || a.precision != b.precision ||
+        a.dissipation != b.dissipation || a.weno_eps != b.weno_eps)
+        return false;
+    for (int l = 0; l < a.nspec; l++)
+        if (a.gamma[l] != b.gamma[l] || a.cv[l] != b.cv[l] || a.pinf[l] != b.pinf[l]) return false;
+    for (int m = 0; m < 3; m++)
+        if (a.chi[m] != b.chi[m]) return false;
+    return true;
+}
+
+BatchTiling batch_tiling(const es_batch* b)
+{
+    BatchTiling tl{};
+    tl.T = b->T[b->var];
+    tl.tiles = b->tiles[b->var];
+    tl.ntiles = b->ntiles[b->var];
+    const long cap = (long)b->occ[b->var] * b->ncu;
+    tl.blocks = (b->persistent && cap > 0 && cap < tl.ntiles) ? (int)cap : tl.ntiles;
+    return tl;
+}
+
+int batch_stage(es_batch* b, int stage, const double* dt_dev, const BatchTables& tb, hipStream_t s)
+{
+    static const double A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
+    static const double B[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
+    return hip_rc(launch_stage_batched(b->ph, b->geos, b->grid0.precision == ES_MIXED, batch_tiling(b), tb,
+                                       A[stage], B[stage], dt_dev, b->status, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+int es_batch_create(const es_grid* grids, int count, es_batch** out)
+{
+    if (!out) return ES_EINVAL;
+    *out = nullptr;
+    if (!grids || count < 1) return ES_EINVAL;
+    for (int i = 0; i < count; i++) {
+        const int rc = check_grid(&grids[i]);
+        if (rc) return rc;
+        if (grids[i].dim != 2) return ES_EUNSUPPORTED;
+        if (!same_scheme(grids[0], grids[i])) return ES_EINVAL;
+    }
+    es_batch* b = new (std::nothrow) es_batch();
+    if (!b) return ES_EHIP;
+    b->count = count;
+    b->grid0 = grids[0];
+    Geo g0;
+    build_params(&grids[0], b->ph, g0);
+    b->geo_h.resize(count);
+    size_t ws_doubles = 0;
+    const int nc = b->ph.nc;
+    for (int i = 0; i < count; i++) {
+        Phys ph;
+        build_params(&grids[i], ph, b->geo_h[i]);
+        ws_doubles += 2 * (size_t)(nc + 1) * b->geo_h[i].P;
+    }
+    int rc = ES_OK;
+    if (hipGetDevice(&b->device) != hipSuccess ||
+        hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
+        rc = ES_EHIP;
+    if (!rc) rc = dalloc(&b->geos, count);
+    if (!rc) rc = dalloc(&b->status, 4);
+    if (!rc && hipMemcpy(b->geos, b->geo_h.data(), count * sizeof(Geo), hipMemcpyHostToDevice) != hipSuccess)
+        rc = ES_EHIP;
+    if (!rc && hipMemset(b->status, 0, 4 * sizeof(unsigned)) != hipSuccess) rc = ES_EHIP;
+    // region work lists
+    for (int v = 0; v < es_batch::NVAR && !rc; v++) {
+        const int T = b->T[v];
+        std::vector<int4> tl;
+        for (int i = 0; i < count; i++)
+            for (int oy = 0; oy < b->geo_h[i].n[1]; oy += T)
+                for (int ox = 0; ox < b->geo_h[i].n[0]; ox += T) tl.push_back(make_int4(i, ox, oy, 0));
+        b->ntiles[v] = (int)tl.size();
+        rc = dalloc(&b->tiles[v], tl.size());
+        if (!rc && hipMemcpy(b->tiles[v], tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
+            rc = ES_EHIP;
+        if (!rc && batch_occupancy(b->ph.nspec, b->grid0.precision == ES_MIXED, T, &b->occ[v]) != hipSuccess)
+            rc = ES_EHIP;
+    }
+    // wave-speed work list: blocks of about 4096 nodes
+    if (!rc) {
+        std::vector<int4> wl;
+        std::vector<int> first(count + 1, 0);
+        for (int i = 0; i < count; i++) {
+            const int n0 = b->geo_h[i].n[0], n1 = b->geo_h[i].n[1];
+            const int rows = std::max(1, 4096 / n0);
+            first[i] = (int)wl.size();
+            for (int j = 0; j < n1; j += rows) wl.push_back(make_int4(i, j, std::min(n1, j + rows), 0));
+        }
+        first[count] = (int)wl.size();
+        b->nwl = (int)wl.size();
+        rc = dalloc(&b->wl, wl.size());
+        if (!rc) rc = dalloc(&b->wfirst, first.size());
+        if (!rc) rc = dalloc(&b->part, wl.size());
+        if (!rc && (hipMemcpy(b->wl, wl.data(), wl.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(b->wfirst, first.data(), first.size() * sizeof(int), hipMemcpyHostToDevice) !=
+                        hipSuccess))
+            rc = ES_EHIP;
+    }
+    // step workspace and its pointer tables
+    if (!rc) rc = dalloc(&b->ws, ws_doubles);
+    if (!rc) rc = dalloc(&b->tab, 4 * (size_t)count);
+    if (!rc) {
+        std::vector<double*> t(4 * (size_t)count);
+        double* p = b->ws;
+        for (int i = 0; i < count; i++) {
+            const size_t P = b->geo_h[i].P;
+            t[0 * count + i] = p;
+            t[1 * count + i] = p + nc * P;
+            p += (nc + 1) * P;
+            t[2 * count + i] = p;
+            t[3 * count + i] = p + nc * P;
+            p += (nc + 1) * P;
+        }
+        if (hipMemcpy(b->tab, t.data(), t.size() * sizeof(double*), hipMemcpyHostToDevice) != hipSuccess)
+            rc = ES_EHIP;
+    }
+    if (rc) {
+        es_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return ES_OK;
+}
+
+int es_batch_destroy(es_batch* b)
+{
+    if (!b) return ES_EINVAL;
+    void* bufs[] = {b->geos, b->status, b->wl, b->wfirst, b->part, b->ws, b->tab,
+                    b->tiles[0], b->tiles[1], b->tiles[2]};
+    for (void* p : bufs)
+        if (p) (void)hipFree(p);
+    delete b;
+    return ES_OK;
+}
+
+int max_wavespeed_batched(es_batch* b, const double* const* JU, const double* const* J,
+                          const double* const* jxi_x, double cfl, double* lambda_dev, double* dt_dev,
+                          void* stream)
+{
+    if (!b || !JU || !J || !jxi_x || !dt_dev || !(cfl > 0.0)) return ES_EINVAL;
+    return hip_rc(wavespeed_batched(b->ph, b->geos, b->wl, b->nwl, b->wfirst, b->count, JU, J, jxi_x, cfl,
+                                    b->part, lambda_dev, dt_dev, b->status, S(stream)));
+}
+
+int es_rk_stage_batched(es_batch* b, int stage, const double* dt_dev, const es_batch_stage_args* a,
+                        void* stream)
+{
+    if (!b || !a || stage < 0 || stage > 2 || !dt_dev || !a->JU_n || !a->J_n || !a->JU_s || !a->J_s ||
+        !a->jxi_x || !a->JU_out || !a->J_out)
+        return ES_EINVAL;
+    if ((const void*)a->JU_out == (const void*)a->JU_s || (const void*)a->J_out == (const void*)a->J_s)
+        return ES_EINVAL;
+    BatchTables tb{a->JU_n, a->J_n, a->JU_s, a->J_s, a->jxi_x, a->jxi_t, a->JU_out, a->J_out};
+    return batch_stage(b, stage, dt_dev, tb, S(stream));
+}
+
+int es_step_batched(es_batch* b, double cfl, double* const* JU, double* const* J,
+                    const double* const* jxi_x, const double* const* jxi_t, double* dt_dev, void* stream)
+{
+    if (!b || !JU || !J || !jxi_x || !dt_dev || !(cfl > 0.0)) return ES_EINVAL;
+    hipStream_t s = S(stream);
+    const int n = b->count;
+    const double* const* cU = JU;
+    const double* const* cJ = J;
+    double* const* AU = b->tab;
+    double* const* AJ = b->tab + n;
+    double* const* BU = b->tab + 2 * n;
+    double* const* BJ = b->tab + 3 * n;
+    int rc = max_wavespeed_batched(b, cU, cJ, jxi_x, cfl, nullptr, dt_dev, stream);
+    if (rc) return rc;
+    // Q1 = Qn + dt L(Qn); Q2 = 3/4 Qn + 1/4 (Q1 + dt L(Q1)); Qn+1 = 1/3 Qn + 2/3 (Q2 + dt L(Q2)),
+    // the last written over Qn (each node's Qn is read by the thread that overwrites it)
+    rc = batch_stage(b, 0, dt_dev, BatchTables{cU, cJ, cU, cJ, jxi_x, jxi_t, AU, AJ}, s);
+    if (!rc) rc = batch_stage(b, 1, dt_dev, BatchTables{cU, cJ, AU, AJ, jxi_x, jxi_t, BU, BJ}, s);
+    if (!rc) rc = batch_stage(b, 2, dt_dev, BatchTables{cU, cJ, BU, BJ, jxi_x, jxi_t, JU, J}, s);
+    return rc;
+}
+
+int es_batch_autotune(es_batch* b, const double* const* JU, const double* const* J,
+                      const double* const* jxi_x, const double* const* jxi_t, const double* dt_dev,
+                      int reps, void* stream, int* region_out)
+{
+    if (!b || !JU || !J || !jxi_x || !dt_dev || reps < 1) return ES_EINVAL;
+    hipStream_t s = S(stream);
+    const int n = b->count;
+    BatchTables tb{JU, J, JU, J, jxi_x, jxi_t, b->tab, b->tab + n};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return ES_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return ES_EHIP; }
+    float best = 1e30f;
+    int best_var = b->var, best_pers = b->persistent;
+    int rc = ES_OK;
+    for (int v = 0; v < es_batch::NVAR && !rc; v++) {
+        for (int pers = 0; pers < 2 && !rc; pers++) {
+            b->var = v;
+            b->persistent = pers;
+            rc = batch_stage(b, 0, dt_dev, tb, s);                   // warm-up
+            if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = ES_EHIP;
+            for (int r = 0; r < reps && !rc; r++) rc = batch_stage(b, 0, dt_dev, tb, s);
+            if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = ES_EHIP;
+            if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = ES_EHIP;
+            float ms = 0.0f;
+            if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = ES_EHIP;
+            if (!rc && ms < best) {
+                best = ms;
+                best_var = v;
+                best_pers = pers;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->var = best_var;
+    b->persistent = best_pers;
+    if (region_out) {
+        region_out[0] = b->T[best_var];
+        region_out[1] = best_pers;
+    }
+    return rc;
+}
+
+int es_batch_set_tiling(es_batch* b, int region, int persistent)
+{
+    if (!b) return ES_EINVAL;
+    for (int v = 0; v < es_batch::NVAR; v++)
+        if (b->T[v] == region) {
+            b->var = v;
+            b->persistent = persistent ? 1 : 0;
+            return ES_OK;
+        }
+    return ES_EINVAL;
+}
+
+int es_batch_status(es_batch* b, void* stream, unsigned* flags, int reset)
+{
+    if (!b) return ES_EINVAL;
+    hipStream_t s = S(stream);
+    unsigned h = 0;
+    if (hipMemcpyAsync(&h, b->status, sizeof(unsigned), hipMemcpyDeviceToHost, s) != hipSuccess) return ES_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return ES_EHIP;
+    if (reset) {
+        if (hipMemsetAsync(b->status, 0, sizeof(unsigned), s) != hipSuccess) return ES_EHIP;
         if (hipStreamSynchronize(s) != hipSuccess) return ES_EHIP;
     }
     if (flags) *flags = h;

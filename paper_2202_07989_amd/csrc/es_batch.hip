@@ -1,0 +1,206 @@
+// es_batch.hip -- one SSP-RK3 stage (Section 5) of many independent 2D
+// instances of uneven size in one persistent launch; each instance is the
+// semi-discrete scheme of Sections 3.1-3.4 on its own periodic grid.
+//
+// The work list holds square regions of T x T nodes of every instance.  A
+// block takes regions round-robin and, for each,
+//   - stages the node quantities of the region plus a 3-node halo along both
+//     directions (a plus-shaped patch) in LDS once,
+//   - sweeps direction 1 and then direction 2 over the patch with the
+//     interface-flux scheme of interface_fluxes() (the metrics of the sweep
+//     direction are reloaded between the sweeps), keeping each node's
+//     right-hand side in registers across the two sweeps,
+//   - writes the Shu-Osher combination to the node and to its periodic ghost
+//     images, so the next stage reads complete ghost layers with no fill.
+// A region's right-hand side depends only on its patch, so regions need no
+// ordering and the launch has no grid-wide synchronisation.
+#include "es_flux.hpp"
+
+namespace es {
+
+// the 10 x 10 region fits three waves per SIMD in registers without
+// spilling; the larger ones would spill and keep two
+template <int N, int T, int NT, typename R>
+__global__ void __launch_bounds__(NT, (T == 10 ? 3 : 2))
+k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict__ tiles, int ntiles,
+                  BatchTables tb, double ca, double cb, const double* __restrict__ dt_dev,
+                  unsigned* __restrict__ status)
+{
+    constexpr int D = 2;
+    constexpr int NC = N + D + 1;
+    constexpr int NE = T + 6;              // patch edge: region + 3-node halo on each side
+    constexpr int NN = NE * NE;
+    constexpr int NI = (T + 1) * T;        // interfaces of one sweep
+    constexpr int NS = T + 4;              // exchange slots per line
+    constexpr int NX = NS * T;
+    constexpr int NW = NT / 64;
+    static_assert(NI <= NT && 3 * T <= 64 && T * T <= NT && NT % 64 == 0, "region does not fit");
+    __shared__ NodeTile<N, D, NN> S;
+    __shared__ R X[NC][NX];
+
+    const int t = threadIdx.x;
+    auto lidx = [](int lx, int ly) { return lx + NE * ly; };
+    unsigned bad = 0;
+
+    for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
+        const int4 tw = tiles[w];
+        const int bi = tw.x, ox = tw.y, oy = tw.z;
+        const Geo g = geos[bi];
+        const long P = g.P;
+        const int nx = g.n[0], ny = g.n[1], np0 = g.np[0], ng = g.ng;
+        const double* __restrict__ JUs = tb.JUs[bi];
+        const double* __restrict__ Js = tb.Js[bi];
+        const double* __restrict__ jxx = tb.jxx[bi];
+        const double* __restrict__ jxt = tb.jxt ? tb.jxt[bi] : nullptr;
+        // interior coordinates (gx, gy) in [-ng, n + ng) -> padded index
+        auto gidx = [&](int gx, int gy) -> long { return (long)(gy + ng) * np0 + (gx + ng); };
+
+        // ---- node quantities of the plus-shaped patch ---------------------
+        for (int q = t; q < NN; q += NT) {
+            const int lx = q % NE, ly = q / NE;
+            const bool cx = lx >= 3 && lx < 3 + T, cy = ly >= 3 && ly < 3 + T;
+            if (!(cx || cy)) continue;                       // corners are never read
+            const int gx = ox + lx - 3, gy = oy + ly - 3;
+            if (gx >= nx + 3 || gy >= ny + 3) continue;      // beyond a ragged last region
+            bad |= node_state<N, D, NN>(ph, S, q, JUs, Js, P, gidx(gx, gy));
+        }
+
+        // node owned by this thread in the node phases
+        const int ni = t % T, nj = t / T;
+        double acc[NC], accJ = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) acc[cc] = 0.0;
+
+        auto sweep = [&](auto kc) {
+            constexpr int K = decltype(kc)::value;
+            // metrics of direction K on the lines of this sweep
+            for (int q = t; q < NE * T; q += NT) {
+                const int lx = (K == 0) ? q % NE : 3 + q % T;
+                const int ly = (K == 0) ? 3 + q / NE : q / T;
+                const int gx = ox + lx - 3, gy = oy + ly - 3;
+                if (gx >= nx + 3 || gy >= ny + 3) continue;
+                const long gi = gidx(gx, gy);
+                const int li = lidx(lx, ly);
+                S.m[0][li] = jxt ? jxt[(long)K * P + gi] : 0.0;
+#pragma unroll
+                for (int j = 0; j < D; j++) S.m[1 + j][li] = jxx[(long)(K * D + j) * P + gi];
+            }
+            __syncthreads();
+            // line c of the sweep is row oy + c (K = 0) or column ox + c (K = 1);
+            // node l of a line sits at patch along-coordinate l
+            auto tidx = [](int l, int c) { return (K == 0) ? (l + NE * (c + 3)) : ((c + 3) + NE * l); };
+            auto xidx = [](int s, int c) { return s + NS * c; };
+            const int nK = (K == 0) ? nx : ny, nL = (K == 0) ? ny : nx;
+            const int o_along = (K == 0) ? ox : oy, o_line = (K == 0) ? oy : ox;
+            const int fi = t % (T + 1), fc = t / (T + 1);
+            // the interface's right stencil node fi + 5 (patch coordinate) must be loaded
+            const bool f_ok = (t < NI) && (o_line + fc < nL) && (o_along + fi + 2 < nK + 3);
+            interface_fluxes<N, D, NN, T, T, R>(ph, S, X, tidx, xidx,
+                                                [&](int c) { return o_line + c < nL; }, fi, fc, f_ok,
+                                                t - (int)((blockIdx.x + w) % NW) * 64);
+            if (t < T * T) {
+                const int lo = (K == 0) ? ni : nj, c = (K == 0) ? nj : ni;
+                if (o_along + lo < nK && o_line + c < nL) {
+                    const int l = lo + 3;
+                    double gcl = 0.0;
+#pragma unroll
+                    for (int m = 1; m <= 3; m++)
+                        gcl += ph.alpha[m - 1] * (S.m[0][tidx(l + m, c)] - S.m[0][tidx(l - m, c)]);
+                    const double h = g.idxi[K];
+                    // each direction's term is rounded on its own before it is
+                    // added (separate statements, no fused multiply-add), as in
+                    // the single-instance sweeps
+                    const double dJ = -0.5 * gcl * h;
+                    accJ = accJ + dJ;
+#pragma unroll
+                    for (int cc = 0; cc < NC; cc++) {
+                        const double d = -(double)(X[cc][xidx(lo + 2, c)] - X[cc][xidx(lo + 1, c)]) * h;
+                        acc[cc] = acc[cc] + d;
+                    }
+                }
+            }
+            __syncthreads();   // S.m and X are reused by the next sweep / region
+        };
+        sweep(std::integral_constant<int, 0>{});
+        sweep(std::integral_constant<int, 1>{});
+
+        // ---- Shu-Osher combination, written to the node and its ghost images
+        if (t < T * T && ox + ni < nx && oy + nj < ny) {
+            const int gx = ox + ni, gy = oy + nj;
+            const long gi = gidx(gx, gy);
+            const double dt = dt_dev[bi];
+            const double* __restrict__ JUn = tb.JUn[bi];
+            const double* __restrict__ Jn = tb.Jn[bi];
+            double* __restrict__ JUo = tb.JUo[bi];
+            double* __restrict__ Jo = tb.Jo[bi];
+            double o[NC];
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) o[cc] = ca * JUn[cc * P + gi] + cb * (JUs[cc * P + gi] + dt * acc[cc]);
+            const double oJ = ca * Jn[gi] + cb * (Js[gi] + dt * accJ);
+#pragma unroll
+            for (int ky = -1; ky <= 1; ky++) {
+                const int yy = gy + ky * ny;
+                if (yy < -ng || yy >= ny + ng) continue;
+#pragma unroll
+                for (int kx = -1; kx <= 1; kx++) {
+                    const int xx = gx + kx * nx;
+                    if (xx < -ng || xx >= nx + ng) continue;
+                    const long gj = gidx(xx, yy);
+#pragma unroll
+                    for (int cc = 0; cc < NC; cc++) JUo[cc * P + gj] = o[cc];
+                    Jo[gj] = oJ;
+                }
+            }
+        }
+    }
+    if (bad) atomicOr(status, bad);
+}
+
+template <int N, typename R>
+static hipError_t launch_variant(int T, const Phys& ph, const Geo* geos, const BatchTiling& tl,
+                                 const BatchTables& tb, double ca, double cb, const double* dt_dev,
+                                 unsigned* status, hipStream_t s)
+{
+#define ES_BATCH_CASE(T_, NT_)                                                                       \
+    if (T == T_) {                                                                                   \
+        hipLaunchKernelGGL((k_stage2d_batched<N, T_, NT_, R>), dim3(tl.blocks), dim3(NT_), 0, s, ph, \
+                           geos, tl.tiles, tl.ntiles, tb, ca, cb, dt_dev, status);                   \
+        return hipGetLastError();                                                                    \
+    }
+    ES_BATCH_CASE(10, 128)
+    ES_BATCH_CASE(15, 256)
+    ES_BATCH_CASE(21, 512)
+#undef ES_BATCH_CASE
+    return hipErrorInvalidValue;
+}
+
+int batch_threads(int T) { return T == 10 ? 128 : (T == 15 ? 256 : (T == 21 ? 512 : 0)); }
+
+hipError_t batch_occupancy(int nspec, int mixed, int T, int* blocks_per_cu)
+{
+#define ES_OCC(N_, R_, T_, NT_)                                                                      \
+    if (nspec == N_ && (mixed != 0) == std::is_same<R_, float>::value && T == T_)                    \
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,                          \
+                                                            k_stage2d_batched<N_, T_, NT_, R_>,     \
+                                                            NT_, 0);
+    ES_OCC(1, double, 10, 128) ES_OCC(1, double, 15, 256) ES_OCC(1, double, 21, 512)
+    ES_OCC(2, double, 10, 128) ES_OCC(2, double, 15, 256) ES_OCC(2, double, 21, 512)
+    ES_OCC(1, float, 10, 128) ES_OCC(1, float, 15, 256) ES_OCC(1, float, 21, 512)
+    ES_OCC(2, float, 10, 128) ES_OCC(2, float, 15, 256) ES_OCC(2, float, 21, 512)
+#undef ES_OCC
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_stage_batched(const Phys& ph, const Geo* geos, int mixed, const BatchTiling& tl,
+                                const BatchTables& tb, double ca, double cb, const double* dt_dev,
+                                unsigned* status, hipStream_t s)
+{
+    if (tl.ntiles == 0) return hipSuccess;
+    if (ph.nspec == 1)
+        return mixed ? launch_variant<1, float>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s)
+                     : launch_variant<1, double>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s);
+    return mixed ? launch_variant<2, float>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s)
+                 : launch_variant<2, double>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s);
+}
+
+}  // namespace es

@@ -1,0 +1,378 @@
+// es_flux.hpp -- the per-node and per-interface pieces of the ES flux
+// (Sections 3.1-3.4) shared by the direction-sweep kernels of es_rhs.hip and
+// the batched stage kernel of es_batch.hip.  Node quantities live in an LDS
+// tile (NodeTile); the functions read them by tile index.
+#pragma once
+#include "es_kernels.hpp"
+
+namespace es {
+
+enum { MODE_WRITE = 0, MODE_ADD = 1, MODE_RK = 2 };
+
+template <int N, int D, int NN>
+struct NodeTile {
+    double rho[N][NN];     // species densities
+    double lrho[N][NN];    // their logs
+    double lrt[N == 2 ? NN : 1];  // log of the total density (N = 2)
+    double v[D][NN];       // velocity
+    double b[NN];          // beta = 1/T
+    double lb[NN];         // log beta
+    double m[D + 1][NN];   // metrics of direction k: n_t, n_1..n_D
+};
+
+// mixture Gamma, gas constant and pressure of tile node q (N = 2)
+template <int N, int D, int NN>
+__device__ __forceinline__ void mixture(const Phys& ph, const NodeTile<N, D, NN>& S, int q,
+                                        double& gm, double& rm, double& p)
+{
+    const double r0 = S.rho[0][q], r1 = S.rho[1][q];
+    const double cvr = ph.cv[0] * r0 + ph.cv[1] * r1;
+    const double rR = ph.Rg[0] * r0 + ph.Rg[1] * r1;
+    gm = (ph.cvgam[0] * r0 + ph.cvgam[1] * r1) / cvr;
+    rm = rR / (r0 + r1);
+    p = rR / S.b[q] - ph.pinf_tot;
+}
+
+// two-point EC flux between tile nodes ia, ib (eq ECfluxMM), written in the
+// direction-generic form n_t Utilde + sum_j n_j Ftilde_j:
+//   M_l = {rho_l}^ln ({v}.n + n_t),  p^ = Pi - p_inf with Pi = sum R_l {rho_l} / {beta},
+//   momentum = {v} sum M_l + p^ n,
+//   energy = sum M_l (c_vl/{beta}^ln - {|v|^2}/2) + |{v}|^2 sum M_l + Pi {v}.n + p_inf n_t,
+// with {|v|^2} the mean of squares.  The energy line is {v}.momentum +
+// p_inf ({v}.n + n_t) with the two p_inf {v}.n terms cancelled by hand, and
+// Pi is formed in FP64 in both precisions: with a stiffened gas Pi and
+// p_inf are both ~p_inf, so neither difference may be left to FP32.
+template <int N, int D, int NN, typename R>
+__device__ __forceinline__ void ec_pair(const Phys& ph, const NodeTile<N, D, NN>& S, int ia, int ib,
+                                        R* F)
+{
+    constexpr int NC = N + D + 1;
+    const R nt = R(0.5) * (R(S.m[0][ia]) + R(S.m[0][ib]));
+    R n[D], vm[D];
+    R vdn = R(0), v2 = R(0);
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        n[j] = R(0.5) * (R(S.m[1 + j][ia]) + R(S.m[1 + j][ib]));
+        const R va = R(S.v[j][ia]), vb = R(S.v[j][ib]);
+        vm[j] = R(0.5) * (va + vb);
+        v2 += va * va + vb * vb;
+        vdn += vm[j] * n[j];
+    }
+    v2 *= R(0.5);
+    const R vn = vdn + nt;
+    const R ibln = R(inv_logmean(S.b[ia], S.b[ib], S.lb[ia], S.lb[ib]));
+    double Rr = 0.0;
+#pragma unroll
+    for (int l = 0; l < N; l++) Rr += ph.Rg[l] * (S.rho[l][ia] + S.rho[l][ib]);
+    const double Pi = Rr / (S.b[ia] + S.b[ib]);
+    const R phat = R(Pi - ph.pinf_tot);
+    R Mt = R(0), eng = R(0);
+#pragma unroll
+    for (int l = 0; l < N; l++) {
+        const R rln = R(logmean(S.rho[l][ia], S.rho[l][ib], S.lrho[l][ia], S.lrho[l][ib]));
+        const R Ml = rln * vn;
+        F[l] = Ml;
+        Mt += Ml;
+        eng += Ml * (R(ph.cv[l]) * ibln - R(0.5) * v2);
+    }
+    R vv = R(0);
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        F[N + j] = vm[j] * Mt + phat * n[j];
+        vv += vm[j] * vm[j];
+    }
+    F[NC - 1] = eng + vv * Mt + R(Pi) * vdn + R(ph.pinf_tot) * nt;
+}
+
+// ES dissipation 1/2 s T^T R Y [[W]]^WENO at the interface between tile
+// nodes iL (= i) and iR (= i+1); st[t] are the tile indices of nodes
+// i-2..i+3.  Interface metrics, averages and R follow Section 3.4.
+template <int N, int D, int NN, typename R>
+__device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D, NN>& S,
+                                            const int st[6], const Weno<R>& Wc, R* Dout)
+{
+    constexpr int NC = N + D + 1;
+    const int iL = st[2], iR = st[3];
+    // interface metric: mean of the two nodes
+    R n[D];
+    const R nt = R(0.5) * (R(S.m[0][iL]) + R(S.m[0][iR]));
+    R nn2 = R(0);
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        n[j] = R(0.5) * (R(S.m[1 + j][iL]) + R(S.m[1 + j][iR]));
+        nn2 += n[j] * n[j];
+    }
+    const R nn = sqrt(nn2);
+    const R inn = nn > R(0) ? R(1) / nn : R(0);
+    Rot<D, R> T;
+    if (nn > R(0)) {
+        make_rot<D, R>(n, inn, T);
+    } else {
+#pragma unroll
+        for (int a = 0; a < D; a++)
+#pragma unroll
+            for (int b = 0; b < D; b++) T.t[a][b] = R(a == b);
+    }
+    // averaged state
+    R vbar[D];
+    R vn = R(0);
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        vbar[j] = R(0.5) * (R(S.v[j][iL]) + R(S.v[j][iR]));
+        vn += vbar[j] * n[j];
+    }
+    Frame<N, D, R> F;
+    rot_apply<D, R>(T, vbar, F.vh);
+    R vv = R(0);
+#pragma unroll
+    for (int j = 0; j < D; j++) vv += F.vh[j] * F.vh[j];
+    F.K = R(0.5) * vv;
+    const R Tbar = R(inv_logmean(S.b[iL], S.b[iR], S.lb[iL], S.lb[iR]));   // 1/{beta}^ln
+    if constexpr (N == 1) {
+        const R G = R(ph.gam[0]), Rg = R(ph.Rg[0]), cv = R(ph.cv[0]);
+        const R rho = R(logmean(S.rho[0][iL], S.rho[0][iR], S.lrho[0][iL], S.lrho[0][iR]));
+        F.c = sqrt(G * Rg * Tbar);
+        F.H = G * cv * Tbar + F.K;
+        F.sa = sqrt(rho / (R(2) * G * Rg));
+        F.se = sqrt(rho / (cv * G));
+        F.st = sqrt(rho * Tbar);
+    } else {
+        R rl[2];
+        double gmL, gmR, rmL, rmR, pL, pR;
+        mixture<N, D, NN>(ph, S, iL, gmL, rmL, pL);
+        mixture<N, D, NN>(ph, S, iR, gmR, rmR, pR);
+        const R Rm[2] = {R(rmL), R(rmR)};
+        const R Gm[2] = {R(gmL), R(gmR)};
+#pragma unroll
+        for (int l = 0; l < 2; l++)
+            rl[l] = R(logmean(S.rho[l][iL], S.rho[l][iR], S.lrho[l][iL], S.lrho[l][iR]));
+        const double rL = S.rho[0][iL] + S.rho[1][iL], rR = S.rho[0][iR] + S.rho[1][iR];
+        const R rho = R(logmean(rL, rR, S.lrt[iL], S.lrt[iR]));
+        const R Rb = R(0.5) * (Rm[0] + Rm[1]);
+        const R Gb = R(0.5) * (Gm[0] + Gm[1]);
+        const R irho = R(1) / rho;
+        R rhoh = R(0.5) * (R(pL) + R(pR));
+#pragma unroll
+        for (int l = 0; l < 2; l++) rhoh += R(ph.cv[l]) * rl[l] * Tbar + R(ph.pinf[l]);
+        F.H = rhoh * irho + F.K;
+        F.Y[0] = rl[0] * irho;
+        F.Y[1] = rl[1] * irho;
+        const R igm1 = R(1) / (Gb - R(1));
+#pragma unroll
+        for (int l = 0; l < 2; l++)
+            F.e2[l] = F.K - (R(ph.cv[l]) + R(ph.Rg[l]) - Gb * R(ph.cv[l])) * Tbar * igm1;
+        F.c = sqrt(Gb * Rb * Tbar);
+        F.sq = sqrt(rho / (Gb * Rb));
+        F.s2a = F.sq * R(0.70710678118654752440);
+        const R yy = sqrt(F.Y[0] * F.Y[1]);
+        const R sg = sqrt(Gb - R(1));
+        const R syg = F.sq * yy * sqrt(Gb);
+        F.d11 = -syg * R(ph.sr21);
+        F.d12 = F.sq * F.Y[0] * sg;
+        F.d21 = syg * R(ph.isr21);
+        F.d22 = F.sq * F.Y[1] * sg;
+    }
+    const R s = fabs(nt + vn) + nn * F.c;
+
+    // scaled entropy variables W_j = R^T T V(U_j), j = i-2..i+3
+    R W[6][NC];
+#pragma unroll
+    for (int t = 0; t < 6; t++) {
+        const int q = st[t];
+        const R bq = R(S.b[q]);
+        R vq[D], vr[D];
+        R v2 = R(0);
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            vq[j] = R(S.v[j][q]);
+            v2 += vq[j] * vq[j];
+        }
+        R y[NC];
+        const double lbq = S.lb[q];
+#pragma unroll
+        for (int l = 0; l < N; l++)
+            y[l] = R(ph.cv[l] * lbq + ph.Rg[l] * S.lrho[l][q] + ph.cvgam[l]) - R(0.5) * bq * v2;
+        rot_apply<D, R>(T, vq, vr);
+#pragma unroll
+        for (int j = 0; j < D; j++) y[N + j] = bq * vr[j];
+        y[NC - 1] = -bq;
+        frame_project<N, D, R>(F, y, W[t]);
+    }
+    // MR-WENO on each scaled characteristic field, sign matrix Y
+    R Z[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+        const R jw = mr5_jump<R>(W[0][c], W[1][c], W[2][c], W[3][c], W[4][c], W[5][c], Wc);
+        const R jump = W[3][c] - W[2][c];
+        // sign matrix Y: the WENO jump and the jump agree in sign, and the jump
+        // is not zero to working precision (across a contact the acoustic
+        // jumps vanish up to rounding; those count as sign 0)
+        const bool y = (jw * jump > R(0)) && (fabs(jump) > Wc.zero_tol * (fabs(W[2][c]) + fabs(W[3][c])));
+        Z[c] = y ? jw : R(0);
+    }
+    R RZ[NC];
+    frame_expand<N, D, R>(F, Z, RZ);
+    const R hs = R(0.5) * s;
+#pragma unroll
+    for (int l = 0; l < N; l++) Dout[l] = hs * RZ[l];
+    R mv[D], mo[D];
+#pragma unroll
+    for (int j = 0; j < D; j++) mv[j] = RZ[N + j];
+    rot_apply_t<D, R>(T, mv, mo);
+#pragma unroll
+    for (int j = 0; j < D; j++) Dout[N + j] = hs * mo[j];
+    Dout[NC - 1] = hs * RZ[NC - 1];
+}
+
+// Numerical flux at the TL + 1 interfaces of each of TC lines of a tile
+// (the interface form of eq ECFlux_curv_2p minus the ES dissipation of eq
+// HOstable), left in X slot f + 1 of line c.
+//
+// Interface slot f = 0..TL of a line has left node l = f + 2 (the tile's
+// first own node is l = 3).  Its thread evaluates P_m = F(l, l+m), m = 1..3,
+// and with B(f) = a3 P_3 and H(f) = a2 P_2 + B(f) the flux is
+//   F_f = a1 P_1 - D_f + H(f) + H(f-1) + B(f-2),
+// so each two-point flux is evaluated once.  X slot f + 2 carries B(f),
+// then H(f), and finally slot f + 1 holds F_f.  The pairs F(0,3), F(1,4),
+// F(1,3) left of the first interface (B(-2), B(-1), H(-1)) are taken by
+// the lanes with hid = 0 .. 3 TC - 1 (one wave, chosen by the caller).
+// lidx(l, c) is the tile index of node l of line c, xidx(s, c) the X index
+// of slot s of line c, line_ok(c) whether line c exists; f_ok says that
+// this thread's interface (fi, fc) exists and its six nodes are loaded.
+// Every thread of the block must call this (it holds barriers).
+template <int N, int D, int NN, int TL, int TC, typename R, typename LI, typename XI, typename LOK>
+__device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<N, D, NN>& S,
+                                                 R (*X)[(TL + 4) * TC], LI lidx, XI xidx,
+                                                 LOK line_ok, int fi, int fc, bool f_ok, int hid)
+{
+    constexpr int NC = N + D + 1;
+    const R a1 = R(ph.alpha[0]), a2 = R(ph.alpha[1]), a3 = R(ph.alpha[2]);
+    if (hid >= 0 && hid < 3 * TC) {
+        const int h = hid / TC, c = hid % TC;
+        const R am = (h == 2) ? a2 : a3;
+        const int slot = (h == 0) ? 0 : ((h == 1) ? 1 : TL + 3);
+        R F[NC];
+        if (line_ok(c) && am != R(0)) {
+            ec_pair<N, D, NN, R>(ph, S, lidx(h == 0 ? 0 : 1, c), lidx(h == 1 ? 4 : 3, c), F);
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) F[cc] = R(0);
+        }
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) X[cc][xidx(slot, c)] = am * F[cc];
+    }
+    const int fl = fi + 2;
+    R G[NC], A2[NC];
+    if (f_ok) {
+        R F[NC];
+        if (a3 != R(0)) {
+            ec_pair<N, D, NN, R>(ph, S, lidx(fl, fc), lidx(fl + 3, fc), F);
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) F[cc] = R(0);
+        }
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) X[cc][xidx(fi + 2, fc)] = a3 * F[cc];
+        if (ph.dissipation) {
+            Weno<R> Wc;
+            Wc.chi1 = R(ph.chi[0]); Wc.chi2 = R(ph.chi[1]); Wc.chi3 = R(ph.chi[2]);
+            Wc.eps = R(ph.eps); Wc.ichi3 = R(ph.ichi3); Wc.c1c3 = R(ph.c1c3); Wc.c2c3 = R(ph.c2c3);
+            Wc.zero_tol = sizeof(R) == 8 ? R(1e-12) : R(4e-6);
+            int st[6];
+#pragma unroll
+            for (int q = 0; q < 6; q++) st[q] = lidx(fl - 2 + q, fc);
+            dissipation<N, D, NN, R>(ph, S, st, Wc, G);
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) G[cc] = R(0);
+        }
+        ec_pair<N, D, NN, R>(ph, S, lidx(fl, fc), lidx(fl + 1, fc), F);
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) G[cc] = a1 * F[cc] - G[cc];
+        if (a2 != R(0)) {
+            ec_pair<N, D, NN, R>(ph, S, lidx(fl, fc), lidx(fl + 2, fc), F);
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) F[cc] = R(0);
+        }
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) A2[cc] = a2 * F[cc];
+    }
+    __syncthreads();
+    R Hf[NC], Hm[NC];
+    if (f_ok) {
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) {
+            G[cc] += X[cc][xidx(fi, fc)];                   // + B(f-2)
+            Hf[cc] = A2[cc] + X[cc][xidx(fi + 2, fc)];      // H(f)
+        }
+        if (fi == 0) {
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) Hm[cc] = X[cc][xidx(TL + 3, fc)] + X[cc][xidx(1, fc)];
+        }
+    }
+    __syncthreads();
+    if (f_ok) {
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) X[cc][xidx(fi + 2, fc)] = Hf[cc];
+        if (fi == 0) {
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) X[cc][xidx(1, fc)] = Hm[cc];
+        }
+    }
+    __syncthreads();
+    if (f_ok) {
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) {
+            const int xi = xidx(fi + 1, fc);
+            X[cc][xi] = G[cc] + (Hf[cc] + X[cc][xi]);     // F_f into slot f+1
+        }
+    }
+    __syncthreads();
+}
+
+// primitive node quantities of node gi of (JU, J) into tile slot li; returns
+// the status bits of the node (1: rho_l <= 0, T <= 0 or non-finite; 2: J <= 0)
+template <int N, int D, int NN>
+__device__ __forceinline__ unsigned node_state(const Phys& ph, NodeTile<N, D, NN>& S, int li,
+                                               const double* __restrict__ JU,
+                                               const double* __restrict__ Jv, long P, long gi)
+{
+    constexpr int NC = N + D + 1;
+    const double Jq = Jv[gi];
+    const double iJ = 1.0 / Jq;
+    double U[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; cc++) U[cc] = JU[cc * P + gi] * iJ;
+    double rt = 0.0, cvr = 0.0;
+#pragma unroll
+    for (int sp = 0; sp < N; sp++) {
+        rt += U[sp];
+        cvr += ph.cv[sp] * U[sp];
+    }
+    const double ir = 1.0 / rt;
+    double kin = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        const double vj = U[N + j] * ir;
+        S.v[j][li] = vj;
+        kin += 0.5 * U[N + j] * vj;
+    }
+    const double e = U[NC - 1] - kin - ph.pinf_tot;
+    const double beta = cvr / e;
+    S.b[li] = beta;
+    S.lb[li] = log(beta);
+    bool ok = (beta > 0.0) && isfinite(beta) && isfinite(kin);
+#pragma unroll
+    for (int sp = 0; sp < N; sp++) {
+        S.rho[sp][li] = U[sp];
+        S.lrho[sp][li] = log(U[sp]);
+        ok = ok && (U[sp] > 0.0);
+    }
+    if constexpr (N == 2) S.lrt[li] = log(rt);
+    unsigned bad = ok ? 0u : 1u;
+    if (!(Jq > 0.0)) bad |= 2u;
+    return bad;
+}
+
+}  // namespace es

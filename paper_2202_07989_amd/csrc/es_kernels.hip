@@ -598,6 +598,87 @@ hipError_t wavespeed(const Phys& ph, const Geo& g, const double* JU, const doubl
     return hipGetLastError();
 }
 
+// per-instance CFL wave speed of a batch of 2D instances (eq cfl for each):
+// block (b, j0, j1) reduces rows j0..j1-1 of instance b; a second pass
+// reduces each instance's blocks in a fixed order.
+template <int N>
+__global__ void k_wavespeed_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict__ wl,
+                                    const double* const* __restrict__ JUt,
+                                    const double* const* __restrict__ Jt,
+                                    const double* const* __restrict__ jxxt, double* __restrict__ part,
+                                    unsigned* __restrict__ status)
+{
+    constexpr int D = 2;
+    const int4 e = wl[blockIdx.x];
+    const Geo g = geos[e.x];
+    const double* JU = JUt[e.x];
+    const double* Jv = Jt[e.x];
+    const double* jxx = jxxt[e.x];
+    const long P = g.P;
+    const int n0 = g.n[0];
+    const int cnt = (e.z - e.y) * n0;
+    double lam = 0.0;
+    unsigned bad = 0;
+    for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+        const long i = node_index(g, q % n0 + g.ng, e.y + q / n0 + g.ng, 0);
+        NodeState<N, D> s;
+        load_state<N, D>(ph, JU, Jv, P, i, s);
+        if (!s.ok) bad |= 1u;
+        double cvr = 0.0, cg = 0.0, rR = 0.0;
+#pragma unroll
+        for (int l = 0; l < N; l++) {
+            cvr += ph.cv[l] * s.U[l];
+            cg += ph.cvgam[l] * s.U[l];
+            rR += ph.Rg[l] * s.U[l];
+        }
+        const double c = sqrt((rR / s.rho) * (cg / cvr) * s.T);
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            double vn = 0.0, nn = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; j++) {
+                const double n = jxx[(k * D + j) * P + i];
+                vn += s.v[j] * n;
+                nn += n * n;
+            }
+            sum += (fabs(vn) + c * sqrt(nn)) / Jv[i] / g.dxi[k];
+        }
+        lam = fmax(lam, sum);
+    }
+    if (bad) atomicOr(status, bad);
+    lam = block_reduce<RED_MAX>(lam);
+    if (threadIdx.x == 0) part[blockIdx.x] = lam;
+}
+
+__global__ void k_finish_batched(const double* __restrict__ part, const int* __restrict__ first, double cfl,
+                                 double* __restrict__ lam_out, double* __restrict__ dt_out)
+{
+    const int b = blockIdx.x;
+    double v = -INFINITY;
+    for (int t = first[b] + threadIdx.x; t < first[b + 1]; t += blockDim.x) v = fmax(v, part[t]);
+    v = block_reduce<RED_MAX>(v);
+    if (threadIdx.x == 0) {
+        if (lam_out) lam_out[b] = v;
+        dt_out[b] = cfl / v;
+    }
+}
+
+hipError_t wavespeed_batched(const Phys& ph, const Geo* geos, const int4* wl, int nwl, const int* first,
+                             int count, const double* const* JU, const double* const* J,
+                             const double* const* jxx, double cfl, double* part, double* lambda_out,
+                             double* dt_out, unsigned* status, hipStream_t s)
+{
+    if (ph.nspec == 1)
+        hipLaunchKernelGGL(k_wavespeed_batched<1>, dim3(nwl), dim3(256), 0, s, ph, geos, wl, JU, J, jxx,
+                           part, status);
+    else
+        hipLaunchKernelGGL(k_wavespeed_batched<2>, dim3(nwl), dim3(256), 0, s, ph, geos, wl, JU, J, jxx,
+                           part, status);
+    hipLaunchKernelGGL(k_finish_batched, dim3(count), dim3(256), 0, s, part, first, cfl, lambda_out, dt_out);
+    return hipGetLastError();
+}
+
 template <int N, int D>
 static void launch_entropy(const Phys& ph, const Geo& g, const double* JU, const double* J,
                            const double* dJU, const double* dJ, double* part, int nb, hipStream_t s)

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "es_device.hpp"
@@ -54,5 +55,37 @@ struct RkArgs {
 hipError_t launch_rhs(const Phys& ph, const Geo& g, int mixed, const double* JU, const double* J,
                       const double* jxx, const double* jxt, double* outU, double* outJ,
                       const RkArgs* rk, unsigned* status, hipStream_t s);
+
+// batched 2D instances: device tables of per-instance pointers
+struct BatchTables {
+    const double* const* JUn;
+    const double* const* Jn;
+    const double* const* JUs;
+    const double* const* Js;
+    const double* const* jxx;
+    const double* const* jxt;   // may be null (fixed mesh)
+    double* const* JUo;
+    double* const* Jo;
+};
+
+// one region size of the batched stage: the work list and the grid
+struct BatchTiling {
+    int T;                // region edge (10, 15 or 21)
+    int blocks;           // launch grid (persistent when below ntiles)
+    const int4* tiles;    // (instance, x origin, y origin, 0) per region
+    int ntiles;
+};
+
+int batch_threads(int T);
+hipError_t batch_occupancy(int nspec, int mixed, int T, int* blocks_per_cu);
+hipError_t launch_stage_batched(const Phys& ph, const Geo* geos, int mixed, const BatchTiling& tl,
+                                const BatchTables& tb, double ca, double cb, const double* dt_dev,
+                                unsigned* status, hipStream_t s);
+// per-instance CFL wave speed: wl holds (instance, first row, end row, 0)
+// per block, first[b]..first[b+1] the blocks of instance b
+hipError_t wavespeed_batched(const Phys& ph, const Geo* geos, const int4* wl, int nwl, const int* first,
+                             int count, const double* const* JU, const double* const* J,
+                             const double* const* jxx, double cfl, double* part, double* lambda_out,
+                             double* dt_out, unsigned* status, hipStream_t s);
 
 }  // namespace es

@@ -60,6 +60,14 @@ _SIGS = {
     "es_step": [_P, C.POINTER(EsMonitor), C.c_double, C.c_double, C.c_int, _P, _P, _P, _P, _P, _P],
     "es_status": [_P, _P, C.POINTER(C.c_uint), C.c_int],
     "es_npoints": [_P],
+    "es_batch_create": [C.c_void_p, C.c_int, _P],
+    "es_batch_destroy": [_P],
+    "es_rk_stage_batched": [_P, C.c_int, _P, _P, _P],
+    "max_wavespeed_batched": [_P, _P, _P, _P, C.c_double, _P, _P, _P],
+    "es_step_batched": [_P, C.c_double, _P, _P, _P, _P, _P, _P],
+    "es_batch_autotune": [_P, _P, _P, _P, _P, _P, C.c_int, _P, _P],
+    "es_batch_set_tiling": [_P, C.c_int, C.c_int],
+    "es_batch_status": [_P, _P, C.POINTER(C.c_uint), C.c_int],
 }
 
 
@@ -206,3 +214,97 @@ class Context:
         if rc not in (ES_OK, ES_ENONPHYS, ES_ETANGLE):
             raise EsError("es_status", rc)
         return rc, flags.value
+
+
+class EsBatchStageArgs(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("JU_n", "J_n", "JU_s", "J_s", "jxi_x", "jxi_t", "JU_out",
+                                          "J_out")]
+
+
+class PtrTable:
+    """Device array of the data pointers of a list of tensors (one per
+    instance); keeps the tensors alive as long as the table."""
+
+    def __init__(self, tensors):
+        self.tensors = list(tensors)
+        for t in self.tensors:
+            _ptr(t)                          # type / device / layout check
+        self.dev = torch.tensor([t.data_ptr() for t in self.tensors], dtype=torch.int64, device="cuda")
+
+    @property
+    def ptr(self):
+        return C.c_void_p(self.dev.data_ptr())
+
+
+def _table(x):
+    if x is None:
+        return None
+    return x if isinstance(x, PtrTable) else PtrTable(x)
+
+
+class Batch:
+    """One es_batch: independent 2D instances (a list of specs that differ
+    only in their grid) advanced together.  Array arguments are lists of
+    tensors, one per instance, or PtrTable objects built from them."""
+
+    def __init__(self, specs, precision=ES_FP64):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libes needs a HIP device; there is no CPU fallback")
+        self.specs = list(specs)
+        self.count = len(self.specs)
+        grids = (EsGrid * self.count)(*[make_grid(sp, precision) for sp in self.specs])
+        self._grids = grids
+        h = C.c_void_p()
+        _check("es_batch_create", lib.es_batch_create(C.cast(grids, C.c_void_p), self.count, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib.es_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def es_rk_stage_batched(self, stage, dt_dev, JU_n, J_n, JU_s, J_s, jxi_x, jxi_t, JU_out, J_out,
+                            stream=None):
+        tabs = [_table(a) for a in (JU_n, J_n, JU_s, J_s, jxi_x, jxi_t, JU_out, J_out)]
+        args = EsBatchStageArgs(*[t.ptr if t is not None else None for t in tabs])
+        _check("es_rk_stage_batched", lib.es_rk_stage_batched(self.h, stage, _ptr(dt_dev), C.byref(args),
+                                                              _stream(stream)))
+        return tabs
+
+    def max_wavespeed_batched(self, JU, J, jxi_x, cfl, lambda_dev=None, dt_dev=None, stream=None):
+        tabs = [_table(a) for a in (JU, J, jxi_x)]
+        _check("max_wavespeed_batched", lib.max_wavespeed_batched(
+            self.h, tabs[0].ptr, tabs[1].ptr, tabs[2].ptr, float(cfl), _ptr(lambda_dev), _ptr(dt_dev),
+            _stream(stream)))
+        return tabs
+
+    def es_step_batched(self, cfl, JU, J, jxi_x, jxi_t, dt_dev, stream=None):
+        tabs = [_table(a) for a in (JU, J, jxi_x, jxi_t)]
+        _check("es_step_batched", lib.es_step_batched(
+            self.h, float(cfl), tabs[0].ptr, tabs[1].ptr, tabs[2].ptr,
+            tabs[3].ptr if tabs[3] is not None else None, _ptr(dt_dev), _stream(stream)))
+        return tabs
+
+    def es_batch_autotune(self, JU, J, jxi_x, jxi_t, dt_dev, reps=3, stream=None):
+        tabs = [_table(a) for a in (JU, J, jxi_x, jxi_t)]
+        out = (C.c_int * 2)()
+        _check("es_batch_autotune", lib.es_batch_autotune(
+            self.h, tabs[0].ptr, tabs[1].ptr, tabs[2].ptr, tabs[3].ptr if tabs[3] is not None else None,
+            _ptr(dt_dev), int(reps), _stream(stream), C.cast(out, C.c_void_p)))
+        return out[0], out[1]
+
+    def es_batch_set_tiling(self, region, persistent=True):
+        _check("es_batch_set_tiling", lib.es_batch_set_tiling(self.h, int(region), int(bool(persistent))))
+
+    def es_batch_status(self, stream=None, reset=False):
+        f = C.c_uint()
+        rc = lib.es_batch_status(self.h, _stream(stream), C.byref(f), int(reset))
+        if rc not in (ES_OK, ES_ENONPHYS, ES_ETANGLE):
+            raise EsError("es_batch_status", rc)
+        return rc, f.value

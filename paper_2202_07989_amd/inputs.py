@@ -271,3 +271,70 @@ def init_random(spec, seed, noise=0.0, mesh_amp=0.03, **kw):
     rng = np.random.default_rng(seed + 2)
     J = 1.0 + 0.2 * _smooth_field(rng, xi_nodes(spec))
     return assemble(spec, U, J, from_mesh)
+
+
+# --------------------------------------------------------------------------
+# batched form: many 2D two-species instances of uneven size
+# --------------------------------------------------------------------------
+def c5_sizes(count=64, seed=2202):
+    """Square instance sizes N_b = floor(128 * 8**u_b), u_b ~ U[0, 1) (so
+    log-uniform between 128 and 1024), drawn in instance order."""
+    rng = np.random.default_rng(seed)
+    return [int(math.floor(128.0 * 8.0 ** u)) for u in rng.uniform(0.0, 1.0, size=count)]
+
+
+def spec_c5(n):
+    """One instance of the batch: n x n on the unit box, water/air."""
+    return make_spec(2, 2, (n, n), chi=CHI_SHOCK, **WATER_AIR)
+
+
+def c5_quadrants(rng):
+    """Primitive states of the four quadrants of one instance: rho ~ U[0.5, 2],
+    Y_1 ~ U[0.05, 0.95], p log-uniform in [1e5, 1e9], v in a uniformly drawn
+    direction with |v| ~ U[0, 1]; quadrant order (x<1/2,y<1/2), (x>=1/2,
+    y<1/2), (x<1/2, y>=1/2), (x>=1/2, y>=1/2)."""
+    q = []
+    for _ in range(4):
+        rho = rng.uniform(0.5, 2.0)
+        y1 = rng.uniform(0.05, 0.95)
+        p = 10.0 ** rng.uniform(5.0, 9.0)
+        th = rng.uniform(0.0, 2.0 * math.pi)
+        s = rng.uniform(0.0, 1.0)
+        q.append(dict(rho=(rho * y1, rho * (1.0 - y1)), v=(s * math.cos(th), s * math.sin(th)), p=p))
+    return q
+
+
+def init_riemann4(spec, rng, width=2.0):
+    """Four-quadrant Riemann data split at (1/2, 1/2) of the unit box on a
+    fixed uniform mesh (x = xi).  The quadrant states are blended across
+    tanh layers `width` cells wide: the periodic box has the two splits at
+    1/2 and the seam at 0/1, all smoothed the same way (the sharp data trips
+    the positivity of the partial densities, as for the shock-bubble)."""
+    q = c5_quadrants(rng)
+    x, y = xi_nodes(spec)
+    h = spec["dxi"][0]
+
+    def step(s):                       # 0 left of 1/2, 1 right of it; periodic seam at 0/1
+        return 0.5 * (np.tanh((s - 0.5) / (width * h)) - np.tanh((s - 1.0) / (width * h))
+                      - np.tanh(s / (width * h)) + 1.0)
+
+    sx, sy = np.clip(step(x), 0.0, 1.0), np.clip(step(y), 0.0, 1.0)
+    w = [(1 - sx) * (1 - sy), sx * (1 - sy), (1 - sx) * sy, sx * sy]
+    rho = [sum(w[k] * q[k]["rho"][l] for k in range(4)) for l in range(2)]
+    v = [sum(w[k] * q[k]["v"][m] for k in range(4)) for m in range(2)]
+    # log-blend the pressure (it spans four decades)
+    p = np.exp(sum(w[k] * math.log(q[k]["p"]) for k in range(4)))
+    U = conserved(spec, rho, v, p)
+    J = np.ones_like(x)
+    return assemble(spec, U, J, [x, y])
+
+
+def init_c5(count=64, seed=2202, sizes=None):
+    """Specs and initial (JU, J, x) of every instance of the batch; instance
+    b draws its data from default_rng([seed, b])."""
+    sizes = sizes if sizes is not None else c5_sizes(count, seed)
+    out = []
+    for b, n in enumerate(sizes):
+        sp = spec_c5(n)
+        out.append((sp,) + init_riemann4(sp, np.random.default_rng([seed, b])))
+    return out

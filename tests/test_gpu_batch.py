@@ -1,0 +1,212 @@
+"""Batched 2D instances (es_batch_*) against the single-instance path and the
+CPU FP64 oracle.
+
+Each instance of a batch runs the same scheme as es_rk_stage on its own
+grid, with the same per-interface arithmetic in the same order, so the
+batched stage must equal the single-instance stage bit for bit for every
+region size and grid kind; against the oracle the FP64 bar (1e-11 of the
+state scale) applies, ghost layers included (the batched stage writes the
+periodic ghost images itself).  Sizes are ragged against the 10/15/21
+regions."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_07989_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_2202_07989_amd import es  # noqa: E402
+from gpu_util import TOL_FP64, dev, host, parity, state_scale, say  # noqa: E402
+
+SIZES = [19, 40, 33, 12, 26]
+TOL_MIXED = 2e-5
+
+
+def instances(sizes=SIZES, seed=2202):
+    """Per instance: spec, oracle, padded JU, J (ghosts filled), metrics."""
+    out = []
+    for sp, JU, J, x in I.init_c5(seed=seed, sizes=sizes):
+        o = oracle.Oracle(sp)
+        o.fill_ghosts(JU, o.nc)
+        o.fill_ghosts(J, 1)
+        o.fill_ghosts_x(x)
+        jx, _ = o.metrics(x)
+        out.append(dict(sp=sp, o=o, JU=JU, J=J, x=x, jx=jx))
+    return out
+
+
+def oracle_dt(inst, cfl):
+    return np.array([d["o"].max_wavespeed(d["JU"], d["J"], d["jx"], cfl)[2] for d in inst])
+
+
+@pytest.fixture(scope="module")
+def batch_inputs():
+    say("[batch] building instances")
+    inst = instances()
+    rng = np.random.default_rng(8)
+    for d in inst:
+        d["JUn"] = d["JU"] * (1 + 1e-3 * rng.uniform(-1, 1, d["JU"].shape[1:]))[None]
+        d["Jn"] = d["J"].copy()
+    return inst
+
+
+def test_wavespeed_batched(batch_inputs):
+    inst = batch_inputs
+    b = es.Batch([d["sp"] for d in inst])
+    lam = torch.zeros(len(inst), dtype=torch.float64, device="cuda")
+    dt = torch.zeros_like(lam)
+    b.max_wavespeed_batched([dev(d["JU"]) for d in inst], [dev(d["J"]) for d in inst],
+                            [dev(d["jx"]) for d in inst], 0.4, lam, dt)
+    hl, hd = host(lam), host(dt)
+    for k, d in enumerate(inst):
+        _, l, t = d["o"].max_wavespeed(d["JU"], d["J"], d["jx"], 0.4)
+        assert hl[k] == pytest.approx(l, rel=1e-13)
+        assert hd[k] == pytest.approx(t, rel=1e-13)
+
+
+@pytest.mark.parametrize("precision", [es.ES_FP64, es.ES_MIXED])
+@pytest.mark.parametrize("region,persistent", [(10, 1), (15, 1), (21, 1), (15, 0)])
+def test_stage_batched_equals_single(batch_inputs, precision, region, persistent):
+    say(f"[batch stage] precision={precision} region={region} persistent={persistent}")
+    inst = batch_inputs
+    b = es.Batch([d["sp"] for d in inst], precision=precision)
+    b.es_batch_set_tiling(region, persistent)
+    dts = oracle_dt(inst, 0.4)
+    dt_dev = torch.tensor(dts, dtype=torch.float64, device="cuda")
+    gU = [dev(d["JU"]) for d in inst]
+    gJ = [dev(d["J"]) for d in inst]
+    gUn = [dev(d["JUn"]) for d in inst]
+    gJn = [dev(d["Jn"]) for d in inst]
+    gx = [dev(d["jx"]) for d in inst]
+    for stage in range(3):
+        outU = [torch.full_like(t, np.nan) for t in gU]
+        outJ = [torch.full_like(t, np.nan) for t in gJ]
+        b.es_rk_stage_batched(stage, dt_dev, gUn, gJn, gU, gJ, gx, None, outU, outJ)
+        torch.cuda.synchronize()
+        for k, d in enumerate(inst):
+            ctx = es.Context(d["sp"], precision=precision)
+            rU, rJ = torch.zeros_like(gU[k]), torch.zeros_like(gJ[k])
+            ctx.es_rk_stage(stage, dt_dev[k:k + 1].clone(), gUn[k], gJn[k], gU[k], gJ[k], gx[k], None, rU, rJ)
+            ctx.es_fill_ghosts(rU, d["o"].nc)
+            ctx.es_fill_ghosts(rJ, 1)
+            dU = (outU[k] - rU).abs().max().item()
+            assert torch.equal(outU[k], rU), (k, stage, dU, rU.abs().max().item())
+            assert torch.equal(outJ[k], rJ), (k, stage, (outJ[k] - rJ).abs().max().item())
+    assert b.es_batch_status()[0] == es.ES_OK
+
+
+def test_stage_batched_oracle(batch_inputs):
+    inst = batch_inputs
+    b = es.Batch([d["sp"] for d in inst])
+    dts = oracle_dt(inst, 0.4)
+    dt_dev = torch.tensor(dts, dtype=torch.float64, device="cuda")
+    outU = [torch.zeros_like(dev(d["JU"])) for d in inst]
+    outJ = [torch.zeros_like(dev(d["J"])) for d in inst]
+    b.es_rk_stage_batched(1, dt_dev, [dev(d["JUn"]) for d in inst], [dev(d["Jn"]) for d in inst],
+                          [dev(d["JU"]) for d in inst], [dev(d["J"]) for d in inst],
+                          [dev(d["jx"]) for d in inst], None, outU, outJ)
+    for k, d in enumerate(inst):
+        o, sp = d["o"], d["sp"]
+        rc, oU, oJ = o.rk_stage(1, dts[k], d["JUn"], d["Jn"], d["JU"], d["J"], d["jx"],
+                                np.zeros((2,) + d["J"].shape[1:]))
+        assert rc == 0
+        o.fill_ghosts(oU, o.nc)
+        o.fill_ghosts(oJ, 1)
+        _, lam, _ = o.max_wavespeed(d["JU"], d["J"], d["jx"], 1.0)
+        sc = state_scale(d["JU"], sp, lam)
+        hU, hJ = host(outU[k]), host(outJ[k])
+        for c in range(o.nc):
+            assert parity(hU[c], oU[c], sc[c]) <= TOL_FP64, (k, c)       # whole padded array
+        assert parity(hJ, oJ, np.abs(d["J"]).max()) <= TOL_FP64
+
+
+@pytest.mark.parametrize("precision,tol", [(es.ES_FP64, TOL_FP64), (es.ES_MIXED, 3 * 0.4 * 3 * TOL_MIXED)])
+def test_step_batched_oracle(precision, tol):
+    say(f"[batch step] precision={precision}")
+    inst = instances(sizes=[23, 17, 31])
+    b = es.Batch([d["sp"] for d in inst], precision=precision)
+    gU = [dev(d["JU"]) for d in inst]
+    gJ = [dev(d["J"]) for d in inst]
+    gx = [dev(d["jx"]) for d in inst]
+    tU, tJ, tx = es.PtrTable(gU), es.PtrTable(gJ), es.PtrTable(gx)
+    dt_dev = torch.zeros(len(inst), dtype=torch.float64, device="cuda")
+    nsteps = 3
+    for _ in range(nsteps):
+        b.es_step_batched(0.4, tU, tJ, tx, None, dt_dev)
+        for d in inst:
+            rc, dt, _ = d["o"].step(d["JU"], d["J"], d["x"], cfl=0.4, move_mesh=False)
+            assert rc == 0
+    for k, d in enumerate(inst):
+        sp, o = d["sp"], d["o"]
+        _, lam, _ = o.max_wavespeed(d["JU"], d["J"], d["jx"], 1.0)
+        sc = state_scale(d["JU"], sp, lam)
+        hU = host(gU[k])
+        errs = [parity(hU[c], d["JU"][c], sc[c]) for c in range(o.nc)]
+        say(f"    instance {k} n={sp['n'][0]}: {' '.join(f'{e:.1e}' for e in errs)}")
+        assert max(errs) <= tol, (k, errs)
+    assert b.es_batch_status()[0] == es.ES_OK
+
+
+def test_autotune_picks_a_variant_with_equal_results(batch_inputs):
+    inst = batch_inputs
+    b = es.Batch([d["sp"] for d in inst])
+    gU = [dev(d["JU"]) for d in inst]
+    gJ = [dev(d["J"]) for d in inst]
+    gx = [dev(d["jx"]) for d in inst]
+    dt_dev = torch.tensor(oracle_dt(inst, 0.4), dtype=torch.float64, device="cuda")
+    region, pers = b.es_batch_autotune(gU, gJ, gx, None, dt_dev, reps=2)
+    assert region in (10, 15, 21) and pers in (0, 1)
+    outs = []
+    for r, p in ((region, pers), (15, 1)):
+        b.es_batch_set_tiling(r, p)
+        oU = [torch.zeros_like(t) for t in gU]
+        oJ = [torch.zeros_like(t) for t in gJ]
+        b.es_rk_stage_batched(0, dt_dev, gU, gJ, gU, gJ, gx, None, oU, oJ)
+        outs.append([host(t) for t in oU])
+    for a, c in zip(*outs):
+        np.testing.assert_array_equal(a, c)
+
+
+def test_step_batched_graph_replays():
+    """es_step_batched captured in a graph: every replay equals the eager
+    steps, with eager work and synchronisations between the replays."""
+    inst = instances(sizes=[21, 14, 30])
+    b = es.Batch([d["sp"] for d in inst])
+    U0 = [dev(d["JU"]) for d in inst]
+    J0 = [dev(d["J"]) for d in inst]
+    gx = [dev(d["jx"]) for d in inst]
+    # eager reference: two steps
+    eU, eJ = [t.clone() for t in U0], [t.clone() for t in J0]
+    dt_e = torch.zeros(len(inst), dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        b.es_step_batched(0.4, eU, eJ, gx, None, dt_e)
+    torch.cuda.synchronize()
+    # graph of two steps on fixed buffers
+    gU, gJ = [t.clone() for t in U0], [t.clone() for t in J0]
+    tU, tJ, tx = es.PtrTable(gU), es.PtrTable(gJ), es.PtrTable(gx)
+    dt_g = torch.zeros(len(inst), dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.es_step_batched(0.4, tU, tJ, tx, None, dt_g)       # warm-up on the side stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(2):
+            b.es_step_batched(0.4, tU, tJ, tx, None, dt_g)
+    for rep in range(3):
+        for a, c in zip(gU + gJ, U0 + J0):
+            a.copy_(c)                                       # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, c in zip(gU + gJ, eU + eJ):
+            assert torch.equal(a, c), rep
+        assert torch.equal(dt_g, dt_e)
+    assert b.es_batch_status()[0] == es.ES_OK
