@@ -18,10 +18,8 @@
 
 namespace es {
 
-// the 10 x 10 region fits three waves per SIMD in registers without
-// spilling; the larger ones would spill and keep two
 template <int N, int T, int NT, typename R>
-__global__ void __launch_bounds__(NT, (T == 10 ? 3 : 2))
+__global__ void __launch_bounds__(NT)
 k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict__ tiles, int ntiles,
                   BatchTables tb, double ca, double cb, const double* __restrict__ dt_dev,
                   unsigned* __restrict__ status)
