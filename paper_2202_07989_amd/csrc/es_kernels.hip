@@ -132,13 +132,21 @@ __device__ __forceinline__ double xs_at(const double* xn, const double* disp, do
 //   Pr[a][j] = delta_a[xs_p] xs_q,  (p, q) = (j+1, j+2) mod 3,
 // at every node interior along a; pass 2 differences them,
 //   J dxi_k/dx_j = (delta_b[Pr[a][j]] - delta_a[Pr[b][j]]) / (dxi_a dxi_b),  (k, a, b) cyclic.
-// A block owns an MT x MT column of (x, y) nodes and walks up a chunk of z
-// planes: z-differences come from a 7-plane ring in registers (each value is
-// loaded once), x/y-differences from the current plane staged in LDS with a
-// 3-node halo.  delta is the 2w-order central difference
-// 1/2 sum_m alpha_m (f_{+m} - f_{-m}) (alpha_m = 0 for m > w).
+// delta is the 2w-order central difference 1/2 sum_m alpha_m (f_{+m} - f_{-m})
+// (alpha_m = 0 for m > w).  Each thread walks one (x, y) column up a chunk of
+// z planes, and z-differences come from a 7-plane ring in registers (each
+// value is loaded once).
+//   Pass 1 (16 x 16 columns) stages the stage mesh xs = x + c_s disp of the
+//   current plane with a 3-node halo in LDS for the x/y-differences (two
+//   loads per value, each used by up to 13 nodes).
+//   Pass 2 (64 x 4 columns, so a wavefront reads 64 consecutive doubles of a
+//   row) reads the in-plane neighbours of the products straight from memory:
+//   the neighbouring rows are read by other waves at the same time and come
+//   from the caches, and with no LDS and no barrier every wave walks at its
+//   own pace.  Both shapes were the faster of the two designs for their pass.
 constexpr int MT = 16;
 constexpr int MH = MT + 6;
+constexpr int MX = 64, MY = 4;
 
 __device__ __forceinline__ double cdiff(const double* al, double p1, double m1, double p2, double m2,
                                         double p3, double m3)
@@ -227,95 +235,74 @@ k_metric_prod3(Geo g, Phys ph, const double* __restrict__ xn, const double* __re
     }
 }
 
-__global__ void __launch_bounds__(MT * MT)
+__global__ void __launch_bounds__(MX * MY)
 k_metric3(Geo g, Phys ph, const double* __restrict__ disp, const double* __restrict__ Pr,
           const double* __restrict__ dt_dev, double* __restrict__ jxx, double* __restrict__ jxt,
           int zchunk)
 {
-    __shared__ double T[9][MH][MH];   // Pr[a][j] of the current plane, tile + halo
     const long P = g.P;
     const int np0 = g.np[0], np1 = g.np[1];
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    const int x0 = g.ng + blockIdx.x * MT, y0 = g.ng + blockIdx.y * MT;
-    const int x = x0 + tx, y = y0 + ty;
+    const int x = g.ng + blockIdx.x * MX + threadIdx.x, y = g.ng + blockIdx.y * MY + threadIdx.y;
     const int zc0 = g.ng + blockIdx.z * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
-    const bool in = x < g.ng + g.n[0] && y < g.ng + g.n[1];
+    if (x >= g.ng + g.n[0] || y >= g.ng + g.n[1]) return;
     const double dt = dt_dev ? *dt_dev : 0.0;
     const double al[3] = {ph.alpha[0], ph.alpha[1], ph.alpha[2]};
     const double s01 = g.idxi[0] * g.idxi[1], s12 = g.idxi[1] * g.idxi[2], s20 = g.idxi[2] * g.idxi[0];
+    const long sy = np0;
     double ring[6][7];   // Pr[0][j] (0..2) and Pr[1][j] (3..5) at the own node, planes zl-6..zl
 #pragma unroll
     for (int c = 0; c < 6; c++)
 #pragma unroll
         for (int r = 0; r < 7; r++) ring[c][r] = 0.0;
     for (int zl = zc0 - 3; zl < zc1 + 3; zl++) {
+        const long il = ((long)zl * np1 + y) * np0 + x;
 #pragma unroll
         for (int c = 0; c < 6; c++) {
 #pragma unroll
             for (int r = 0; r < 6; r++) ring[c][r] = ring[c][r + 1];
-            ring[c][6] = in ? Pr[(long)c * P + ((long)zl * np1 + y) * np0 + x] : 0.0;
+            ring[c][6] = Pr[(long)c * P + il];
         }
         const int z = zl - 3;
-        if (z < zc0) continue;   // uniform over the block
-        // stage plane z: Pr[0] needs the y-halo, Pr[1] the x-halo, Pr[2] both
-        for (int q = ty * MT + tx; q < MH * MH; q += MT * MT) {
-            const int hx = q % MH, hy = q / MH;
-            const int gx = x0 + hx - 3, gy = y0 + hy - 3;
-            const bool xc = hx >= 3 && hx < 3 + MT, yc = hy >= 3 && hy < 3 + MT;
-            if (gx >= np0 || gy >= np1 || !(xc || yc)) continue;
-            const long i = ((long)z * np1 + gy) * np0 + gx;
+        if (z < zc0) continue;
+        const long i = ((long)z * np1 + y) * np0 + x;
+        double M[3][3];
 #pragma unroll
-            for (int j = 0; j < 3; j++) {
-                if (xc) T[j][hy][hx] = Pr[(long)j * P + i];
-                if (yc) T[3 + j][hy][hx] = Pr[(long)(3 + j) * P + i];
-                T[6 + j][hy][hx] = Pr[(long)(6 + j) * P + i];
+        for (int j = 0; j < 3; j++) {
+            const double* P0 = Pr + (long)j * P + i;
+            const double* P1 = Pr + (long)(3 + j) * P + i;
+            const double* P2 = Pr + (long)(6 + j) * P + i;
+            // k = 0 (a = 1, b = 2): delta_2 Pr[1][j] - delta_1 Pr[2][j]
+            const double* r1 = ring[3 + j];
+            const double t1 = cdiff(al, r1[4], r1[2], r1[5], r1[1], r1[6], r1[0]);
+            const double t2 = cdiff(al, P2[sy], P2[-sy], P2[2 * sy], P2[-2 * sy], P2[3 * sy], P2[-3 * sy]);
+            M[0][j] = (t1 - t2) * s12;
+            // k = 1 (a = 2, b = 0): delta_0 Pr[2][j] - delta_2 Pr[0][j]
+            const double* r0 = ring[j];
+            const double u1 = cdiff(al, P2[1], P2[-1], P2[2], P2[-2], P2[3], P2[-3]);
+            const double u2 = cdiff(al, r0[4], r0[2], r0[5], r0[1], r0[6], r0[0]);
+            M[1][j] = (u1 - u2) * s20;
+            // k = 2 (a = 0, b = 1): delta_1 Pr[0][j] - delta_0 Pr[1][j]
+            const double v1 = cdiff(al, P0[sy], P0[-sy], P0[2 * sy], P0[-2 * sy], P0[3 * sy], P0[-3 * sy]);
+            const double v2 = cdiff(al, P1[1], P1[-1], P1[2], P1[-2], P1[3], P1[-3]);
+            M[2][j] = (v1 - v2) * s01;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) jxx[(k * 3 + j) * P + i] = M[k][j];
+        if (jxt) {
+            double w[3] = {0.0, 0.0, 0.0};
+            if (disp && dt > 0.0)
+#pragma unroll
+                for (int j = 0; j < 3; j++) w[j] = disp[j * P + i] / dt;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                double nt = 0.0;
+#pragma unroll
+                for (int j = 0; j < 3; j++) nt -= w[j] * M[k][j];
+                jxt[k * P + i] = nt;
             }
         }
-        __syncthreads();
-        if (in) {
-            const long i = ((long)z * np1 + y) * np0 + x;
-            const int cx = tx + 3, cy = ty + 3;
-            double M[3][3];
-#pragma unroll
-            for (int j = 0; j < 3; j++) {
-                // k = 0 (a = 1, b = 2): delta_2 Pr[1][j] - delta_1 Pr[2][j]
-                const double* r1 = ring[3 + j];
-                const double t1 = cdiff(al, r1[4], r1[2], r1[5], r1[1], r1[6], r1[0]);
-                const double t2 = cdiff(al, T[6 + j][cy + 1][cx], T[6 + j][cy - 1][cx], T[6 + j][cy + 2][cx],
-                                        T[6 + j][cy - 2][cx], T[6 + j][cy + 3][cx], T[6 + j][cy - 3][cx]);
-                M[0][j] = (t1 - t2) * s12;
-                // k = 1 (a = 2, b = 0): delta_0 Pr[2][j] - delta_2 Pr[0][j]
-                const double* r0 = ring[j];
-                const double u1 = cdiff(al, T[6 + j][cy][cx + 1], T[6 + j][cy][cx - 1], T[6 + j][cy][cx + 2],
-                                        T[6 + j][cy][cx - 2], T[6 + j][cy][cx + 3], T[6 + j][cy][cx - 3]);
-                const double u2 = cdiff(al, r0[4], r0[2], r0[5], r0[1], r0[6], r0[0]);
-                M[1][j] = (u1 - u2) * s20;
-                // k = 2 (a = 0, b = 1): delta_1 Pr[0][j] - delta_0 Pr[1][j]
-                const double v1 = cdiff(al, T[j][cy + 1][cx], T[j][cy - 1][cx], T[j][cy + 2][cx],
-                                        T[j][cy - 2][cx], T[j][cy + 3][cx], T[j][cy - 3][cx]);
-                const double v2 = cdiff(al, T[3 + j][cy][cx + 1], T[3 + j][cy][cx - 1], T[3 + j][cy][cx + 2],
-                                        T[3 + j][cy][cx - 2], T[3 + j][cy][cx + 3], T[3 + j][cy][cx - 3]);
-                M[2][j] = (v1 - v2) * s01;
-            }
-#pragma unroll
-            for (int k = 0; k < 3; k++)
-#pragma unroll
-                for (int j = 0; j < 3; j++) jxx[(k * 3 + j) * P + i] = M[k][j];
-            if (jxt) {
-                double w[3] = {0.0, 0.0, 0.0};
-                if (disp && dt > 0.0)
-#pragma unroll
-                    for (int j = 0; j < 3; j++) w[j] = disp[j * P + i] / dt;
-#pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    double nt = 0.0;
-#pragma unroll
-                    for (int j = 0; j < 3; j++) nt -= w[j] * M[k][j];
-                    jxt[k * P + i] = nt;
-                }
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -405,10 +392,10 @@ hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double*
         const int zc1 = (g.np[2] + nc1 - 1) / nc1;
         hipLaunchKernelGGL(k_metric_prod3, dim3(bx1, by1, (g.np[2] + zc1 - 1) / zc1), dim3(MT, MT), 0, s,
                            g, ph, xn, disp, cs, G, zc1);
-        const int bx2 = (g.n[0] + MT - 1) / MT, by2 = (g.n[1] + MT - 1) / MT;
+        const int bx2 = (g.n[0] + MX - 1) / MX, by2 = (g.n[1] + MY - 1) / MY;
         const int nc2 = std::max(1, std::min(g.n[2] / 16, (4096 + bx2 * by2 - 1) / (bx2 * by2)));
         const int zc2 = (g.n[2] + nc2 - 1) / nc2;
-        hipLaunchKernelGGL(k_metric3, dim3(bx2, by2, (g.n[2] + zc2 - 1) / zc2), dim3(MT, MT), 0, s, g, ph,
+        hipLaunchKernelGGL(k_metric3, dim3(bx2, by2, (g.n[2] + zc2 - 1) / zc2), dim3(MX, MY), 0, s, g, ph,
                            disp, G, dt_dev, jxx, jxt, zc2);
     }
     hipError_t e = hipGetLastError();
@@ -832,6 +819,74 @@ __global__ void k_jacobi(Geo g, const double* __restrict__ th, const double* __r
 }
 
 // movement limiter: per-block min of the bounds (1 if none)
+// 3D Jacobi sweep (the arithmetic of k_jacobi<3>, term for term), walking
+// z: each thread owns one (x, y) column of a 64 x 4 block over a chunk of z
+// planes; theta and x at z-1, z, z+1 come from a 3-plane ring in registers,
+// the in-plane neighbours straight from memory.  Per-block residual maxima go
+// to part[] in block order.
+__global__ void __launch_bounds__(256)
+k_jacobi3(Geo g, const double* __restrict__ th, const double* __restrict__ xa, double* __restrict__ xb,
+          double* __restrict__ part, int zchunk)
+{
+    const long P = g.P;
+    const int np0 = g.np[0], np1 = g.np[1];
+    const int x = g.ng + blockIdx.x * 64 + (int)(threadIdx.x & 63);
+    const int y = g.ng + blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+    const int zc0 = g.ng + blockIdx.z * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
+    const bool in = x < g.ng + g.n[0] && y < g.ng + g.n[1];
+    const long sy = np0, sz = (long)np0 * np1;
+    double ih2[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) ih2[k] = g.dxi[k] * g.dxi[k];
+    double r = 0.0;
+    if (in && zc0 < zc1) {
+        long i = ((long)zc0 * np1 + y) * np0 + x;
+        double tm1 = th[i - sz], t0 = th[i];
+        double xm1[3], x0[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            xm1[c] = xa[c * P + i - sz];
+            x0[c] = xa[c * P + i];
+        }
+        for (int z = zc0; z < zc1; z++, i += sz) {
+            const double tp1 = th[i + sz];
+            double xp1[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) xp1[c] = xa[c * P + i + sz];
+            double tp[3], tm[3];
+            tp[0] = 0.5 * (t0 + th[i + 1]);
+            tm[0] = 0.5 * (t0 + th[i - 1]);
+            tp[1] = 0.5 * (t0 + th[i + sy]);
+            tm[1] = 0.5 * (t0 + th[i - sy]);
+            tp[2] = 0.5 * (t0 + tp1);
+            tm[2] = 0.5 * (t0 + tm1);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const double* xc = xa + c * P + i;
+                double num = 0.0, den = 0.0;
+                num += (tp[0] * xc[1] + tm[0] * xc[-1]) / ih2[0];
+                den += (tp[0] + tm[0]) / ih2[0];
+                num += (tp[1] * xc[sy] + tm[1] * xc[-sy]) / ih2[1];
+                den += (tp[1] + tm[1]) / ih2[1];
+                num += (tp[2] * xp1[c] + tm[2] * xm1[c]) / ih2[2];
+                den += (tp[2] + tm[2]) / ih2[2];
+                const double xn = num / den;
+                xb[c * P + i] = xn;
+                r = fmax(r, fabs(xn - x0[c]));
+            }
+            tm1 = t0;
+            t0 = tp1;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                xm1[c] = x0[c];
+                x0[c] = xp1[c];
+            }
+        }
+    }
+    r = block_reduce<RED_MAX>(r);
+    if (threadIdx.x == 0) part[((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = r;
+}
+
 template <int D>
 __global__ void k_limiter(Geo g, const double* __restrict__ xmu, const double* __restrict__ xn,
                           double* __restrict__ part)
@@ -901,15 +956,25 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, c
     if ((e = copy(xn, w.xa, g.dim * P, s)) != hipSuccess) return e;
     double* xa = w.xa;
     double* xb = w.xb;
+    // 3D sweeps: 64 x 4 columns, z chunks so that the blocks (one residual
+    // partial each) stay within the partial buffer
+    const int jx = (g.n[0] + 63) / 64, jy = (g.n[1] + 3) / 4;
+    const int jz = std::max(1, std::min(g.n[2], RED_BLOCKS / (jx * jy)));
+    const int jchunk = (g.n[2] + jz - 1) / jz;
+    const int jblocks = jx * jy * ((g.n[2] + jchunk - 1) / jchunk);
+    const bool march = g.dim == 3 && jblocks <= RED_BLOCKS;
     for (int nu = 0; nu < mo.n_sweeps; nu++) {
-        if (g.dim == 2)
+        if (march)
+            hipLaunchKernelGGL(k_jacobi3, dim3(jx, jy, (g.n[2] + jchunk - 1) / jchunk), dim3(256), 0, s, g,
+                               th, xa, xb, w.part, jchunk);
+        else if (g.dim == 2)
             hipLaunchKernelGGL(k_jacobi<2>, dim3(nb), dim3(256), 0, s, g, th, xa, xb, w.part);
         else
             hipLaunchKernelGGL(k_jacobi<3>, dim3(nb), dim3(256), 0, s, g, th, xa, xb, w.part);
         if ((e = fill_ghosts(g, xb, g.dim, 1, s)) != hipSuccess) return e;
         if (resid_out)
-            hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part, nb, resid_out + nu, 0,
-                               0.0, status);
+            hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part, march ? jblocks : nb,
+                               resid_out + nu, 0, 0.0, status);
         std::swap(xa, xb);
     }
     // limiter and displacement
