@@ -42,6 +42,29 @@ __device__ __forceinline__ long dir_stride(const Geo& g, int k)
 }
 
 // --------------------------------------------------------------------------
+// reciprocal of a finite, normal, nonzero x: the hardware estimate refined
+// by Newton steps r <- r (2 - x r) (two in FP64, one in FP32), within about
+// an ulp of 1/x.  It replaces IEEE division on the hot path, whose scaling
+// for special operands costs about twice the instructions; a zero, infinite
+// or denormal x only arises from a non-physical state, which then turns
+// non-finite and is reported by the status checks.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ float rcp(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// --------------------------------------------------------------------------
 // logarithmic mean [[a]]/[[ln a]] (Section 3.3.1) from precomputed node logs.
 // Near a = b (f = (a-b)/(a+b), u = f^2 < 1e-4) the ratio is evaluated from
 // series in u instead: {a}^ln = (a+b)/2 * f/atanh(f) and
@@ -52,24 +75,24 @@ __device__ __forceinline__ double logmean(double a, double b, double la, double 
 {
     const double d = a - b, s = a + b;
     if (d * d < 1.0e-4 * (s * s)) {
-        const double is = 1.0 / s;
+        const double is = rcp(s);
         const double f = d * is, u = f * f;
         const double G = 1.0 - u * (1.0 / 3.0 + u * (4.0 / 45.0 + u * (44.0 / 945.0)));
         return 0.5 * s * G;
     }
-    return d / (la - lb);
+    return d * rcp(la - lb);
 }
 
 __device__ __forceinline__ double inv_logmean(double a, double b, double la, double lb)
 {
     const double d = a - b, s = a + b;
     if (d * d < 1.0e-4 * (s * s)) {
-        const double is = 1.0 / s;
+        const double is = rcp(s);
         const double f = d * is, u = f * f;
         const double F = 1.0 + u * (1.0 / 3.0 + u * (1.0 / 5.0 + u * (1.0 / 7.0)));
         return 2.0 * F * is;
     }
-    return (la - lb) / d;
+    return (la - lb) * rcp(d);
 }
 
 // --------------------------------------------------------------------------
@@ -111,7 +134,7 @@ __device__ __forceinline__ void mr5_nd(R qm2, R qm1, R q0, R qp1, R qp2, const W
     // denominator d_1 d_2 d_3 so that the normalised sum needs one division
     R d1 = W.eps + b1, d2 = W.eps + b2, d3 = W.eps + b3;
     if constexpr (sizeof(R) == 4) {   // keep the products in float range
-        const R dm = R(1) / fmax(fmax(d1, d2), d3);
+        const R dm = rcp(fmax(fmax(d1, d2), d3));
         d1 *= dm; d2 *= dm; d3 *= dm; tau *= dm;
     }
     const R w1 = W.chi1 * (d1 + tau) * (d2 * d3);
@@ -126,7 +149,7 @@ __device__ __forceinline__ R mr5(R qm2, R qm1, R q0, R qp1, R qp2, const Weno<R>
 {
     R n, d;
     mr5_nd<R>(qm2, qm1, q0, qp1, qp2, W, n, d);
-    return n / d;
+    return n * rcp(d);
 }
 
 // jump of the two one-sided reconstructions at an interface, wp - wm, from
@@ -139,8 +162,8 @@ __device__ __forceinline__ R mr5_jump(R q0, R q1, R q2, R q3, R q4, R q5, const 
     R nm, dm, np, dp;
     mr5_nd<R>(q0, q1, q2, q3, q4, W, nm, dm);
     mr5_nd<R>(q5, q4, q3, q2, q1, W, np, dp);
-    if constexpr (sizeof(R) == 8) return (np * dm - nm * dp) / (dp * dm);
-    else return np / dp - nm / dm;
+    if constexpr (sizeof(R) == 8) return (np * dm - nm * dp) * rcp(dp * dm);
+    else return np * rcp(dp) - nm * rcp(dm);
 }
 
 // --------------------------------------------------------------------------
@@ -164,7 +187,7 @@ __device__ __forceinline__ void make_rot(const R n[D], R inv_norm, Rot<D, R>& T)
         R ct = R(1), st = R(0), cp = R(0);
         if (r12sq > R(0)) {
             const R r12 = sqrt(r12sq);
-            const R ir12 = R(1) / r12;
+            const R ir12 = rcp(r12);
             ct = n[0] * ir12;
             st = n[1] * ir12;
             cp = r12 * inv_norm;

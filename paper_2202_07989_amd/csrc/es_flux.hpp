@@ -28,9 +28,9 @@ __device__ __forceinline__ void mixture(const Phys& ph, const NodeTile<N, D, NN>
     const double r0 = S.rho[0][q], r1 = S.rho[1][q];
     const double cvr = ph.cv[0] * r0 + ph.cv[1] * r1;
     const double rR = ph.Rg[0] * r0 + ph.Rg[1] * r1;
-    gm = (ph.cvgam[0] * r0 + ph.cvgam[1] * r1) / cvr;
-    rm = rR / (r0 + r1);
-    p = rR / S.b[q] - ph.pinf_tot;
+    gm = (ph.cvgam[0] * r0 + ph.cvgam[1] * r1) * rcp(cvr);
+    rm = rR * rcp(r0 + r1);
+    p = rR * rcp(S.b[q]) - ph.pinf_tot;
 }
 
 // two-point EC flux between tile nodes ia, ib (eq ECfluxMM), written in the
@@ -64,7 +64,7 @@ __device__ __forceinline__ void ec_pair(const Phys& ph, const NodeTile<N, D, NN>
     double Rr = 0.0;
 #pragma unroll
     for (int l = 0; l < N; l++) Rr += ph.Rg[l] * (S.rho[l][ia] + S.rho[l][ib]);
-    const double Pi = Rr / (S.b[ia] + S.b[ib]);
+    const double Pi = Rr * rcp(S.b[ia] + S.b[ib]);
     const R phat = R(Pi - ph.pinf_tot);
     R Mt = R(0), eng = R(0);
 #pragma unroll
@@ -103,7 +103,7 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
         nn2 += n[j] * n[j];
     }
     const R nn = sqrt(nn2);
-    const R inn = nn > R(0) ? R(1) / nn : R(0);
+    const R inn = nn > R(0) ? rcp(nn) : R(0);
     Rot<D, R> T;
     if (nn > R(0)) {
         make_rot<D, R>(n, inn, T);
@@ -133,8 +133,8 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
         const R rho = R(logmean(S.rho[0][iL], S.rho[0][iR], S.lrho[0][iL], S.lrho[0][iR]));
         F.c = sqrt(G * Rg * Tbar);
         F.H = G * cv * Tbar + F.K;
-        F.sa = sqrt(rho / (R(2) * G * Rg));
-        F.se = sqrt(rho / (cv * G));
+        F.sa = sqrt(rho * rcp(R(2) * G * Rg));
+        F.se = sqrt(rho * rcp(cv * G));
         F.st = sqrt(rho * Tbar);
     } else {
         R rl[2];
@@ -150,19 +150,19 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
         const R rho = R(logmean(rL, rR, S.lrt[iL], S.lrt[iR]));
         const R Rb = R(0.5) * (Rm[0] + Rm[1]);
         const R Gb = R(0.5) * (Gm[0] + Gm[1]);
-        const R irho = R(1) / rho;
+        const R irho = rcp(rho);
         R rhoh = R(0.5) * (R(pL) + R(pR));
 #pragma unroll
         for (int l = 0; l < 2; l++) rhoh += R(ph.cv[l]) * rl[l] * Tbar + R(ph.pinf[l]);
         F.H = rhoh * irho + F.K;
         F.Y[0] = rl[0] * irho;
         F.Y[1] = rl[1] * irho;
-        const R igm1 = R(1) / (Gb - R(1));
+        const R igm1 = rcp(Gb - R(1));
 #pragma unroll
         for (int l = 0; l < 2; l++)
             F.e2[l] = F.K - (R(ph.cv[l]) + R(ph.Rg[l]) - Gb * R(ph.cv[l])) * Tbar * igm1;
         F.c = sqrt(Gb * Rb * Tbar);
-        F.sq = sqrt(rho / (Gb * Rb));
+        F.sq = sqrt(rho * rcp(Gb * Rb));
         F.s2a = F.sq * R(0.70710678118654752440);
         const R yy = sqrt(F.Y[0] * F.Y[1]);
         const R sg = sqrt(Gb - R(1));
@@ -340,7 +340,7 @@ __device__ __forceinline__ unsigned node_state(const Phys& ph, NodeTile<N, D, NN
 {
     constexpr int NC = N + D + 1;
     const double Jq = Jv[gi];
-    const double iJ = 1.0 / Jq;
+    const double iJ = rcp(Jq);
     double U[NC];
 #pragma unroll
     for (int cc = 0; cc < NC; cc++) U[cc] = JU[cc * P + gi] * iJ;
@@ -350,7 +350,7 @@ __device__ __forceinline__ unsigned node_state(const Phys& ph, NodeTile<N, D, NN
         rt += U[sp];
         cvr += ph.cv[sp] * U[sp];
     }
-    const double ir = 1.0 / rt;
+    const double ir = rcp(rt);
     double kin = 0.0;
 #pragma unroll
     for (int j = 0; j < D; j++) {
@@ -359,7 +359,7 @@ __device__ __forceinline__ unsigned node_state(const Phys& ph, NodeTile<N, D, NN
         kin += 0.5 * U[N + j] * vj;
     }
     const double e = U[NC - 1] - kin - ph.pinf_tot;
-    const double beta = cvr / e;
+    const double beta = cvr * rcp(e);
     S.b[li] = beta;
     S.lb[li] = log(beta);
     bool ok = (beta > 0.0) && isfinite(beta) && isfinite(kin);

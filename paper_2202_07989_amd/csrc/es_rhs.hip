@@ -50,8 +50,11 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
     const long sK = dir_stride(g, K);
     const int t = threadIdx.x;
 
-    auto lidx = [](int l, int c) { return (K == 0) ? (l + NL * c) : (c + TC * l); };
-    auto xidx = [](int s, int c) { return (K == 0) ? (s + NS * c) : (c + TC * s); };
+    // LDS layouts are line-fastest in every direction, so the lanes of a wave
+    // (consecutive lines) read consecutive words; the x sweep still walks x
+    // fastest in its global loads and stores
+    auto lidx = [](int l, int c) { return c + TC * l; };
+    auto xidx = [](int s, int c) { return c + TC * s; };
     // padded index of the node at along-index 0 of line c of the block
     auto line_base = [&](int c) -> long {
         const long L = line0 + c;
@@ -80,8 +83,8 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
     __syncthreads();
 
     // ---- phase 2: interface fluxes --------------------------------------
-    const int fi = (K == 0) ? (t % (TL + 1)) : (t / TC);
-    const int fc = (K == 0) ? (t / (TL + 1)) : (t % TC);
+    const int fi = t / TC;
+    const int fc = t % TC;
     // node fi + 5 must be inside the padded grid (ragged last segment)
     const bool f_ok = (t < NI) && (line0 + fc < nlines) && (g.ng + seg0 + fi + 2 < g.np[K]);
     interface_fluxes<N, D, NN, TL, TC, R>(ph, S, X, lidx, xidx,
