@@ -106,8 +106,6 @@ void build_params(const es_grid* g, Phys& ph, Geo& geo)
     for (int m = 0; m < 3; m++) ph.chi[m] = g->chi[m];
     ph.eps = g->weno_eps;
     ph.ichi3 = 1.0 / g->chi[2];
-    ph.c1c3 = g->chi[0] / g->chi[2];
-    ph.c2c3 = g->chi[1] / g->chi[2];
     ph.r21 = g->nspec == 2 ? ph.Rg[1] / ph.Rg[0] : 1.0;
     ph.sr21 = sqrt(ph.r21);
     ph.isr21 = 1.0 / ph.sr21;

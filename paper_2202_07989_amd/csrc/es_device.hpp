@@ -18,7 +18,7 @@ struct Phys {
     double pinf_tot;
     double alpha[3];          // alpha_{w,m}
     double chi[3], eps;       // MR-WENO linear weights and epsilon
-    double ichi3, c1c3, c2c3; // 1/chi_3, chi_1/chi_3, chi_2/chi_3
+    double ichi3;             // 1/chi_3
     double r21;               // R_2 / R_1 (N = 2)
     double sr21, isr21;       // sqrt(R_2 / R_1) and its reciprocal
 };
@@ -97,41 +97,45 @@ __device__ __forceinline__ double inv_logmean(double a, double b, double la, dou
 
 // --------------------------------------------------------------------------
 // fifth-order multi-resolution WENO (Appendix A): value at the right face of
-// the centre cell of (q_-2 .. q_2).  h_2, h_3 are the Legendre expansions
-// collapsed to their face values; beta_1 is the min of squared one-sided
-// differences; beta_2, beta_3 are the printed closed forms.
+// the centre cell of (q_-2 .. q_2), written in the four differences
+// D_0..D_3 = q_-1 - q_-2, q_0 - q_-1, q_1 - q_0, q_2 - q_1 (the scheme only
+// ever looks at differences: the smoothness indicators are quadratic forms
+// in them and every reconstruction is q_0 plus a combination of them):
+//   beta_1 = min(D_1^2, D_2^2),
+//   beta_2 = a_2^2 + 13/3 a_3^2 with a_2 = (D_1 + D_2)/2, a_3 = (D_2 - D_1)/2,
+//   beta_3 = the printed closed form, with its Legendre coefficients
+//            t_1 = (7 S12 - S03)/12, t_2 = (11 A03 + 163 A21)/260,
+//            c_4 = (S03 - S12)/12, c_5 = -(A03 + 3 A21)/24
+//            (S03 = D_0 + D_3, S12 = D_1 + D_2, A03 = D_0 - D_3, A21 = D_2 - D_1),
+//   h_1 - q_0 = 0, h_2 - q_0 = (D_1 + 2 D_2)/6,
+//   h_3 - q_0 = (-2 D_0 + 11 D_1 + 24 D_2 - 3 D_3)/60,
+// and the value is q_0 + (w_2 (h_2 - q_0) + w_3 (hc - q_0)) / (w_1 + w_2 + w_3)
+// with hc - q_0 = ((h_3 - q_0) - chi_2 (h_2 - q_0)) / chi_3.  These equal the
+// Legendre forms exactly in rational arithmetic; the weights chi_m (1 + tau /
+// d_m), d_m = eps + beta_m, are taken over the common denominator
+// d_1 d_2 d_3 (one division for the normalised sum).
 // --------------------------------------------------------------------------
 template <typename R>
 struct Weno {
-    R chi1, chi2, chi3, eps, ichi3, c1c3, c2c3;
+    R chi1, chi2, chi3, eps, ichi3;
     R zero_tol;   // relative size below which a jump counts as zero in the sign test
 };
 
-// numerator and denominator of the normalised weighted sum
+// numerator and denominator of (value - q_0)
 template <typename R>
-__device__ __forceinline__ void mr5_nd(R qm2, R qm1, R q0, R qp1, R qp2, const Weno<R>& W, R& num,
-                                       R& den)
+__device__ __forceinline__ void mr5_diff(R D0, R D1, R D2, R D3, const Weno<R>& W, R& num, R& den)
 {
-    const R dl = q0 - qm1, dr = qp1 - q0;
-    const R b1 = fmin(dl * dl, dr * dr);
-    const R a2 = R(0.5) * (qp1 - qm1);
-    const R a3 = R(0.5) * (qm1 - R(2) * q0 + qp1);
-    const R b2 = a2 * a2 + R(13.0 / 3.0) * a3 * a3;
-    const R c2 = (R(11) * (qm2 - qp2) + R(82) * (qp1 - qm1)) * R(1.0 / 120.0);
-    const R c3 = (R(-3) * (qm2 + qp2) + R(40) * (qm1 + qp1) - R(74) * q0) * R(1.0 / 56.0);
-    const R c4 = ((qp2 - qm2) + R(2) * (qm1 - qp1)) * R(1.0 / 12.0);
-    const R c5 = ((qm2 + qp2) - R(4) * (qm1 + qp1) + R(6) * q0) * R(1.0 / 24.0);
-    const R t1 = c2 + R(0.1) * c4, t2 = c3 + R(123.0 / 455.0) * c5;
-    const R b3 = t1 * t1 + R(13.0 / 3.0) * t2 * t2 + R(781.0 / 20.0) * c4 * c4
-               + R(1421461.0 / 2275.0) * c5 * c5;
-    R tau = R(0.5) * (fabs(b3 - b1) + fabs(b3 - b2));
-    tau = tau * tau;
-    const R h1 = q0;
-    const R h2 = (R(-1) * qm1 + R(5) * q0 + R(2) * qp1) * R(1.0 / 6.0);
-    const R h3 = (R(2) * qm2 - R(13) * qm1 + R(47) * q0 + R(27) * qp1 - R(3) * qp2) * R(1.0 / 60.0);
-    const R hc = h3 * W.ichi3 - W.c1c3 * h1 - W.c2c3 * h2;
-    // weights chi_m (1 + tau/d_m), d_m = eps + beta_m, taken over the common
-    // denominator d_1 d_2 d_3 so that the normalised sum needs one division
+    const R S03 = D0 + D3, S12 = D1 + D2, A03 = D0 - D3, A21 = D2 - D1;
+    const R b1 = fmin(D1 * D1, D2 * D2);
+    const R b2 = R(0.25) * (S12 * S12) + R(13.0 / 12.0) * (A21 * A21);
+    const R u1 = R(7) * S12 - S03, u2 = R(11) * A03 + R(163) * A21, u3 = S03 - S12, u4 = A03 + R(3) * A21;
+    const R b3 = R(1.0 / 144.0) * (u1 * u1) + R(13.0 / 3.0 / 67600.0) * (u2 * u2)
+               + R(781.0 / 20.0 / 144.0) * (u3 * u3) + R(1421461.0 / 2275.0 / 576.0) * (u4 * u4);
+    R tau = fabs(b3 - b1) + fabs(b3 - b2);
+    tau = R(0.25) * (tau * tau);
+    const R h2 = (D1 + R(2) * D2) * R(1.0 / 6.0);
+    const R h3 = (R(11) * D1 + R(24) * D2 - R(2) * D0 - R(3) * D3) * R(1.0 / 60.0);
+    const R hc = (h3 - W.chi2 * h2) * W.ichi3;
     R d1 = W.eps + b1, d2 = W.eps + b2, d3 = W.eps + b3;
     if constexpr (sizeof(R) == 4) {   // keep the products in float range
         const R dm = rcp(fmax(fmax(d1, d2), d3));
@@ -140,30 +144,27 @@ __device__ __forceinline__ void mr5_nd(R qm2, R qm1, R q0, R qp1, R qp2, const W
     const R w1 = W.chi1 * (d1 + tau) * (d2 * d3);
     const R w2 = W.chi2 * (d2 + tau) * (d1 * d3);
     const R w3 = W.chi3 * (d3 + tau) * (d1 * d2);
-    num = w1 * h1 + w2 * h2 + w3 * hc;
+    num = w2 * h2 + w3 * hc;
     den = w1 + w2 + w3;
 }
 
+// Jump of the two one-sided reconstructions at an interface, wp - wm, from
+// the stencil W_0..W_5 (nodes i-2..i+3): wm is the reconstruction of
+// (W_0..W_4) at the right face of node i, wp that of the mirrored
+// (W_5..W_1) at the left face of node i+1.  With D_k = W_{k+1} - W_k,
+// wm = W_2 + Nm/Dm from (D_0, D_1, D_2, D_3) and wp = W_3 + Np/Dp from
+// (-D_4, -D_3, -D_2, -D_1), so wp - wm = D_2 + Np/Dp - Nm/Dm; FP64 takes the
+// two quotients over one denominator.  jump_out = W_3 - W_2 = D_2.
 template <typename R>
-__device__ __forceinline__ R mr5(R qm2, R qm1, R q0, R qp1, R qp2, const Weno<R>& W)
+__device__ __forceinline__ R mr5_jump(R q0, R q1, R q2, R q3, R q4, R q5, const Weno<R>& W, R& jump_out)
 {
-    R n, d;
-    mr5_nd<R>(qm2, qm1, q0, qp1, qp2, W, n, d);
-    return n * rcp(d);
-}
-
-// jump of the two one-sided reconstructions at an interface, wp - wm, from
-// the stencils (q_-2..q_3) seen from the left and from the right.  FP64 takes
-// both quotients over one denominator (the weights stay far inside the FP64
-// range); FP32 divides separately.
-template <typename R>
-__device__ __forceinline__ R mr5_jump(R q0, R q1, R q2, R q3, R q4, R q5, const Weno<R>& W)
-{
+    const R D0 = q1 - q0, D1 = q2 - q1, D2 = q3 - q2, D3 = q4 - q3, D4 = q5 - q4;
     R nm, dm, np, dp;
-    mr5_nd<R>(q0, q1, q2, q3, q4, W, nm, dm);
-    mr5_nd<R>(q5, q4, q3, q2, q1, W, np, dp);
-    if constexpr (sizeof(R) == 8) return (np * dm - nm * dp) * rcp(dp * dm);
-    else return np * rcp(dp) - nm * rcp(dm);
+    mr5_diff<R>(D0, D1, D2, D3, W, nm, dm);
+    mr5_diff<R>(-D4, -D3, -D2, -D1, W, np, dp);
+    jump_out = D2;
+    if constexpr (sizeof(R) == 8) return D2 + (np * dm - nm * dp) * rcp(dp * dm);
+    else return D2 + (np * rcp(dp) - nm * rcp(dm));
 }
 
 // --------------------------------------------------------------------------

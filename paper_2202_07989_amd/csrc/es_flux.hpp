@@ -202,8 +202,8 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
     R Z[NC];
 #pragma unroll
     for (int c = 0; c < NC; c++) {
-        const R jw = mr5_jump<R>(W[0][c], W[1][c], W[2][c], W[3][c], W[4][c], W[5][c], Wc);
-        const R jump = W[3][c] - W[2][c];
+        R jump;
+        const R jw = mr5_jump<R>(W[0][c], W[1][c], W[2][c], W[3][c], W[4][c], W[5][c], Wc, jump);
         // sign matrix Y: the WENO jump and the jump agree in sign, and the jump
         // is not zero to working precision (across a contact the acoustic
         // jumps vanish up to rounding; those count as sign 0)
@@ -276,7 +276,7 @@ __device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<
         if (ph.dissipation) {
             Weno<R> Wc;
             Wc.chi1 = R(ph.chi[0]); Wc.chi2 = R(ph.chi[1]); Wc.chi3 = R(ph.chi[2]);
-            Wc.eps = R(ph.eps); Wc.ichi3 = R(ph.ichi3); Wc.c1c3 = R(ph.c1c3); Wc.c2c3 = R(ph.c2c3);
+            Wc.eps = R(ph.eps); Wc.ichi3 = R(ph.ichi3);
             Wc.zero_tol = sizeof(R) == 8 ? R(1e-12) : R(4e-6);
             int st[6];
 #pragma unroll
