@@ -64,6 +64,25 @@ __device__ __forceinline__ float rcp(float x)
     return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
+// square root of a finite, positive, normal x: the hardware 1/sqrt estimate
+// y, then s = x y, h = y/2 refined by one Goldschmidt step and two
+// corrections s += (x - s^2) h, within about an ulp; IEEE sqrt adds the
+// scaling of tiny operands and the selects for 0 and infinity
+__device__ __forceinline__ double sqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double sq = x * y, h = 0.5 * y;
+    const double r = fma(-h, sq, 0.5);
+    sq = fma(sq, r, sq);
+    h = fma(h, r, h);
+    double d = fma(-sq, sq, x);
+    sq = fma(d, h, sq);
+    d = fma(-sq, sq, x);
+    return fma(d, h, sq);
+}
+
+__device__ __forceinline__ float sqrt_pos(float x) { return sqrtf(x); }
+
 // --------------------------------------------------------------------------
 // logarithmic mean [[a]]/[[ln a]] (Section 3.3.1) from precomputed node logs.
 // Near a = b (f = (a-b)/(a+b), u = f^2 < 1e-4) the ratio is evaluated from
@@ -187,7 +206,7 @@ __device__ __forceinline__ void make_rot(const R n[D], R inv_norm, Rot<D, R>& T)
         const R r12sq = n[0] * n[0] + n[1] * n[1];
         R ct = R(1), st = R(0), cp = R(0);
         if (r12sq > R(0)) {
-            const R r12 = sqrt(r12sq);
+            const R r12 = sqrt_pos(r12sq);
             const R ir12 = rcp(r12);
             ct = n[0] * ir12;
             st = n[1] * ir12;

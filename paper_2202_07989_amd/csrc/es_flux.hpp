@@ -131,11 +131,11 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
     if constexpr (N == 1) {
         const R G = R(ph.gam[0]), Rg = R(ph.Rg[0]), cv = R(ph.cv[0]);
         const R rho = R(logmean(S.rho[0][iL], S.rho[0][iR], S.lrho[0][iL], S.lrho[0][iR]));
-        F.c = sqrt(G * Rg * Tbar);
+        F.c = sqrt_pos(G * Rg * Tbar);
         F.H = G * cv * Tbar + F.K;
-        F.sa = sqrt(rho * rcp(R(2) * G * Rg));
-        F.se = sqrt(rho * rcp(cv * G));
-        F.st = sqrt(rho * Tbar);
+        F.sa = sqrt_pos(rho * rcp(R(2) * G * Rg));
+        F.se = sqrt_pos(rho * rcp(cv * G));
+        F.st = sqrt_pos(rho * Tbar);
     } else {
         R rl[2];
         double gmL, gmR, rmL, rmR, pL, pR;
@@ -161,12 +161,12 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
 #pragma unroll
         for (int l = 0; l < 2; l++)
             F.e2[l] = F.K - (R(ph.cv[l]) + R(ph.Rg[l]) - Gb * R(ph.cv[l])) * Tbar * igm1;
-        F.c = sqrt(Gb * Rb * Tbar);
-        F.sq = sqrt(rho * rcp(Gb * Rb));
+        F.c = sqrt_pos(Gb * Rb * Tbar);
+        F.sq = sqrt_pos(rho * rcp(Gb * Rb));
         F.s2a = F.sq * R(0.70710678118654752440);
-        const R yy = sqrt(F.Y[0] * F.Y[1]);
-        const R sg = sqrt(Gb - R(1));
-        const R syg = F.sq * yy * sqrt(Gb);
+        const R yy = sqrt_pos(F.Y[0] * F.Y[1]);
+        const R sg = sqrt_pos(Gb - R(1));
+        const R syg = F.sq * yy * sqrt_pos(Gb);
         F.d11 = -syg * R(ph.sr21);
         F.d12 = F.sq * F.Y[0] * sg;
         F.d21 = syg * R(ph.isr21);

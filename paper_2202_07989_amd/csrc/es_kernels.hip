@@ -10,36 +10,65 @@ namespace es {
 // k; pass k covers the full padded range of the directions already done
 // (so edges and corners come out right) and the interior of the others.
 // ---------------------------------------------------------------------------
-__global__ void k_fill_dir(Geo g, double* __restrict__ a, int ncomp, int K, int is_x)
+// Periodic ghost layers in one launch: every ghost node (the shell of the
+// padded box: the z slabs, then the y slabs over interior z, then the x slabs
+// over interior y and z) copies the interior node it wraps to, with all
+// coordinates wrapped at once.  For the mesh (is_x) component k gains
+// -L_k / +L_k when the node lies below / above the interior along k, the
+// same single shift a direction-by-direction fill would apply.
+__global__ void k_fill_shell(Geo g, double* __restrict__ a, int ncomp, int is_x, long nzs, long nys, long nxs)
 {
-    const int A = (K == 0) ? 1 : 0;
-    const int B = (K == 2) ? 1 : 2;
-    // range along A and B
-    const bool fullA = A < K, fullB = B < K;
-    const int loA = fullA ? 0 : (A < g.dim ? g.ng : 0);
-    const int nA = fullA ? g.np[A] : (A < g.dim ? g.n[A] : 1);
-    const int loB = fullB ? 0 : (B < g.dim ? g.ng : 0);
-    const int nB = fullB ? g.np[B] : (B < g.dim ? g.n[B] : 1);
-    const int ng = g.ng, nK = g.n[K];
-    const long total = (long)2 * ng * nA * nB;
-    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total;
-         t += (long)gridDim.x * blockDim.x) {
-        const int gs = (int)(t % (2 * ng));
-        const long r = t / (2 * ng);
-        const int ia = loA + (int)(r % nA);
-        const int ib = loB + (int)(r / nA);
-        const int ik = gs < ng ? gs : nK + gs;
-        const int src = gs < ng ? ik + nK : ik - nK;
-        const double shift = gs < ng ? -1.0 : 1.0;
-        int d[3], s[3];
-        d[K] = ik; s[K] = src;
-        d[A] = ia; s[A] = ia;
-        d[B] = ib; s[B] = ib;
+    const int ng = g.ng;
+    const int np0 = g.np[0], np1 = g.np[1];
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    const int z0 = g.dim == 3 ? ng : 0, nz = g.dim == 3 ? n2 : 1;
+    (void)nz;
+    const long total = nzs + nys + nxs;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+        int d[3];
+        if (t < nzs) {                                   // z ghost planes
+            const long pl = (long)np0 * np1;
+            const int k = (int)(t / pl);
+            const int r = (int)(t % pl);
+            d[2] = k < ng ? k : k + n2;
+            d[1] = r / np0;
+            d[0] = r % np0;
+        } else if (t < nzs + nys) {                      // y ghost rows over interior z
+            const long u = t - nzs;
+            const long per = 2L * ng * np0;
+            d[2] = z0 + (int)(u / per);
+            const int r = (int)(u % per);
+            const int k = r / np0;
+            d[1] = k < ng ? k : k + n1;
+            d[0] = r % np0;
+        } else {                                         // x ghost columns over interior y, z
+            const long u = t - nzs - nys;
+            const long row = u / (2 * ng);
+            const int k = (int)(u % (2 * ng));
+            d[0] = k < ng ? k : k + n0;
+            d[1] = ng + (int)(row % n1);
+            d[2] = z0 + (int)(row / n1);
+        }
+        int sidx[3];
+        double shift[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            sidx[k] = d[k];
+            if (k < g.dim) {
+                if (d[k] < ng) {
+                    sidx[k] = d[k] + g.n[k];
+                    shift[k] = -g.len[k];
+                } else if (d[k] >= ng + g.n[k]) {
+                    sidx[k] = d[k] - g.n[k];
+                    shift[k] = g.len[k];
+                }
+            }
+        }
         const long di = node_index(g, d[0], d[1], d[2]);
-        const long si = node_index(g, s[0], s[1], s[2]);
+        const long si = node_index(g, sidx[0], sidx[1], sidx[2]);
         for (int c = 0; c < ncomp; c++) {
             double v = a[c * g.P + si];
-            if (is_x && c == K) v += shift * g.len[K];
+            if (is_x && c < g.dim) v += shift[c];
             a[c * g.P + di] = v;
         }
     }
@@ -47,14 +76,14 @@ __global__ void k_fill_dir(Geo g, double* __restrict__ a, int ncomp, int K, int 
 
 hipError_t fill_ghosts(const Geo& g, double* a, int ncomp, int is_x, hipStream_t s)
 {
-    for (int K = 0; K < g.dim; K++) {
-        const int A = (K == 0) ? 1 : 0, B = (K == 2) ? 1 : 2;
-        const long nA = A < K ? g.np[A] : (A < g.dim ? g.n[A] : 1);
-        const long nB = B < K ? g.np[B] : (B < g.dim ? g.n[B] : 1);
-        const long total = 2L * g.ng * nA * nB;
-        const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
-        hipLaunchKernelGGL(k_fill_dir, dim3(blocks), dim3(256), 0, s, g, a, ncomp, K, is_x);
-    }
+    const long ng2 = 2L * g.ng;
+    const long nz = g.dim == 3 ? g.n[2] : 1;
+    const long nzs = g.dim == 3 ? ng2 * g.np[0] * g.np[1] : 0;
+    const long nys = ng2 * g.np[0] * nz;
+    const long nxs = ng2 * g.n[1] * nz;
+    const long total = nzs + nys + nxs;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill_shell, dim3(blocks), dim3(256), 0, s, g, a, ncomp, is_x, nzs, nys, nxs);
     return hipGetLastError();
 }
 
