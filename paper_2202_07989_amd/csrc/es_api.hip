@@ -24,7 +24,7 @@ struct es_ctx {
     MeshWork mesh{};
     bool mesh_ready = false;
     int mesh_nsig = 0;
-    double *JUn = nullptr, *Jn = nullptr, *bufA = nullptr, *bufB = nullptr;
+    double *bufA = nullptr, *bufB = nullptr;
     double *jxx = nullptr, *jxt = nullptr, *disp = nullptr;
 };
 
@@ -159,9 +159,7 @@ int ensure_mesh_ws(es_ctx* c, int nsig)
 int ensure_step_ws(es_ctx* c)
 {
     const size_t P = c->geo.P, d = c->geo.dim, nc = c->ph.nc;
-    int rc = dalloc(&c->JUn, nc * P);
-    if (!rc) rc = dalloc(&c->Jn, P);
-    if (!rc) rc = dalloc(&c->bufA, (nc + 1) * P);
+    int rc = dalloc(&c->bufA, (nc + 1) * P);
     if (!rc) rc = dalloc(&c->bufB, (nc + 1) * P);
     if (!rc) rc = dalloc(&c->jxx, d * d * P);
     if (!rc) rc = dalloc(&c->jxt, d * P);
@@ -212,6 +210,10 @@ int es_create(const es_grid* g, es_ctx** out)
     if (!rc) rc = dalloc(&c->part, 4 * 2048);
     if (!rc && hipMemset(c->status, 0, 4 * sizeof(unsigned)) != hipSuccess) rc = ES_EHIP;
     if (!rc && hipMemset(c->scal, 0, 16 * sizeof(double)) != hipSuccess) rc = ES_EHIP;
+    if (!rc) {
+        const double one = 1.0;   // scal[5]: the unit divisor of the step's first metric pass
+        if (hipMemcpy(c->scal + 5, &one, sizeof(double), hipMemcpyHostToDevice) != hipSuccess) rc = ES_EHIP;
+    }
     if (rc) { es_destroy(c); return rc; }
     *out = c;
     return ES_OK;
@@ -221,7 +223,7 @@ int es_destroy(es_ctx* c)
 {
     if (!c) return ES_EINVAL;
     void* bufs[] = {c->status, c->scal, c->part, c->G, c->mesh.grad, c->mesh.th0, c->mesh.th1,
-                    c->mesh.xa, c->mesh.xb, c->mesh.part, c->mesh.scal, c->JUn, c->Jn, c->bufA,
+                    c->mesh.xa, c->mesh.xb, c->mesh.part, c->mesh.scal, c->bufA,
                     c->bufB, c->jxx, c->jxt, c->disp};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
@@ -357,23 +359,28 @@ int es_step(es_ctx* c, const es_monitor* m, double cfl, double dt_fixed, int mov
     } else {
         ES_TRY(set_scalar(dtau, 0.0, s));
     }
-    // metrics of x^n and the CFL step (zero mesh velocity)
-    ES_TRY(metrics(ph, g, x, nullptr, 0.0, nullptr, c->jxx, nullptr, 0, c->G, s));
+    // metrics of x^n and the CFL step (zero mesh velocity).  With a moving
+    // mesh the same pass leaves -sum_j disp_j J dxi_k/dx_j in jxt (divided by
+    // the device scalar 1); stage 0's sweeps divide it by dt once dt exists
+    ES_TRY(metrics(ph, g, x, disp, 0.0, disp ? c->scal + 5 : nullptr, c->jxx, disp ? c->jxt : nullptr, 0,
+                   c->G, s));
     if (dt_fixed > 0.0) ES_TRY(set_scalar(dt, dt_fixed, s));
     else ES_TRY(wavespeed(ph, g, JU, J, c->jxx, cfl, c->part, c->scal, c->status, s));
-    ES_TRY(copy(JU, c->JUn, nc * P, s));
-    ES_TRY(copy(J, c->Jn, P, s));
     static const double A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
     static const double B[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
     static const double Cs[3] = {0.0, 1.0, 0.5};
+    // Q_n is the caller's (JU, J) itself: stages 0 and 1 only read it, and
+    // stage 2 accumulates its direction sweeps in bufA (free by then) and
+    // writes Q_{n+1} over Q_n, each node by the thread that read its Q_n
     const double* inU = JU;
     const double* inJ = J;
+    double* accs[3][2] = {{c->bufA, c->bufA + nc * P}, {c->bufB, c->bufB + nc * P}, {c->bufA, c->bufA + nc * P}};
     double* outs[3][2] = {{c->bufA, c->bufA + nc * P}, {c->bufB, c->bufB + nc * P}, {JU, J}};
     for (int st = 0; st < 3; st++) {
-        // stage mesh x^n + c_s disp: stage 0 keeps the spatial metrics of x^n
-        if (disp) ES_TRY(metrics(ph, g, x, disp, Cs[st], dt, c->jxx, c->jxt, st == 0 ? 1 : 0, c->G, s));
-        RkArgs rk{c->JUn, c->Jn, dt, A[st], B[st]};
-        ES_TRY(launch_rhs(ph, g, mixed, inU, inJ, c->jxx, disp ? c->jxt : nullptr, outs[st][0], outs[st][1],
+        // stage mesh x^n + c_s disp (stage 0 has it from the pass above)
+        if (disp && st > 0) ES_TRY(metrics(ph, g, x, disp, Cs[st], dt, c->jxx, c->jxt, 0, c->G, s));
+        RkArgs rk{JU, J, dt, A[st], B[st], outs[st][0], outs[st][1], (disp && st == 0) ? dt : nullptr};
+        ES_TRY(launch_rhs(ph, g, mixed, inU, inJ, c->jxx, disp ? c->jxt : nullptr, accs[st][0], accs[st][1],
                           &rk, c->status, s));
         ES_TRY(fill_ghosts(g, outs[st][0], nc, 0, s));
         ES_TRY(fill_ghosts(g, outs[st][1], 1, 0, s));

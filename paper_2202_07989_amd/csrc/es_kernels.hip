@@ -981,8 +981,8 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, c
         if ((e = fill_ghosts(g, th2, 1, 0, s)) != hipSuccess) return e;
         std::swap(th, th2);
     }
-    // Jacobi sweeps
-    if ((e = copy(xn, w.xa, g.dim * P, s)) != hipSuccess) return e;
+    // Jacobi sweeps: the first reads x_n itself, then xa and xb alternate
+    const double* xcur = xn;
     double* xa = w.xa;
     double* xb = w.xb;
     // 3D sweeps: 64 x 4 columns, z chunks so that the blocks (one residual
@@ -995,25 +995,26 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, c
     for (int nu = 0; nu < mo.n_sweeps; nu++) {
         if (march)
             hipLaunchKernelGGL(k_jacobi3, dim3(jx, jy, (g.n[2] + jchunk - 1) / jchunk), dim3(256), 0, s, g,
-                               th, xa, xb, w.part, jchunk);
+                               th, xcur, xa, w.part, jchunk);
         else if (g.dim == 2)
-            hipLaunchKernelGGL(k_jacobi<2>, dim3(nb), dim3(256), 0, s, g, th, xa, xb, w.part);
+            hipLaunchKernelGGL(k_jacobi<2>, dim3(nb), dim3(256), 0, s, g, th, xcur, xa, w.part);
         else
-            hipLaunchKernelGGL(k_jacobi<3>, dim3(nb), dim3(256), 0, s, g, th, xa, xb, w.part);
-        if ((e = fill_ghosts(g, xb, g.dim, 1, s)) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_jacobi<3>, dim3(nb), dim3(256), 0, s, g, th, xcur, xa, w.part);
+        if ((e = fill_ghosts(g, xa, g.dim, 1, s)) != hipSuccess) return e;
         if (resid_out)
             hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part, march ? jblocks : nb,
                                resid_out + nu, 0, 0.0, status);
+        xcur = xa;
         std::swap(xa, xb);
     }
     // limiter and displacement
     if (g.dim == 2)
-        hipLaunchKernelGGL(k_limiter<2>, dim3(nb), dim3(256), 0, s, g, xa, xn, w.part);
+        hipLaunchKernelGGL(k_limiter<2>, dim3(nb), dim3(256), 0, s, g, xcur, xn, w.part);
     else
-        hipLaunchKernelGGL(k_limiter<3>, dim3(nb), dim3(256), 0, s, g, xa, xn, w.part);
+        hipLaunchKernelGGL(k_limiter<3>, dim3(nb), dim3(256), 0, s, g, xcur, xn, w.part);
     hipLaunchKernelGGL(k_finish<RED_MIN>, dim3(1), dim3(256), 0, s, w.part, nb, w.scal + 4, 2, 0.0, status);
     if ((e = fill_value(disp, g.dim * P, 0.0, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_disp, dim3(gi), dim3(256), 0, s, g, xa, xn, w.scal + 4, disp);
+    hipLaunchKernelGGL(k_disp, dim3(gi), dim3(256), 0, s, g, xcur, xn, w.scal + 4, disp);
     if ((e = fill_ghosts(g, disp, g.dim, 0, s)) != hipSuccess) return e;
     if (dtau_out && (e = copy(w.scal + 4, dtau_out, 1, s)) != hipSuccess) return e;
     return hipGetLastError();

@@ -50,6 +50,14 @@ struct RkArgs {
     const double* Jn;
     const double* dt;
     double a, b;
+    // where the stage result goes; null: over the accumulator.  It may be
+    // JUn/Jn themselves (each node's Q_n is read by the thread that then
+    // writes the node)
+    double* outU = nullptr;
+    double* outJ = nullptr;
+    // when set, jxt holds -sum_j disp_j J dxi_k/dx_j and the sweeps divide it
+    // by this device scalar (the step's dt) as they stage it
+    const double* tdiv = nullptr;
 };
 
 hipError_t launch_rhs(const Phys& ph, const Geo& g, int mixed, const double* JU, const double* J,

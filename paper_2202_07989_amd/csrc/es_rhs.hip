@@ -67,6 +67,7 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
 
     // ---- phase 1: node quantities of the tile (+ halo) into LDS ----------
     unsigned bad = 0;
+    const double itd = rk.tdiv ? 1.0 / *rk.tdiv : 1.0;
     for (int q = t; q < NN; q += NT) {
         const int l = (K == 0) ? (q % NL) : (q / TC);
         const int c = (K == 0) ? (q / NL) : (q % TC);
@@ -75,7 +76,7 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
         const long gi = line_base(c) + along * sK;
         const int li = lidx(l, c);
         bad |= node_state<N, D, NN>(ph, S, li, JU, Jv, P, gi);
-        S.m[0][li] = jxt ? jxt[(long)K * P + gi] : 0.0;
+        S.m[0][li] = jxt ? jxt[(long)K * P + gi] * itd : 0.0;
 #pragma unroll
         for (int j = 0; j < D; j++) S.m[1 + j][li] = jxx[(long)(K * D + j) * P + gi];
     }
@@ -115,7 +116,8 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
                     *o += d;
                 } else {
                     const double L = *o + d;
-                    *o = rk.a * rk.JUn[cc * P + gi] + rk.b * (JU[cc * P + gi] + dt * L);
+                    double* w = (rk.outU ? rk.outU : accU) + cc * P + gi;
+                    *w = rk.a * rk.JUn[cc * P + gi] + rk.b * (JU[cc * P + gi] + dt * L);
                 }
             }
             if constexpr (MODE == MODE_WRITE) {
@@ -124,7 +126,7 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
                 accJ[gi] += dJ;
             } else {
                 const double L = accJ[gi] + dJ;
-                accJ[gi] = rk.a * rk.Jn[gi] + rk.b * (Jv[gi] + dt * L);
+                (rk.outJ ? rk.outJ : accJ)[gi] = rk.a * rk.Jn[gi] + rk.b * (Jv[gi] + dt * L);
             }
         }
     }
@@ -157,6 +159,7 @@ static hipError_t rhs_all(const Phys& ph, const Geo& g, const double* JU, const 
                           const RkArgs* rk, unsigned* status, hipStream_t s)
 {
     RkArgs none{nullptr, nullptr, nullptr, 0.0, 0.0};
+    if (rk) none.tdiv = rk->tdiv;
     hipError_t e = launch_dir<N, D, 0, MODE_WRITE, R>(ph, g, JU, J, jxx, jxt, outU, outJ, none,
                                                       status, s);
     if (e != hipSuccess) return e;
