@@ -35,7 +35,7 @@ BYTES_PER_CELL_STAGE = {(3, 2): 33 * 8, (3, 1): 29 * 8, (2, 2): 23 * 8, (2, 1): 
 
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for f in ("es_rhs.hip", "es_device.hpp"):
+    for f in ("es_rhs.hip", "es_flux.hpp", "es_device.hpp"):
         with open(os.path.join(ROOT, "paper_2202_07989_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
