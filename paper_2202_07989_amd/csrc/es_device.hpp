@@ -83,6 +83,39 @@ __device__ __forceinline__ double sqrt_pos(double x)
 
 __device__ __forceinline__ float sqrt_pos(float x) { return sqrtf(x); }
 
+// natural logarithm of a finite, positive, normal x: x = 2^e m with m in
+// [sqrt(1/2), sqrt(2)), ln x = e ln 2 + 2 atanh(s), s = (m - 1)/(m + 1),
+// |s| <= 0.1716, and atanh(s) = s sum_k s^(2k)/(2k+1) taken to k = 9 (the
+// first dropped term is below 1e-17 relative).  ln 2 is carried as a double
+// and its remainder, each multiplied into a fused multiply-add.  Within two
+// ulps (the rounding of m + 1 dominates near x = 1); a third of the
+// instructions of the library logarithm, which works in double-double.
+// Non-positive or non-finite x only arise from states the status checks
+// report.
+__device__ __forceinline__ double ln_pos(double x)
+{
+    int e = __builtin_amdgcn_frexp_exp(x);        // x = m 2^e, m in [1/2, 1)
+    double m = __builtin_amdgcn_frexp_mant(x);
+    const bool lo = m < 0.70710678118654752440;
+    m = lo ? 2.0 * m : m;
+    e = lo ? e - 1 : e;
+    const double s = (m - 1.0) * rcp(m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 19.0;
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double hs = 2.0 * s;
+    const double lm = fma(hs * z, p, hs);
+    const double de = (double)e;
+    return fma(de, 0x1.62e42fefa39efp-1, fma(de, 0x1.abc9e3b39803fp-56, lm));
+}
+
 // --------------------------------------------------------------------------
 // logarithmic mean [[a]]/[[ln a]] (Section 3.3.1) from precomputed node logs.
 // Near a = b (f = (a-b)/(a+b), u = f^2 < 1e-4) the ratio is evaluated from

@@ -361,15 +361,15 @@ __device__ __forceinline__ unsigned node_state(const Phys& ph, NodeTile<N, D, NN
     const double e = U[NC - 1] - kin - ph.pinf_tot;
     const double beta = cvr * rcp(e);
     S.b[li] = beta;
-    S.lb[li] = log(beta);
+    S.lb[li] = ln_pos(beta);
     bool ok = (beta > 0.0) && isfinite(beta) && isfinite(kin);
 #pragma unroll
     for (int sp = 0; sp < N; sp++) {
         S.rho[sp][li] = U[sp];
-        S.lrho[sp][li] = log(U[sp]);
+        S.lrho[sp][li] = ln_pos(U[sp]);
         ok = ok && (U[sp] > 0.0);
     }
-    if constexpr (N == 2) S.lrt[li] = log(rt);
+    if constexpr (N == 2) S.lrt[li] = ln_pos(rt);
     unsigned bad = ok ? 0u : 1u;
     if (!(Jq > 0.0)) bad |= 2u;
     return bad;
