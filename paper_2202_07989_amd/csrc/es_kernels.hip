@@ -318,7 +318,7 @@ k_metric3(Geo g, Phys ph, const double* __restrict__ disp, const double* __restr
 #pragma unroll
         for (int k = 0; k < 3; k++)
 #pragma unroll
-            for (int j = 0; j < 3; j++) jxx[(k * 3 + j) * P + i] = M[k][j];
+            for (int j = 0; j < 3; j++) __builtin_nontemporal_store(M[k][j], &jxx[(k * 3 + j) * P + i]);
         if (jxt) {
             double w[3] = {0.0, 0.0, 0.0};
             if (disp && dt > 0.0)
@@ -329,7 +329,7 @@ k_metric3(Geo g, Phys ph, const double* __restrict__ disp, const double* __restr
                 double nt = 0.0;
 #pragma unroll
                 for (int j = 0; j < 3; j++) nt -= w[j] * M[k][j];
-                jxt[k * P + i] = nt;
+                __builtin_nontemporal_store(nt, &jxt[k * P + i]);
             }
         }
     }
@@ -768,6 +768,85 @@ __global__ void k_monitor_grad(Phys ph, Geo g, MonitorP mo, const double* __rest
     }
 }
 
+// 3D monitor gradient walking z (the central differences of k_monitor_grad):
+// each thread owns one (x, y) column of a 64 x 4 block over a chunk of z
+// planes; sigma at z-1, z, z+1 of the own column comes from a 3-plane ring,
+// the four in-plane neighbours are evaluated from the state directly.
+// Per-block maxima go to part[s * RED_BLOCKS + block] in block order.
+template <int N>
+__global__ void __launch_bounds__(256)
+k_monitor_grad3(Phys ph, Geo g, MonitorP mo, const double* __restrict__ JU, const double* __restrict__ Jv,
+                double* __restrict__ grad, double* __restrict__ part, int zchunk)
+{
+    constexpr int D = 3;
+    const long P = g.P;
+    const int np0 = g.np[0], np1 = g.np[1];
+    const int x = g.ng + blockIdx.x * 64 + (int)(threadIdx.x & 63);
+    const int y = g.ng + blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+    const int zc0 = g.ng + blockIdx.z * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
+    const bool in = x < g.ng + g.n[0] && y < g.ng + g.n[1];
+    const long sy = np0, sz = (long)np0 * np1;
+    double ih[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) ih[k] = 1.0 / (2.0 * g.dxi[k]);
+    double gm[4] = {0.0, 0.0, 0.0, 0.0};
+    if (in && zc0 < zc1) {
+        for (int s = 0; s < mo.nsig; s++) {
+            const int sg = mo.sigma[s];
+            long i = ((long)zc0 * np1 + y) * np0 + x;
+            double sm = sigma_of<N, D>(ph, JU, Jv, P, i - sz, sg);
+            double s0 = sigma_of<N, D>(ph, JU, Jv, P, i, sg);
+            for (int z = zc0; z < zc1; z++, i += sz) {
+                const double sp = sigma_of<N, D>(ph, JU, Jv, P, i + sz, sg);
+                const double d0 = (sigma_of<N, D>(ph, JU, Jv, P, i + 1, sg) -
+                                   sigma_of<N, D>(ph, JU, Jv, P, i - 1, sg)) * ih[0];
+                const double d1 = (sigma_of<N, D>(ph, JU, Jv, P, i + sy, sg) -
+                                   sigma_of<N, D>(ph, JU, Jv, P, i - sy, sg)) * ih[1];
+                const double d2 = (sp - sm) * ih[2];
+                const double gv = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+                grad[s * P + i] = gv;
+                gm[s] = fmax(gm[s], gv);
+                sm = s0;
+                s0 = sp;
+            }
+        }
+    }
+    const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    for (int s = 0; s < 4; s++) {
+        const double r = block_reduce<RED_MAX>(gm[s]);
+        if (threadIdx.x == 0 && s < mo.nsig) part[s * RED_BLOCKS + blk] = r;
+    }
+}
+
+// 3D monitor filter walking z: the weights 2^-(|j|_1 + 3), j in {-1,0,1}^3,
+// are the product of (1/4, 1/2, 1/4) along each direction, so each plane
+// contributes its 9-point in-plane sum q(z') and out = q(z-1)/4 + q(z)/2 +
+// q(z+1)/4 from a 3-plane ring.
+__global__ void __launch_bounds__(256)
+k_filter3(Geo g, const double* __restrict__ in, double* __restrict__ out, int zchunk)
+{
+    const int np0 = g.np[0], np1 = g.np[1];
+    const int x = g.ng + blockIdx.x * 64 + (int)(threadIdx.x & 63);
+    const int y = g.ng + blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+    const int zc0 = g.ng + blockIdx.z * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
+    if (x >= g.ng + g.n[0] || y >= g.ng + g.n[1] || zc0 >= zc1) return;
+    const long sy = np0, sz = (long)np0 * np1;
+    auto plane = [&](long c) {   // in-plane (1/4, 1/2, 1/4) x (1/4, 1/2, 1/4) sum around c
+        const double r0 = 0.25 * in[c - sy - 1] + 0.5 * in[c - sy] + 0.25 * in[c - sy + 1];
+        const double r1 = 0.25 * in[c - 1] + 0.5 * in[c] + 0.25 * in[c + 1];
+        const double r2 = 0.25 * in[c + sy - 1] + 0.5 * in[c + sy] + 0.25 * in[c + sy + 1];
+        return 0.25 * r0 + 0.5 * r1 + 0.25 * r2;
+    };
+    long i = ((long)zc0 * np1 + y) * np0 + x;
+    double qm = plane(i - sz), q0 = plane(i);
+    for (int z = zc0; z < zc1; z++, i += sz) {
+        const double qp = plane(i + sz);
+        out[i] = 0.25 * qm + 0.5 * q0 + 0.25 * qp;
+        qm = q0;
+        q0 = qp;
+    }
+}
+
 __global__ void k_theta(Geo g, MonitorP mo, const double* __restrict__ grad, const double* __restrict__ gmax,
                         double* __restrict__ theta)
 {
@@ -966,18 +1045,34 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, c
     const long nint = (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1);
     const int nb = red_grid(nint);
     const int gi = grid_for(nint);
+    // 3D kernels walk z over 64 x 4 columns, in z chunks so that the blocks
+    // (one reduction partial each) stay within the partial buffer
+    const int jx = (g.n[0] + 63) / 64, jy = (g.n[1] + 3) / 4;
+    const int jz = std::max(1, std::min(g.n[2], RED_BLOCKS / (jx * jy)));
+    const int jchunk = (g.n[2] + jz - 1) / jz;
+    const dim3 jgrid(jx, jy, (g.n[2] + jchunk - 1) / jchunk);
+    const int jblocks = jx * jy * (int)jgrid.z;
+    const bool march = g.dim == 3 && jblocks <= RED_BLOCKS;
     // monitor and its global maxima
-    ES_DISPATCH_ND(ph, g, launch_monitor, ph, g, mo, JU, J, w.grad, w.part, nb, s);
+    if (march && ph.nspec == 1)
+        hipLaunchKernelGGL(k_monitor_grad3<1>, jgrid, dim3(256), 0, s, ph, g, mo, JU, J, w.grad, w.part, jchunk);
+    else if (march)
+        hipLaunchKernelGGL(k_monitor_grad3<2>, jgrid, dim3(256), 0, s, ph, g, mo, JU, J, w.grad, w.part, jchunk);
+    else
+        ES_DISPATCH_ND(ph, g, launch_monitor, ph, g, mo, JU, J, w.grad, w.part, nb, s);
     for (int q = 0; q < mo.nsig; q++)
-        hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part + q * RED_BLOCKS, nb,
-                           w.scal + q, 0, 0.0, status);
+        hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part + q * RED_BLOCKS,
+                           march ? jblocks : nb, w.scal + q, 0, 0.0, status);
     hipLaunchKernelGGL(k_theta, dim3(gi), dim3(256), 0, s, g, mo, w.grad, w.scal, w.th0);
     hipError_t e = fill_ghosts(g, w.th0, 1, 0, s);
     if (e != hipSuccess) return e;
     double* th = w.th0;
     double* th2 = w.th1;
     for (int q = 0; q < mo.n_smooth; q++) {
-        hipLaunchKernelGGL(k_filter, dim3(gi), dim3(256), 0, s, g, th, th2);
+        if (march)
+            hipLaunchKernelGGL(k_filter3, jgrid, dim3(256), 0, s, g, th, th2, jchunk);
+        else
+            hipLaunchKernelGGL(k_filter, dim3(gi), dim3(256), 0, s, g, th, th2);
         if ((e = fill_ghosts(g, th2, 1, 0, s)) != hipSuccess) return e;
         std::swap(th, th2);
     }
@@ -985,17 +1080,9 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, c
     const double* xcur = xn;
     double* xa = w.xa;
     double* xb = w.xb;
-    // 3D sweeps: 64 x 4 columns, z chunks so that the blocks (one residual
-    // partial each) stay within the partial buffer
-    const int jx = (g.n[0] + 63) / 64, jy = (g.n[1] + 3) / 4;
-    const int jz = std::max(1, std::min(g.n[2], RED_BLOCKS / (jx * jy)));
-    const int jchunk = (g.n[2] + jz - 1) / jz;
-    const int jblocks = jx * jy * ((g.n[2] + jchunk - 1) / jchunk);
-    const bool march = g.dim == 3 && jblocks <= RED_BLOCKS;
     for (int nu = 0; nu < mo.n_sweeps; nu++) {
         if (march)
-            hipLaunchKernelGGL(k_jacobi3, dim3(jx, jy, (g.n[2] + jchunk - 1) / jchunk), dim3(256), 0, s, g,
-                               th, xcur, xa, w.part, jchunk);
+            hipLaunchKernelGGL(k_jacobi3, jgrid, dim3(256), 0, s, g, th, xcur, xa, w.part, jchunk);
         else if (g.dim == 2)
             hipLaunchKernelGGL(k_jacobi<2>, dim3(nb), dim3(256), 0, s, g, th, xcur, xa, w.part);
         else

@@ -55,15 +55,19 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
     // fastest in its global loads and stores
     auto lidx = [](int l, int c) { return c + TC * l; };
     auto xidx = [](int s, int c) { return c + TC * s; };
-    // padded index of the node at along-index 0 of line c of the block
-    auto line_base = [&](int c) -> long {
-        const long L = line0 + c;
+    // padded index of the node at along-index 0 of each line of the block,
+    // tabulated once (the line index splits into the two across indices by a
+    // division)
+    __shared__ long s_base[TC];
+    if (t < TC) {
+        const int L = (int)line0 + t;
         int i[3];
         i[K] = 0;
-        i[FA] = g.ng + (int)(L % nF);
-        i[SA] = (SA < D) ? g.ng + (int)(L / nF) : 0;
-        return node_index(g, i[0], i[1], i[2]);
-    };
+        i[FA] = g.ng + L % nF;
+        i[SA] = (SA < D) ? g.ng + L / nF : 0;
+        s_base[t] = node_index(g, i[0], i[1], i[2]);
+    }
+    __syncthreads();
 
     // ---- phase 1: node quantities of the tile (+ halo) into LDS ----------
     unsigned bad = 0;
@@ -73,7 +77,7 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
         const int c = (K == 0) ? (q / NL) : (q % TC);
         const int along = g.ng + seg0 + l - 3;
         if (along >= g.np[K] || line0 + c >= nlines) continue;
-        const long gi = line_base(c) + along * sK;
+        const long gi = s_base[c] + along * sK;
         const int li = lidx(l, c);
         bad |= node_state<N, D, NN>(ph, S, li, JU, Jv, P, gi);
         S.m[0][li] = jxt ? jxt[(long)K * P + gi] * itd : 0.0;
@@ -103,7 +107,7 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
 #pragma unroll
             for (int m = 1; m <= 3; m++)
                 gcl += ph.alpha[m - 1] * (S.m[0][lidx(l + m, c)] - S.m[0][lidx(l - m, c)]);
-            const long gi = line_base(c) + (g.ng + seg0 + lo) * sK;
+            const long gi = s_base[c] + (g.ng + seg0 + lo) * sK;
             const double h = g.idxi[K];
             const double dJ = -0.5 * gcl * h;
 #pragma unroll
@@ -146,7 +150,7 @@ static hipError_t launch_dir(const Phys& ph, const Geo& g, const double* JU, con
     const long nseg = (g.n[K] + TL - 1) / TL;
     const long nlines = (long)g.n[FA] * ((SA < D) ? g.n[SA] : 1);
     const long nblk = nseg * ((nlines + TC - 1) / TC);
-    if (nblk > 0x7fffffffL) return hipErrorInvalidConfiguration;
+    if (nblk > 0x7fffffffL || nlines + TC > 0x7fffffffL) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)nblk);
     hipLaunchKernelGGL((k_rhs_dir<N, D, K, TL, TC, MODE, R>), grid, dim3(256), 0, s, ph, g, JU, J,
                        jxx, jxt, accU, accJ, rk, status);
