@@ -426,9 +426,14 @@ def main():
         dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
         gU, gJ, gx = dev(JU), dev(J), dev(x)
         ctx = es.Context(sp, precision=prec)
+        ctx.es_fill_ghosts(gU, sp["nspec"] + 4)
+        ctx.es_fill_ghosts(gJ, 1)
+        ctx.es_fill_ghosts_x(gx)
         mon = I.monitor_spec(n_sweeps=5, n_smooth=3, sigma=(0,), alpha=(1200.0,))
         dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
         run_stage_only(ctx, mon, 0.3, gU, gJ, gx, dt_dev, args.stage_reps)
+        rc, _ = ctx.es_status()
+        print(json.dumps({"mode": "stage", "status": rc}), flush=True)
         return
 
     main_prec = "mixed" if args.precision == "mixed" else "fp64"
