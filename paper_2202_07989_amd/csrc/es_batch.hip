@@ -93,7 +93,7 @@ k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict_
             const int fi = t % (T + 1), fc = t / (T + 1);
             // the interface's right stencil node fi + 5 (patch coordinate) must be loaded
             const bool f_ok = (t < NI) && (o_line + fc < nL) && (o_along + fi + 2 < nK + 3);
-            interface_fluxes<N, D, NN, T, T, R>(ph, S, X, tidx, xidx,
+            interface_fluxes<N, D, NN, T, T, false, R>(ph, S, X, tidx, xidx,
                                                 [&](int c) { return o_line + c < nL; }, fi, fc, f_ok,
                                                 t - (int)((blockIdx.x + w) % NW) * 64);
             if (t < T * T) {
@@ -131,10 +131,13 @@ k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict_
             const double* __restrict__ Jn = tb.Jn[bi];
             double* __restrict__ JUo = tb.JUo[bi];
             double* __restrict__ Jo = tb.Jo[bi];
+            // stage 0 has ca = 0: the state at t^n is not read at all
+            const bool rn = ca != 0.0;
             double o[NC];
 #pragma unroll
-            for (int cc = 0; cc < NC; cc++) o[cc] = ca * JUn[cc * P + gi] + cb * (JUs[cc * P + gi] + dt * acc[cc]);
-            const double oJ = ca * Jn[gi] + cb * (Js[gi] + dt * accJ);
+            for (int cc = 0; cc < NC; cc++)
+                o[cc] = ca * (rn ? JUn[cc * P + gi] : 0.0) + cb * (JUs[cc * P + gi] + dt * acc[cc]);
+            const double oJ = ca * (rn ? Jn[gi] : 0.0) + cb * (Js[gi] + dt * accJ);
 #pragma unroll
             for (int ky = -1; ky <= 1; ky++) {
                 const int yy = gy + ky * ny;

@@ -83,6 +83,20 @@ __device__ __forceinline__ double sqrt_pos(double x)
 
 __device__ __forceinline__ float sqrt_pos(float x) { return sqrtf(x); }
 
+// 1/sqrt(x) of a finite, positive, normal x: the hardware estimate refined by
+// two Newton steps y <- y + y/2 (1 - x y^2)
+__device__ __forceinline__ double rsqrt_pos(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
+// FP32 operands go through FP64: the FP32 estimate does not take denormal
+// operands, and the squared tangential part of a nearly axis-aligned
+// interface normal can be one
+__device__ __forceinline__ float rsqrt_pos(float x) { return (float)rsqrt_pos((double)x); }
+
 // natural logarithm of a finite, positive, normal x: x = 2^e m with m in
 // [sqrt(1/2), sqrt(2)), ln x = e ln 2 + 2 atanh(s), s = (m - 1)/(m + 1),
 // |s| <= 0.1716, and atanh(s) = s sum_k s^(2k)/(2k+1) taken to k = 9 (the
@@ -224,55 +238,66 @@ __device__ __forceinline__ R mr5_jump(R q0, R q1, R q2, R q3, R q4, R q5, const 
 // rows from theta = atan2(n2, n1) (0 when n1 = n2 = 0) and phi.
 // --------------------------------------------------------------------------
 template <int D, typename R>
-struct Rot {
-    R t[D][D];
+struct Rot;
+template <typename R>
+struct Rot<2, R> {       // T = [[c, s], [-s, c]]
+    R c, s;
+};
+template <typename R>
+struct Rot<3, R> {       // T = [[cp ct, cp st, sp], [-st, ct, 0], [-sp ct, -sp st, cp]]
+    R ct, st, cp, sp;
 };
 
+// T from the interface normal n, given 1/|n| (nonzero = false: n = 0, T = I)
 template <int D, typename R>
-__device__ __forceinline__ void make_rot(const R n[D], R inv_norm, Rot<D, R>& T)
+__device__ __forceinline__ void make_rot(const R n[D], R inv_norm, bool nonzero, Rot<D, R>& T)
 {
     if constexpr (D == 2) {
-        const R c = n[0] * inv_norm, s = n[1] * inv_norm;
-        T.t[0][0] = c;  T.t[0][1] = s;
-        T.t[1][0] = -s; T.t[1][1] = c;
+        T.c = nonzero ? n[0] * inv_norm : R(1);
+        T.s = nonzero ? n[1] * inv_norm : R(0);
     } else {
         const R r12sq = n[0] * n[0] + n[1] * n[1];
-        R ct = R(1), st = R(0), cp = R(0);
-        if (r12sq > R(0)) {
-            const R r12 = sqrt_pos(r12sq);
-            const R ir12 = rcp(r12);
-            ct = n[0] * ir12;
-            st = n[1] * ir12;
-            cp = r12 * inv_norm;
+        T.ct = R(1); T.st = R(0); T.cp = R(1); T.sp = R(0);
+        if (nonzero) {
+            T.cp = R(0);
+            if (r12sq > R(0)) {
+                const R ir12 = rsqrt_pos(r12sq);
+                T.ct = n[0] * ir12;
+                T.st = n[1] * ir12;
+                T.cp = (r12sq * ir12) * inv_norm;
+            }
+            T.sp = n[2] * inv_norm;
         }
-        const R sp = n[2] * inv_norm;
-        T.t[0][0] = cp * ct;  T.t[0][1] = cp * st;  T.t[0][2] = sp;
-        T.t[1][0] = -st;      T.t[1][1] = ct;       T.t[1][2] = R(0);
-        T.t[2][0] = -sp * ct; T.t[2][1] = -sp * st; T.t[2][2] = cp;
     }
 }
 
+// out = T in
 template <int D, typename R>
 __device__ __forceinline__ void rot_apply(const Rot<D, R>& T, const R in[D], R out[D])
 {
-#pragma unroll
-    for (int a = 0; a < D; a++) {
-        R s = R(0);
-#pragma unroll
-        for (int b = 0; b < D; b++) s += T.t[a][b] * in[b];
-        out[a] = s;
+    if constexpr (D == 2) {
+        out[0] = T.c * in[0] + T.s * in[1];
+        out[1] = T.c * in[1] - T.s * in[0];
+    } else {
+        const R a = T.ct * in[0] + T.st * in[1];
+        out[0] = T.cp * a + T.sp * in[2];
+        out[1] = T.ct * in[1] - T.st * in[0];
+        out[2] = T.cp * in[2] - T.sp * a;
     }
 }
 
+// out = T^T in
 template <int D, typename R>
 __device__ __forceinline__ void rot_apply_t(const Rot<D, R>& T, const R in[D], R out[D])
 {
-#pragma unroll
-    for (int a = 0; a < D; a++) {
-        R s = R(0);
-#pragma unroll
-        for (int b = 0; b < D; b++) s += T.t[b][a] * in[b];
-        out[a] = s;
+    if constexpr (D == 2) {
+        out[0] = T.c * in[0] - T.s * in[1];
+        out[1] = T.s * in[0] + T.c * in[1];
+    } else {
+        const R b = T.cp * in[0] - T.sp * in[2];
+        out[0] = T.ct * b - T.st * in[1];
+        out[1] = T.st * b + T.ct * in[1];
+        out[2] = T.sp * in[0] + T.cp * in[2];
     }
 }
 
@@ -296,37 +321,41 @@ struct Frame {
     R d11, d12, d21, d22;  // N = 2: D^Y scaled by sqrt(rho/(Gamma R))
 };
 
-// W = R^T y  (y = T V, nc components)
+// W = R^T y (y = T V) split into the tangential fields, W_{N+t} for
+// t = 1..D-1 from y_{N+t} and yE = y_{nc-1} ...
 template <int N, int D, typename R>
-__device__ __forceinline__ void frame_project(const Frame<N, D, R>& F, const R* y, R* W)
+__device__ __forceinline__ void frame_project_tan(const Frame<N, D, R>& F, const R* yt, R yE, R* Wt)
 {
-    constexpr int NC = N + D + 1;
-    const R yE = y[NC - 1];
-    R vdot = R(0);
+    const R sc = (N == 1) ? F.st : F.sq * F.c;
 #pragma unroll
-    for (int j = 0; j < D; j++) vdot += F.vh[j] * y[N + j];
+    for (int t = 1; t < D; t++) Wt[t - 1] = sc * (yt[t - 1] + F.vh[t] * yE);
+}
+
+// ... and the others, W_0..W_N and W_{nc-1} (in that order, N + 2 values),
+// from the species variables y_0..y_{N-1}, the normal momentum variable y_N,
+// vdot = vh.(y_N..y_{N+D-1}) and yE
+template <int N, int D, typename R>
+__device__ __forceinline__ void frame_project_main(const Frame<N, D, R>& F, const R* ysp, R yn, R vdot, R yE,
+                                                   R* Wm)
+{
     if constexpr (N == 1) {
-        const R base = y[0] + vdot;
-        const R gm = base - F.c * y[1] + (F.H - F.c * F.vh[0]) * yE;
-        const R gp = base + F.c * y[1] + (F.H + F.c * F.vh[0]) * yE;
+        const R base = ysp[0] + vdot;
+        const R gm = base - F.c * yn + (F.H - F.c * F.vh[0]) * yE;
+        const R gp = base + F.c * yn + (F.H + F.c * F.vh[0]) * yE;
         const R ge = base + F.K * yE;
-        W[0] = F.sa * gm;
-        W[1] = F.se * ge;
-#pragma unroll
-        for (int t = 1; t < D; t++) W[1 + t] = F.st * (y[1 + t] + F.vh[t] * yE);
-        W[NC - 1] = F.sa * gp;
+        Wm[0] = F.sa * gm;
+        Wm[1] = F.se * ge;
+        Wm[2] = F.sa * gp;
     } else {
-        const R ys = F.Y[0] * y[0] + F.Y[1] * y[1] + vdot;
-        const R gm = ys - F.c * y[2] + (F.H - F.c * F.vh[0]) * yE;
-        const R gp = ys + F.c * y[2] + (F.H + F.c * F.vh[0]) * yE;
-        const R g1 = y[0] + vdot + F.e2[0] * yE;
-        const R g2 = y[1] + vdot + F.e2[1] * yE;
-        W[0] = F.s2a * gm;
-        W[1] = F.d11 * g1 + F.d21 * g2;
-        W[2] = F.d12 * g1 + F.d22 * g2;
-#pragma unroll
-        for (int t = 1; t < D; t++) W[2 + t] = F.sq * F.c * (y[2 + t] + F.vh[t] * yE);
-        W[NC - 1] = F.s2a * gp;
+        const R ys = F.Y[0] * ysp[0] + F.Y[1] * ysp[1] + vdot;
+        const R gm = ys - F.c * yn + (F.H - F.c * F.vh[0]) * yE;
+        const R gp = ys + F.c * yn + (F.H + F.c * F.vh[0]) * yE;
+        const R g1 = ysp[0] + vdot + F.e2[0] * yE;
+        const R g2 = ysp[1] + vdot + F.e2[1] * yE;
+        Wm[0] = F.s2a * gm;
+        Wm[1] = F.d11 * g1 + F.d21 * g2;
+        Wm[2] = F.d12 * g1 + F.d22 * g2;
+        Wm[3] = F.s2a * gp;
     }
 }
 

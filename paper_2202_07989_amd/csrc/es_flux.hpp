@@ -102,17 +102,11 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
         n[j] = R(0.5) * (R(S.m[1 + j][iL]) + R(S.m[1 + j][iR]));
         nn2 += n[j] * n[j];
     }
-    const R nn = sqrt(nn2);
-    const R inn = nn > R(0) ? rcp(nn) : R(0);
+    const bool nz = nn2 > R(0);
+    const R inn = nz ? rsqrt_pos(nn2) : R(0);
+    const R nn = nn2 * inn;
     Rot<D, R> T;
-    if (nn > R(0)) {
-        make_rot<D, R>(n, inn, T);
-    } else {
-#pragma unroll
-        for (int a = 0; a < D; a++)
-#pragma unroll
-            for (int b = 0; b < D; b++) T.t[a][b] = R(a == b);
-    }
+    make_rot<D, R>(n, inn, nz, T);
     // averaged state
     R vbar[D];
     R vn = R(0);
@@ -174,41 +168,76 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
     }
     const R s = fabs(nt + vn) + nn * F.c;
 
-    // scaled entropy variables W_j = R^T T V(U_j), j = i-2..i+3
-    R W[6][NC];
-#pragma unroll
-    for (int t = 0; t < 6; t++) {
-        const int q = st[t];
-        const R bq = R(S.b[q]);
-        R vq[D], vr[D];
-        R v2 = R(0);
-#pragma unroll
-        for (int j = 0; j < D; j++) {
-            vq[j] = R(S.v[j][q]);
-            v2 += vq[j] * vq[j];
-        }
-        R y[NC];
-        const double lbq = S.lb[q];
-#pragma unroll
-        for (int l = 0; l < N; l++)
-            y[l] = R(ph.cv[l] * lbq + ph.Rg[l] * S.lrho[l][q] + ph.cvgam[l]) - R(0.5) * bq * v2;
-        rot_apply<D, R>(T, vq, vr);
-#pragma unroll
-        for (int j = 0; j < D; j++) y[N + j] = bq * vr[j];
-        y[NC - 1] = -bq;
-        frame_project<N, D, R>(F, y, W[t]);
-    }
-    // MR-WENO on each scaled characteristic field, sign matrix Y
+    // scaled entropy variables W_j = R^T T V(U_j) of the stencil nodes
+    // j = i-2..i+3, one group of characteristic fields at a time (the
+    // tangential fields, then the acoustic and species fields), each group's
+    // MR-WENO jumps taken as soon as its stencil values exist.  The acoustic
+    // and species fields see the rotated momentum variables only through
+    // (T vbar).(T b v) = b vbar.v and the normal row of T v.
     R Z[NC];
-#pragma unroll
-    for (int c = 0; c < NC; c++) {
+    // MR-WENO on one scaled characteristic field, sign matrix Y: the WENO
+    // jump and the jump agree in sign, and the jump is not zero to working
+    // precision (across a contact the acoustic jumps vanish up to rounding;
+    // those count as sign 0)
+    auto weno_field = [&](const R (&w)[6]) -> R {
         R jump;
-        const R jw = mr5_jump<R>(W[0][c], W[1][c], W[2][c], W[3][c], W[4][c], W[5][c], Wc, jump);
-        // sign matrix Y: the WENO jump and the jump agree in sign, and the jump
-        // is not zero to working precision (across a contact the acoustic
-        // jumps vanish up to rounding; those count as sign 0)
-        const bool y = (jw * jump > R(0)) && (fabs(jump) > Wc.zero_tol * (fabs(W[2][c]) + fabs(W[3][c])));
-        Z[c] = y ? jw : R(0);
+        const R jw = mr5_jump<R>(w[0], w[1], w[2], w[3], w[4], w[5], Wc, jump);
+        const bool y = (jw * jump > R(0)) && (fabs(jump) > Wc.zero_tol * (fabs(w[2]) + fabs(w[3])));
+        return y ? jw : R(0);
+    };
+    {
+        R Wt[D - 1][6];
+#pragma unroll
+        for (int t = 0; t < 6; t++) {
+            const int q = st[t];
+            const R bq = R(S.b[q]);
+            R vq[D], vr[D];
+#pragma unroll
+            for (int j = 0; j < D; j++) vq[j] = R(S.v[j][q]);
+            rot_apply<D, R>(T, vq, vr);
+            R yt[D - 1];
+#pragma unroll
+            for (int j = 1; j < D; j++) yt[j - 1] = bq * vr[j];
+            R wt[D - 1];
+            frame_project_tan<N, D, R>(F, yt, -bq, wt);
+#pragma unroll
+            for (int j = 0; j < D - 1; j++) Wt[j][t] = wt[j];
+        }
+#pragma unroll
+        for (int j = 0; j < D - 1; j++) Z[N + 1 + j] = weno_field(Wt[j]);
+    }
+    // the second group reloads its node values from LDS rather than keeping
+    // the first group's loads live across the first group's WENO
+    asm volatile("" ::: "memory");
+    {
+        constexpr int NM = N + 2;          // fields 0..N and NC - 1
+        R Wm[NM][6];
+#pragma unroll
+        for (int t = 0; t < 6; t++) {
+            const int q = st[t];
+            const R bq = R(S.b[q]);
+            R vq[D], vr[D];
+            R v2 = R(0), vbv = R(0);
+#pragma unroll
+            for (int j = 0; j < D; j++) {
+                vq[j] = R(S.v[j][q]);
+                v2 += vq[j] * vq[j];
+                vbv += vbar[j] * vq[j];
+            }
+            R ys[N];
+            const double lbq = S.lb[q];
+#pragma unroll
+            for (int l = 0; l < N; l++)
+                ys[l] = R(ph.cv[l] * lbq + ph.Rg[l] * S.lrho[l][q] + ph.cvgam[l]) - R(0.5) * bq * v2;
+            rot_apply<D, R>(T, vq, vr);
+            R wm[NM];
+            frame_project_main<N, D, R>(F, ys, bq * vr[0], bq * vbv, -bq, wm);
+#pragma unroll
+            for (int c = 0; c < NM; c++) Wm[c][t] = wm[c];
+        }
+#pragma unroll
+        for (int c = 0; c <= N; c++) Z[c] = weno_field(Wm[c]);
+        Z[NC - 1] = weno_field(Wm[N + 1]);
     }
     R RZ[NC];
     frame_expand<N, D, R>(F, Z, RZ);
@@ -239,40 +268,22 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
 // lidx(l, c) is the tile index of node l of line c, xidx(s, c) the X index
 // of slot s of line c, line_ok(c) whether line c exists; f_ok says that
 // this thread's interface (fi, fc) exists and its six nodes are loaded.
-// Every thread of the block must call this (it holds barriers).
-template <int N, int D, int NN, int TL, int TC, typename R, typename LI, typename XI, typename LOK>
+// With XALIAS, X overlays the node quantities of S (all but the metrics):
+// every flux is then formed in registers first and X is written only after
+// a barrier that ends all node reads.  Every thread of the block must call
+// this (it holds barriers).
+template <int N, int D, int NN, int TL, int TC, bool XALIAS, typename R, typename LI, typename XI,
+          typename LOK>
 __device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<N, D, NN>& S,
                                                  R (*X)[(TL + 4) * TC], LI lidx, XI xidx,
                                                  LOK line_ok, int fi, int fc, bool f_ok, int hid)
 {
     constexpr int NC = N + D + 1;
     const R a1 = R(ph.alpha[0]), a2 = R(ph.alpha[1]), a3 = R(ph.alpha[2]);
-    if (hid >= 0 && hid < 3 * TC) {
-        const int h = hid / TC, c = hid % TC;
-        const R am = (h == 2) ? a2 : a3;
-        const int slot = (h == 0) ? 0 : ((h == 1) ? 1 : TL + 3);
-        R F[NC];
-        if (line_ok(c) && am != R(0)) {
-            ec_pair<N, D, NN, R>(ph, S, lidx(h == 0 ? 0 : 1, c), lidx(h == 1 ? 4 : 3, c), F);
-        } else {
-#pragma unroll
-            for (int cc = 0; cc < NC; cc++) F[cc] = R(0);
-        }
-#pragma unroll
-        for (int cc = 0; cc < NC; cc++) X[cc][xidx(slot, c)] = am * F[cc];
-    }
     const int fl = fi + 2;
-    R G[NC], A2[NC];
+    R G[NC], A2[NC], B3[NC];
     if (f_ok) {
         R F[NC];
-        if (a3 != R(0)) {
-            ec_pair<N, D, NN, R>(ph, S, lidx(fl, fc), lidx(fl + 3, fc), F);
-        } else {
-#pragma unroll
-            for (int cc = 0; cc < NC; cc++) F[cc] = R(0);
-        }
-#pragma unroll
-        for (int cc = 0; cc < NC; cc++) X[cc][xidx(fi + 2, fc)] = a3 * F[cc];
         if (ph.dissipation) {
             Weno<R> Wc;
             Wc.chi1 = R(ph.chi[0]); Wc.chi2 = R(ph.chi[1]); Wc.chi3 = R(ph.chi[2]);
@@ -297,6 +308,41 @@ __device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<
         }
 #pragma unroll
         for (int cc = 0; cc < NC; cc++) A2[cc] = a2 * F[cc];
+        if (a3 != R(0)) {
+            ec_pair<N, D, NN, R>(ph, S, lidx(fl, fc), lidx(fl + 3, fc), F);
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) F[cc] = R(0);
+        }
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) B3[cc] = a3 * F[cc];
+    }
+    // the pairs F(0,3), F(1,4), F(1,3) left of the first interface
+    const bool halo = hid >= 0 && hid < 3 * TC;
+    R Bh[NC];
+    int hslot = 0, hc = 0;
+    if (halo) {
+        const int h = hid / TC;
+        hc = hid % TC;
+        const R am = (h == 2) ? a2 : a3;
+        hslot = (h == 0) ? 0 : ((h == 1) ? 1 : TL + 3);
+        if (line_ok(hc) && am != R(0)) {
+            ec_pair<N, D, NN, R>(ph, S, lidx(h == 0 ? 0 : 1, hc), lidx(h == 1 ? 4 : 3, hc), Bh);
+        } else {
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) Bh[cc] = R(0);
+        }
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) Bh[cc] = am * Bh[cc];
+    }
+    if constexpr (XALIAS) __syncthreads();   // node reads end before X overwrites them
+    if (halo) {
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) X[cc][xidx(hslot, hc)] = Bh[cc];
+    }
+    if (f_ok) {
+#pragma unroll
+        for (int cc = 0; cc < NC; cc++) X[cc][xidx(fi + 2, fc)] = B3[cc];
     }
     __syncthreads();
     R Hf[NC], Hm[NC];

@@ -38,7 +38,11 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
     constexpr int FA = (K == 0) ? 1 : 0;   // across index that runs fastest
     constexpr int SA = (K == 2) ? 1 : 2;   // slowest across index
     __shared__ NodeTile<N, D, NN> S;
-    __shared__ R X[NC][NX];
+    // the flux exchange overlays the node quantities (not the metrics, which
+    // the GCL term reads afterwards): 37 KB of LDS in all for two species in
+    // 3D, so four blocks share a compute unit
+    static_assert(sizeof(R) * NC * NX <= sizeof(S) - sizeof(S.m), "exchange does not fit the tile");
+    R (*X)[NX] = reinterpret_cast<R (*)[NX]>(&S.rho[0][0]);
 
     const long P = g.P;
     const int nK = g.n[K];
@@ -92,7 +96,7 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
     const int fc = t % TC;
     // node fi + 5 must be inside the padded grid (ragged last segment)
     const bool f_ok = (t < NI) && (line0 + fc < nlines) && (g.ng + seg0 + fi + 2 < g.np[K]);
-    interface_fluxes<N, D, NN, TL, TC, R>(ph, S, X, lidx, xidx,
+    interface_fluxes<N, D, NN, TL, TC, true, R>(ph, S, X, lidx, xidx,
                                           [&](int c) { return line0 + c < nlines; }, fi, fc, f_ok,
                                           t - (int)(blockIdx.x & 3) * 64);
 
@@ -121,7 +125,9 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
                 } else {
                     const double L = *o + d;
                     double* w = (rk.outU ? rk.outU : accU) + cc * P + gi;
-                    *w = rk.a * rk.JUn[cc * P + gi] + rk.b * (JU[cc * P + gi] + dt * L);
+                    // stage 0 has a = 0: Q_n is not read at all
+                    const double qn = rk.a != 0.0 ? rk.JUn[cc * P + gi] : 0.0;
+                    *w = rk.a * qn + rk.b * (JU[cc * P + gi] + dt * L);
                 }
             }
             if constexpr (MODE == MODE_WRITE) {
@@ -130,7 +136,8 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
                 accJ[gi] += dJ;
             } else {
                 const double L = accJ[gi] + dJ;
-                (rk.outJ ? rk.outJ : accJ)[gi] = rk.a * rk.Jn[gi] + rk.b * (Jv[gi] + dt * L);
+                const double qn = rk.a != 0.0 ? rk.Jn[gi] : 0.0;
+                (rk.outJ ? rk.outJ : accJ)[gi] = rk.a * qn + rk.b * (Jv[gi] + dt * L);
             }
         }
     }

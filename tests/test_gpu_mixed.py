@@ -12,6 +12,7 @@ magnitude per unit length is bounded by |U| times the wave speed)."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2202_07989_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -21,7 +22,7 @@ if not torch.cuda.is_available():
     pytest.skip("no HIP device", allow_module_level=True)
 
 from paper_2202_07989_amd import es  # noqa: E402
-from gpu_util import dev, host, parity, rhs_scale, state_scale, say  # noqa: E402
+from gpu_util import dev, ghosts, host, parity, rhs_scale, state_scale, say  # noqa: E402
 
 from cases import CASES, prepared  # noqa: E402
 
@@ -53,6 +54,45 @@ def test_rhs_mixed(name, dissipation):
     # dJ is the GCL term, FP64 in both paths
     assert parity(hJ[Iin], dJ[Iin], sJ) <= 1e-11
     assert ctx.es_status()[0] == es.ES_OK
+
+
+@pytest.mark.parametrize("eps", [1e-21, 1e-30])
+def test_rhs_nearly_axis_aligned_normals(eps):
+    """Normals of the z interfaces with tangential parts ~eps: the metrics of
+    a perturbed mesh with J dzeta/dx_1,2 replaced by eps times smooth fields
+    (the right-hand side takes any metrics).  In FP32 the square of the
+    tangential part is a denormal (eps = 1e-21) or underflows to zero
+    (eps = 1e-30), as near-cancelled metric residues of an almost uniform
+    mesh can be; the FP32 reciprocal square root estimate does not take
+    denormal operands.  FP64 meets its bar in both cases and the mixed path
+    stays finite; at eps = 1e-21 it also meets the mixed bar.  At 1e-30 the
+    FP32 tangential part is zero and the tangential basis of eq rotamatrix
+    falls back to theta = 0 while FP64 still follows atan2 of the tiny
+    normal, so the tangential dissipation legitimately differs there."""
+    say(f"[axis-aligned normals] eps={eps}")
+    sp = I.make_spec(3, 2, (16, 17, 18), gamma=(4.4, 1.4), cv=(1.0, 2.0), pinf=(100.0, 0.0),
+                     chi=I.CHI_SHOCK)
+    o = oracle.Oracle(sp)
+    JU, J, x = I.init_random(sp, seed=15, noise=0.3, p_range=(100.0, 300.0))
+    ghosts(o, JU, J, x)
+    jx, jt = o.metrics(x)
+    Iin = I.interior(sp)
+    xi = I.xi_nodes(sp)
+    jx[6][Iin[1:]] = eps * np.sin(2.0 * np.pi * xi[0] / (sp["n"][0] * sp["dxi"][0]))
+    jx[7][Iin[1:]] = eps * np.cos(2.0 * np.pi * xi[1] / (sp["n"][1] * sp["dxi"][1]))
+    o.fill_ghosts(jx, 9)
+    rc, dU, dJ = o.rhs(JU, J, jx, jt)
+    assert rc == 0
+    _, lam, _ = o.max_wavespeed(JU, J, jx, 1.0)
+    sU, _ = rhs_scale(JU, J, lam, Iin, sp)
+    for prec, tol in [(es.ES_FP64, 1e-11), (es.ES_MIXED, TOL_MIXED if eps > 1e-25 else None)]:
+        hU, _ = _rhs(es.Context(sp, precision=prec), JU, J, jx, jt)
+        assert np.isfinite(hU).all(), prec
+        errs = [parity(hU[c][Iin[1:]], dU[c][Iin[1:]], sU[c]) for c in range(o.nc)]
+        say(f"    precision {prec}: error / S_c {' '.join(f'{e:.1e}' for e in errs)}")
+        if tol is not None:
+            for c, e in enumerate(errs):
+                assert e <= tol, (prec, c, e)
 
 
 def test_mixed_really_rounds_in_fp32():
