@@ -114,6 +114,15 @@ def run_stage_only(ctx, mon, cfl, gU, gJ, gx, dt_dev, reps):
     print(json.dumps({"mode": "stage", "reps": reps, "copy_bytes_each_way": a.numel() * 8}), flush=True)
 
 
+def spec_for(args, I, n):
+    """The 3D two-species workload; --reconstruction js swaps in the classical
+    WENO5 of the comparison variant MM-WENOJS (epsilon 1e-6)."""
+    sp = I.spec_c3(n)
+    if getattr(args, "reconstruction", "mr") == "js":
+        sp["reconstruction"], sp["weno_eps"] = 1, 1e-6
+    return sp
+
+
 def run_precision(args, prec_name, n, steps, warmup, stage_reps):
     """Time whole steps and the fused stage of one precision; returns a dict."""
     import numpy as np
@@ -122,7 +131,7 @@ def run_precision(args, prec_name, n, steps, warmup, stage_reps):
     from paper_2202_07989_amd import es
     from paper_2202_07989_amd import inputs as I
 
-    sp = I.spec_c3(n)
+    sp = spec_for(args, I, n)
     prec = es.ES_MIXED if prec_name == "mixed" else es.ES_FP64
     JU, J, x = I.init_shock_bubble(sp)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -397,9 +406,14 @@ def main():
                          "accuracy: FP64 vs mixed (and vs an oracle reference file) after --steps steps; "
                          "batch: the 64-instance batched 2D form, FP64 and mixed, vs sequential launches")
     ap.add_argument("--count", type=int, default=64, help="batch mode: number of instances")
+    ap.add_argument("--reconstruction", choices=["mr", "js"], default="mr",
+                    help="step/stage modes: multi-resolution WENO (the method) or the classical "
+                         "WENO5 of the comparison variant MM-WENOJS")
     ap.add_argument("--oracle-ref", default=None,
                     help="accuracy mode: .npz written by the oracle's reference script")
     args = ap.parse_args()
+    if args.reconstruction == "js" and args.precision != "fp64":
+        ap.error("--reconstruction js runs in FP64 only (add --precision fp64)")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
@@ -420,7 +434,7 @@ def main():
         batch_study(args)
         return
     if args.mode == "stage":
-        sp = I.spec_c3(n)
+        sp = spec_for(args, I, n)
         prec = es.ES_MIXED if args.precision == "mixed" else es.ES_FP64
         JU, J, x = I.init_shock_bubble(sp)
         dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -456,8 +470,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"3D two-species stiffened-gas shock-bubble {n}^3, moving mesh "
                                "(5 Jacobi sweeps, 3 filter passes, alpha 1200), CFL 0.3, "
-                               "6th-order EC + MR-WENO5 ES flux, SSP-RK3",
-                   "grid": [n, n, n], "species": 2, "precision": main_prec},
+                               f"6th-order EC + {'MR-WENO5' if args.reconstruction == 'mr' else 'WENO5-JS'} "
+                               "ES flux, SSP-RK3",
+                   "grid": [n, n, n], "species": 2, "precision": main_prec,
+                   "reconstruction": args.reconstruction},
         "hbm_frac_of_peak_step": BYTES_PER_CELL_STAGE[key] * r["value"] / 1e9 / PEAK_HBM_GBS,
         "roofline": {"bound": "alu", "achieved": r["achieved"], "peak": r["peak"], "unit": "TFLOP/s",
                      "frac": r["achieved"] / r["peak"], "traffic": traffic,

@@ -51,6 +51,14 @@ enum { ES_ST_NONPHYS = 1u, ES_ST_TANGLE = 2u };
 
 enum { ES_FP64 = 0, ES_MIXED = 1 };
 
+/* interface reconstruction of the scaled entropy variables (Section 3.4):
+ * ES_WENO_MR, the multi-resolution WENO of Appendix A (MM-WENOMR), or
+ * ES_WENO_JS, the classical fifth-order WENO of Jiang and Shu that Section 5
+ * runs for comparison (MM-WENOJS; linear weights 1/10, 6/10, 3/10, weights
+ * d_k / (weno_eps + beta_k)^2; chi is not used).  ES_WENO_JS is FP64 only:
+ * with ES_MIXED, es_create and es_batch_create return ES_EUNSUPPORTED. */
+enum { ES_WENO_MR = 0, ES_WENO_JS = 1 };
+
 typedef struct {
     int dim;           /* d = 2 or 3                                            */
     int nspec;         /* N = 1 or 2                                            */
@@ -67,6 +75,7 @@ typedef struct {
     int dissipation;   /* 0: entropy-conservative scheme, 1: entropy-stable     */
     int precision;     /* ES_FP64, or ES_MIXED: FP32 flux/WENO arithmetic with  */
                        /* FP64 log means, metrics, mesh and entropy sums        */
+    int reconstruction;/* ES_WENO_MR or ES_WENO_JS (else ES_EUNSUPPORTED)       */
 } es_grid;
 
 typedef struct {

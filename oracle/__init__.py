@@ -35,6 +35,7 @@ class Grid(C.Structure):
         ("dxi", C.c_double * 3), ("len", C.c_double * 3), ("w", C.c_int),
         ("gamma", C.c_double * 2), ("cv", C.c_double * 2), ("pinf", C.c_double * 2),
         ("chi", C.c_double * 3), ("weno_eps", C.c_double), ("dissipation", C.c_int),
+        ("reconstruction", C.c_int),
     ]
 
 
@@ -69,6 +70,7 @@ def lib():
             "orc_rotation": (None, [_G, _D, _D]),
             "orc_interface_frame": (C.c_int, [_G, _D, _D, _D, _D, _D]),
             "orc_mr5": (C.c_double, [_D, _D, C.c_double]),
+            "orc_js5": (C.c_double, [_D, C.c_double]),
             "orc_npoints": (C.c_long, [_G]),
             "orc_fill_ghosts": (None, [_G, _D, C.c_int]),
             "orc_fill_ghosts_x": (None, [_G, _D]),
@@ -121,6 +123,7 @@ def grid(spec) -> Grid:
         g.chi[m] = spec["chi"][m]
     g.weno_eps = spec.get("weno_eps", 1e-10)
     g.dissipation = spec.get("dissipation", 1)
+    g.reconstruction = spec.get("reconstruction", 0)
     return g
 
 
@@ -199,6 +202,10 @@ class Oracle:
         args = [np.ascontiguousarray(a, dtype=np.float64) for a in (Ul, Ur, m)]
         self.L.orc_interface_frame(self.gp, *[_p(a) for a in args], _p(R), C.byref(s))
         return R, s.value
+
+    def js5(self, q, eps=None):
+        eps = self.g.weno_eps if eps is None else eps
+        return self.L.orc_js5(_p(np.ascontiguousarray(q, dtype=np.float64)), eps)
 
     def mr5(self, q, chi=None, eps=None):
         chi = np.array(self.spec["chi"] if chi is None else chi, dtype=np.float64)

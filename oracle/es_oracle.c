@@ -507,6 +507,38 @@ double orc_mr5(const double *q, const double *chi, double eps)
 }
 
 /* ------------------------------------------------------------------------ */
+/* The paper's comparison variant MM-WENOJS (Section 5) swaps the MR         */
+/* reconstruction for the classical fifth-order WENO of Jiang and Shu, cited */
+/* there.  Written from its published definition: the three third-order     */
+/* candidates on the sub-stencils {i-2..i}, {i-1..i+1}, {i..i+2} at the     */
+/* right face of node i, the smoothness indicators beta_k, and the weights   */
+/* alpha_k = d_k / (eps + beta_k)^2 normalised, d = (1/10, 6/10, 3/10).      */
+/* ------------------------------------------------------------------------ */
+double orc_js5(const double *q, double eps)
+{
+    double qm2 = q[0], qm1 = q[1], q0 = q[2], qp1 = q[3], qp2 = q[4];
+    double c[3], beta[3], alpha[3];
+    const double d[3] = {0.1, 0.6, 0.3};
+    c[0] = (2.0 * qm2 - 7.0 * qm1 + 11.0 * q0) / 6.0;
+    c[1] = (-qm1 + 5.0 * q0 + 2.0 * qp1) / 6.0;
+    c[2] = (2.0 * q0 + 5.0 * qp1 - qp2) / 6.0;
+    beta[0] = 13.0 / 12.0 * (qm2 - 2.0 * qm1 + q0) * (qm2 - 2.0 * qm1 + q0)
+            + 0.25 * (qm2 - 4.0 * qm1 + 3.0 * q0) * (qm2 - 4.0 * qm1 + 3.0 * q0);
+    beta[1] = 13.0 / 12.0 * (qm1 - 2.0 * q0 + qp1) * (qm1 - 2.0 * q0 + qp1)
+            + 0.25 * (qm1 - qp1) * (qm1 - qp1);
+    beta[2] = 13.0 / 12.0 * (q0 - 2.0 * qp1 + qp2) * (q0 - 2.0 * qp1 + qp2)
+            + 0.25 * (3.0 * q0 - 4.0 * qp1 + qp2) * (3.0 * q0 - 4.0 * qp1 + qp2);
+    double sa = 0.0;
+    for (int k = 0; k < 3; k++) {
+        alpha[k] = d[k] / ((eps + beta[k]) * (eps + beta[k]));
+        sa += alpha[k];
+    }
+    double v = 0.0;
+    for (int k = 0; k < 3; k++) v += alpha[k] / sa * c[k];
+    return v;
+}
+
+/* ------------------------------------------------------------------------ */
 /* ghost layers (periodic)                                                  */
 /* ------------------------------------------------------------------------ */
 static int wrap(const orc_grid *g, int k, int i, int *shift)
@@ -715,8 +747,8 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
     for (int c = 0; c < nc; c++) {
         double qm[5] = {W[0][c], W[1][c], W[2][c], W[3][c], W[4][c]};
         double qp[5] = {W[5][c], W[4][c], W[3][c], W[2][c], W[1][c]};
-        double Wminus = orc_mr5(qm, g->chi, g->weno_eps);
-        double Wplus = orc_mr5(qp, g->chi, g->weno_eps);
+        double Wminus = g->reconstruction ? orc_js5(qm, g->weno_eps) : orc_mr5(qm, g->chi, g->weno_eps);
+        double Wplus = g->reconstruction ? orc_js5(qp, g->weno_eps) : orc_mr5(qp, g->chi, g->weno_eps);
         double JW = Wplus - Wminus;
         double jump = W[3][c] - W[2][c];
         /* reading of sign(0) at working precision: a jump below 1e-12 of

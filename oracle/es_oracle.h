@@ -52,6 +52,8 @@ typedef struct {
     double chi[3];     /* MR-WENO linear weights                               */
     double weno_eps;   /* MR-WENO epsilon                                      */
     int dissipation;   /* 0: EC scheme, 1: ES scheme                           */
+    int reconstruction;/* 0: multi-resolution WENO (Appendix A), 1: classical  */
+                       /*    fifth-order WENO of Jiang and Shu (MM-WENOJS)     */
 } orc_grid;
 
 typedef struct {
@@ -83,6 +85,9 @@ void   orc_rotation(const orc_grid *g, const double *n, double *T);
 int    orc_interface_frame(const orc_grid *g, const double *Ul, const double *Ur,
                            const double *m, double *R, double *s);
 double orc_mr5(const double *q, const double *chi, double eps);
+/* classical fifth-order WENO (Jiang & Shu 1996) at the right face of q[2]
+ * from q[0..4], linear weights (1/10, 6/10, 3/10), alpha_k = d_k/(eps+beta_k)^2 */
+double orc_js5(const double *q, double eps);
 
 /* ---- whole-grid steps ----------------------------------------------------- */
 long   orc_npoints(const orc_grid *g);

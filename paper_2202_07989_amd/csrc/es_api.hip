@@ -69,6 +69,8 @@ int check_grid(const es_grid* g)
     if (g->nspec != 1 && g->nspec != 2) return ES_EUNSUPPORTED;
     if (g->w < 1 || g->w > 3 || g->ng < 3) return ES_EUNSUPPORTED;
     if (g->precision != ES_FP64 && g->precision != ES_MIXED) return ES_EUNSUPPORTED;
+    if (g->reconstruction != ES_WENO_MR && g->reconstruction != ES_WENO_JS) return ES_EUNSUPPORTED;
+    if (g->reconstruction == ES_WENO_JS && g->precision != ES_FP64) return ES_EUNSUPPORTED;
     for (int k = 0; k < g->dim; k++)
         if (g->n[k] < g->ng || !(g->dxi[k] > 0.0) || !(g->len[k] > 0.0)) return ES_EINVAL;
     if (g->dim == 2 && g->n[2] != 1) return ES_EINVAL;
@@ -91,6 +93,7 @@ void build_params(const es_grid* g, Phys& ph, Geo& geo)
     ph.nc = g->nspec + g->dim + 1;
     ph.w = g->w;
     ph.dissipation = g->dissipation ? 1 : 0;
+    ph.recon = g->reconstruction;
     for (int l = 0; l < g->nspec; l++) {
         ph.cv[l] = g->cv[l];
         ph.gam[l] = g->gamma[l];
@@ -105,7 +108,6 @@ void build_params(const es_grid* g, Phys& ph, Geo& geo)
     for (int m = 0; m < 3; m++) ph.alpha[m] = A[g->w - 1][m];
     for (int m = 0; m < 3; m++) ph.chi[m] = g->chi[m];
     ph.eps = g->weno_eps;
-    ph.ichi3 = 1.0 / g->chi[2];
     ph.r21 = g->nspec == 2 ? ph.Rg[1] / ph.Rg[0] : 1.0;
     ph.sr21 = sqrt(ph.r21);
     ph.isr21 = 1.0 / ph.sr21;
@@ -422,7 +424,7 @@ namespace {
 bool same_scheme(const es_grid& a, const es_grid& b)
 {
     if (a.dim != b.dim || a.nspec != b.nspec || a.ng != b.ng || a.w != b.w || a.precision != b.precision ||
-        a.dissipation != b.dissipation || a.weno_eps != b.weno_eps)
+        a.dissipation != b.dissipation || a.weno_eps != b.weno_eps || a.reconstruction != b.reconstruction)
         return false;
     for (int l = 0; l < a.nspec; l++)
         if (a.gamma[l] != b.gamma[l] || a.cv[l] != b.cv[l] || a.pinf[l] != b.pinf[l]) return false;
@@ -499,7 +501,7 @@ int es_batch_create(const es_grid* grids, int count, es_batch** out)
         rc = dalloc(&b->tiles[v], tl.size());
         if (!rc && hipMemcpy(b->tiles[v], tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
             rc = ES_EHIP;
-        if (!rc && batch_occupancy(b->ph.nspec, b->grid0.precision == ES_MIXED, T, &b->occ[v]) != hipSuccess)
+        if (!rc && batch_occupancy(b->ph.nspec, b->grid0.precision == ES_MIXED, b->ph.recon, T, &b->occ[v]) != hipSuccess)
             rc = ES_EHIP;
     }
     // wave-speed work list: blocks of about 4096 nodes

@@ -18,7 +18,7 @@
 
 namespace es {
 
-template <int N, int T, int NT, typename R>
+template <int N, int T, int NT, typename R, int RC>
 __global__ void __launch_bounds__(NT)
 k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict__ tiles, int ntiles,
                   BatchTables tb, double ca, double cb, const double* __restrict__ dt_dev,
@@ -79,9 +79,9 @@ k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict_
                 if (gx >= nx + 3 || gy >= ny + 3) continue;
                 const long gi = gidx(gx, gy);
                 const int li = lidx(lx, ly);
-                S.m[0][li] = jxt ? jxt[(long)K * P + gi] : 0.0;
+                S.m[0][li] = jxt ? 0.5 * jxt[(long)K * P + gi] : 0.0;
 #pragma unroll
-                for (int j = 0; j < D; j++) S.m[1 + j][li] = jxx[(long)(K * D + j) * P + gi];
+                for (int j = 0; j < D; j++) S.m[1 + j][li] = 0.5 * jxx[(long)(K * D + j) * P + gi];
             }
             __syncthreads();
             // line c of the sweep is row oy + c (K = 0) or column ox + c (K = 1);
@@ -93,7 +93,7 @@ k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict_
             const int fi = t % (T + 1), fc = t / (T + 1);
             // the interface's right stencil node fi + 5 (patch coordinate) must be loaded
             const bool f_ok = (t < NI) && (o_line + fc < nL) && (o_along + fi + 2 < nK + 3);
-            interface_fluxes<N, D, NN, T, T, false, R>(ph, S, X, tidx, xidx,
+            interface_fluxes<N, D, NN, T, T, false, RC, R>(ph, S, X, tidx, xidx,
                                                 [&](int c) { return o_line + c < nL; }, fi, fc, f_ok,
                                                 t - (int)((blockIdx.x + w) % NW) * 64);
             if (t < T * T) {
@@ -108,7 +108,7 @@ k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict_
                     // each direction's term is rounded on its own before it is
                     // added (separate statements, no fused multiply-add), as in
                     // the single-instance sweeps
-                    const double dJ = -0.5 * gcl * h;
+                    const double dJ = -gcl * h;   // S.m holds half the metrics
                     accJ = accJ + dJ;
 #pragma unroll
                     for (int cc = 0; cc < NC; cc++) {
@@ -157,14 +157,14 @@ k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict_
     if (bad) atomicOr(status, bad);
 }
 
-template <int N, typename R>
+template <int N, typename R, int RC>
 static hipError_t launch_variant(int T, const Phys& ph, const Geo* geos, const BatchTiling& tl,
                                  const BatchTables& tb, double ca, double cb, const double* dt_dev,
                                  unsigned* status, hipStream_t s)
 {
 #define ES_BATCH_CASE(T_, NT_)                                                                       \
     if (T == T_) {                                                                                   \
-        hipLaunchKernelGGL((k_stage2d_batched<N, T_, NT_, R>), dim3(tl.blocks), dim3(NT_), 0, s, ph, \
+        hipLaunchKernelGGL((k_stage2d_batched<N, T_, NT_, R, RC>), dim3(tl.blocks), dim3(NT_), 0, s, ph, \
                            geos, tl.tiles, tl.ntiles, tb, ca, cb, dt_dev, status);                   \
         return hipGetLastError();                                                                    \
     }
@@ -177,18 +177,18 @@ static hipError_t launch_variant(int T, const Phys& ph, const Geo* geos, const B
 
 int batch_threads(int T) { return T == 10 ? 128 : (T == 15 ? 256 : (T == 21 ? 512 : 0)); }
 
-hipError_t batch_occupancy(int nspec, int mixed, int T, int* blocks_per_cu)
+hipError_t batch_occupancy(int nspec, int mixed, int recon, int T, int* blocks_per_cu)
 {
-#define ES_OCC(N_, R_, T_, NT_)                                                                      \
-    if (nspec == N_ && (mixed != 0) == std::is_same<R_, float>::value && T == T_)                    \
+#define ES_OCC1(N_, R_, T_, NT_, RC_)                                                                \
+    if (nspec == N_ && (mixed != 0) == std::is_same<R_, float>::value && T == T_ && recon == RC_)     \
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,                          \
-                                                            k_stage2d_batched<N_, T_, NT_, R_>,     \
+                                                            k_stage2d_batched<N_, T_, NT_, R_, RC_>, \
                                                             NT_, 0);
-    ES_OCC(1, double, 10, 128) ES_OCC(1, double, 15, 256) ES_OCC(1, double, 21, 512)
-    ES_OCC(2, double, 10, 128) ES_OCC(2, double, 15, 256) ES_OCC(2, double, 21, 512)
-    ES_OCC(1, float, 10, 128) ES_OCC(1, float, 15, 256) ES_OCC(1, float, 21, 512)
-    ES_OCC(2, float, 10, 128) ES_OCC(2, float, 15, 256) ES_OCC(2, float, 21, 512)
+#define ES_OCC(N_, R_, RC_) ES_OCC1(N_, R_, 10, 128, RC_) ES_OCC1(N_, R_, 15, 256, RC_) ES_OCC1(N_, R_, 21, 512, RC_)
+    ES_OCC(1, double, 0) ES_OCC(2, double, 0) ES_OCC(1, float, 0) ES_OCC(2, float, 0)
+    ES_OCC(1, double, 1) ES_OCC(2, double, 1)   // classical WENO5: FP64 only
 #undef ES_OCC
+#undef ES_OCC1
     return hipErrorInvalidValue;
 }
 
@@ -197,11 +197,16 @@ hipError_t launch_stage_batched(const Phys& ph, const Geo* geos, int mixed, cons
                                 unsigned* status, hipStream_t s)
 {
     if (tl.ntiles == 0) return hipSuccess;
+    if (ph.recon == 1) {   // classical WENO5: FP64 only (checked at create)
+        if (mixed) return hipErrorInvalidValue;
+        return ph.nspec == 1 ? launch_variant<1, double, 1>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s)
+                             : launch_variant<2, double, 1>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s);
+    }
     if (ph.nspec == 1)
-        return mixed ? launch_variant<1, float>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s)
-                     : launch_variant<1, double>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s);
-    return mixed ? launch_variant<2, float>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s)
-                 : launch_variant<2, double>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s);
+        return mixed ? launch_variant<1, float, 0>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s)
+                     : launch_variant<1, double, 0>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s);
+    return mixed ? launch_variant<2, float, 0>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s)
+                 : launch_variant<2, double, 0>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s);
 }
 
 }  // namespace es

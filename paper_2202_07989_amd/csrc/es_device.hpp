@@ -14,11 +14,11 @@ namespace es {
 // --------------------------------------------------------------------------
 struct Phys {
     int nspec, dim, nc, w, dissipation;
+    int recon;                // 0: multi-resolution WENO, 1: classical WENO5 (Jiang-Shu)
     double cv[2], gam[2], pinf[2], Rg[2], cvgam[2];
     double pinf_tot;
     double alpha[3];          // alpha_{w,m}
     double chi[3], eps;       // MR-WENO linear weights and epsilon
-    double ichi3;             // 1/chi_3
     double r21;               // R_2 / R_1 (N = 2)
     double sr21, isr21;       // sqrt(R_2 / R_1) and its reciprocal
 };
@@ -177,15 +177,27 @@ __device__ __forceinline__ double inv_logmean(double a, double b, double la, dou
 //   h_3 - q_0 = (-2 D_0 + 11 D_1 + 24 D_2 - 3 D_3)/60,
 // and the value is q_0 + (w_2 (h_2 - q_0) + w_3 (hc - q_0)) / (w_1 + w_2 + w_3)
 // with hc - q_0 = ((h_3 - q_0) - chi_2 (h_2 - q_0)) / chi_3.  These equal the
-// Legendre forms exactly in rational arithmetic; the weights chi_m (1 + tau /
-// d_m), d_m = eps + beta_m, are taken over the common denominator
-// d_1 d_2 d_3 (one division for the normalised sum).
+// Legendre forms exactly in rational arithmetic.  The weights
+// w_m = chi_m (1 + tau / d_m), d_m = eps + beta_m, are taken over the common
+// denominator d_1 d_2 d_3 as chi_m e_m with e_m = (d_m + tau) prod_{l!=m} d_l,
+// and the linear weights are folded into the reconstructions:
+//   num = e_2 c_2 + e_3 c_3,  den = sum chi_m e_m,
+// with c_2 = chi_2 (h_2 - q_0) and c_3 = chi_3 (hc - q_0) = (h_3 - q_0) - c_2.
 // --------------------------------------------------------------------------
 template <typename R>
 struct Weno {
-    R chi1, chi2, chi3, eps, ichi3;
-    R zero_tol;   // relative size below which a jump counts as zero in the sign test
+    R chi1, chi2, chi3, eps;
+    R zero_tol;           // relative size below which a jump counts as zero in the sign test
 };
+
+template <typename R>
+__device__ __forceinline__ Weno<R> make_weno(const double chi[3], double eps, double zero_tol)
+{
+    Weno<R> W;
+    W.chi1 = R(chi[0]); W.chi2 = R(chi[1]); W.chi3 = R(chi[2]); W.eps = R(eps);
+    W.zero_tol = R(zero_tol);
+    return W;
+}
 
 // numerator and denominator of (value - q_0)
 template <typename R>
@@ -199,19 +211,48 @@ __device__ __forceinline__ void mr5_diff(R D0, R D1, R D2, R D3, const Weno<R>& 
                + R(781.0 / 20.0 / 144.0) * (u3 * u3) + R(1421461.0 / 2275.0 / 576.0) * (u4 * u4);
     R tau = fabs(b3 - b1) + fabs(b3 - b2);
     tau = R(0.25) * (tau * tau);
-    const R h2 = (D1 + R(2) * D2) * R(1.0 / 6.0);
-    const R h3 = (R(11) * D1 + R(24) * D2 - R(2) * D0 - R(3) * D3) * R(1.0 / 60.0);
-    const R hc = (h3 - W.chi2 * h2) * W.ichi3;
+    const R c2 = W.chi2 * (R(1.0 / 6.0) * D1 + R(1.0 / 3.0) * D2);
+    const R c3 = R(11.0 / 60.0) * D1 + R(0.4) * D2 - R(1.0 / 30.0) * D0 - R(0.05) * D3 - c2;
     R d1 = W.eps + b1, d2 = W.eps + b2, d3 = W.eps + b3;
     if constexpr (sizeof(R) == 4) {   // keep the products in float range
         const R dm = rcp(fmax(fmax(d1, d2), d3));
         d1 *= dm; d2 *= dm; d3 *= dm; tau *= dm;
     }
-    const R w1 = W.chi1 * (d1 + tau) * (d2 * d3);
-    const R w2 = W.chi2 * (d2 + tau) * (d1 * d3);
-    const R w3 = W.chi3 * (d3 + tau) * (d1 * d2);
-    num = w2 * h2 + w3 * hc;
-    den = w1 + w2 + w3;
+    const R e1 = (d1 + tau) * (d2 * d3);
+    const R e2 = (d2 + tau) * (d1 * d3);
+    const R e3 = (d3 + tau) * (d1 * d2);
+    num = e2 * c2 + e3 * c3;
+    den = W.chi1 * e1 + W.chi2 * e2 + W.chi3 * e3;
+}
+
+// Classical fifth-order WENO of Jiang and Shu (the comparison variant of
+// Section 5) in the same difference form, value - q_0 = num / den:
+//   candidates  c_0 = (5 D_1 - 2 D_0)/6, c_1 = (D_1 + 2 D_2)/6, c_2 = (4 D_2 - D_3)/6,
+//   beta_0 = 13/12 (D_1 - D_0)^2 + 1/4 (3 D_1 - D_0)^2,
+//   beta_1 = 13/12 (D_2 - D_1)^2 + 1/4 (D_1 + D_2)^2,
+//   beta_2 = 13/12 (D_3 - D_2)^2 + 1/4 (3 D_2 - D_3)^2,
+// weights d_k / e_k with e_k = (eps + beta_k)^2 and d = (1/10, 6/10, 3/10),
+// taken over the common denominator e_0 e_1 e_2.
+template <typename R>
+__device__ __forceinline__ void js5_diff(R D0, R D1, R D2, R D3, R eps, R& num, R& den)
+{
+    const R s0 = D1 - D0, t0 = R(3) * D1 - D0;
+    const R s1 = D2 - D1, t1 = D1 + D2;
+    const R s2 = D3 - D2, t2 = R(3) * D2 - D3;
+    R e0 = eps + (R(13.0 / 12.0) * (s0 * s0) + R(0.25) * (t0 * t0));
+    R e1 = eps + (R(13.0 / 12.0) * (s1 * s1) + R(0.25) * (t1 * t1));
+    R e2 = eps + (R(13.0 / 12.0) * (s2 * s2) + R(0.25) * (t2 * t2));
+    e0 *= e0; e1 *= e1; e2 *= e2;
+    if constexpr (sizeof(R) == 4) {   // keep the products in float range
+        const R em = rcp(fmax(fmax(e0, e1), e2));
+        e0 *= em; e1 *= em; e2 *= em;
+    }
+    const R p0 = R(0.1) * (e1 * e2), p1 = R(0.6) * (e0 * e2), p2 = R(0.3) * (e0 * e1);
+    const R c0 = (R(5) * D1 - R(2) * D0) * R(1.0 / 6.0);
+    const R c1 = (D1 + R(2) * D2) * R(1.0 / 6.0);
+    const R c2 = (R(4) * D2 - D3) * R(1.0 / 6.0);
+    num = p0 * c0 + p1 * c1 + p2 * c2;
+    den = p0 + p1 + p2;
 }
 
 // Jump of the two one-sided reconstructions at an interface, wp - wm, from
@@ -221,13 +262,19 @@ __device__ __forceinline__ void mr5_diff(R D0, R D1, R D2, R D3, const Weno<R>& 
 // wm = W_2 + Nm/Dm from (D_0, D_1, D_2, D_3) and wp = W_3 + Np/Dp from
 // (-D_4, -D_3, -D_2, -D_1), so wp - wm = D_2 + Np/Dp - Nm/Dm; FP64 takes the
 // two quotients over one denominator.  jump_out = W_3 - W_2 = D_2.
-template <typename R>
+// JS selects the classical reconstruction instead of MR.
+template <typename R, bool JS = false>
 __device__ __forceinline__ R mr5_jump(R q0, R q1, R q2, R q3, R q4, R q5, const Weno<R>& W, R& jump_out)
 {
     const R D0 = q1 - q0, D1 = q2 - q1, D2 = q3 - q2, D3 = q4 - q3, D4 = q5 - q4;
     R nm, dm, np, dp;
-    mr5_diff<R>(D0, D1, D2, D3, W, nm, dm);
-    mr5_diff<R>(-D4, -D3, -D2, -D1, W, np, dp);
+    if constexpr (JS) {
+        js5_diff<R>(D0, D1, D2, D3, W.eps, nm, dm);
+        js5_diff<R>(-D4, -D3, -D2, -D1, W.eps, np, dp);
+    } else {
+        mr5_diff<R>(D0, D1, D2, D3, W, nm, dm);
+        mr5_diff<R>(-D4, -D3, -D2, -D1, W, np, dp);
+    }
     jump_out = D2;
     if constexpr (sizeof(R) == 8) return D2 + (np * dm - nm * dp) * rcp(dp * dm);
     else return D2 + (np * rcp(dp) - nm * rcp(dm));
@@ -256,15 +303,19 @@ __device__ __forceinline__ void make_rot(const R n[D], R inv_norm, bool nonzero,
         T.c = nonzero ? n[0] * inv_norm : R(1);
         T.s = nonzero ? n[1] * inv_norm : R(0);
     } else {
-        const R r12sq = n[0] * n[0] + n[1] * n[1];
+        // the tangential part (n_1, n_2) and its length in FP64 in both
+        // precisions: in FP32 its square can be denormal (a nearly
+        // axis-aligned normal) and would carry only a few bits
+        const double a = n[0], b = n[1];
+        const double r12sq = a * a + b * b;
         T.ct = R(1); T.st = R(0); T.cp = R(1); T.sp = R(0);
         if (nonzero) {
             T.cp = R(0);
-            if (r12sq > R(0)) {
-                const R ir12 = rsqrt_pos(r12sq);
-                T.ct = n[0] * ir12;
-                T.st = n[1] * ir12;
-                T.cp = (r12sq * ir12) * inv_norm;
+            if (r12sq > 0.0) {
+                const double ir12 = rsqrt_pos(r12sq);
+                T.ct = R(a * ir12);
+                T.st = R(b * ir12);
+                T.cp = R(r12sq * ir12) * inv_norm;
             }
             T.sp = n[2] * inv_norm;
         }

@@ -17,7 +17,8 @@ struct NodeTile {
     double v[D][NN];       // velocity
     double b[NN];          // beta = 1/T
     double lb[NN];         // log beta
-    double m[D + 1][NN];   // metrics of direction k: n_t, n_1..n_D
+    double m[D + 1][NN];   // half the metrics of direction k: n_t/2, n_1/2..n_D/2 (an
+                           // interface average is then one sum; halving is exact)
 };
 
 // mixture Gamma, gas constant and pressure of tile node q (N = 2)
@@ -47,12 +48,12 @@ __device__ __forceinline__ void ec_pair(const Phys& ph, const NodeTile<N, D, NN>
                                         R* F)
 {
     constexpr int NC = N + D + 1;
-    const R nt = R(0.5) * (R(S.m[0][ia]) + R(S.m[0][ib]));
+    const R nt = R(S.m[0][ia]) + R(S.m[0][ib]);
     R n[D], vm[D];
     R vdn = R(0), v2 = R(0);
 #pragma unroll
     for (int j = 0; j < D; j++) {
-        n[j] = R(0.5) * (R(S.m[1 + j][ia]) + R(S.m[1 + j][ib]));
+        n[j] = R(S.m[1 + j][ia]) + R(S.m[1 + j][ib]);
         const R va = R(S.v[j][ia]), vb = R(S.v[j][ib]);
         vm[j] = R(0.5) * (va + vb);
         v2 += va * va + vb * vb;
@@ -87,7 +88,7 @@ __device__ __forceinline__ void ec_pair(const Phys& ph, const NodeTile<N, D, NN>
 // ES dissipation 1/2 s T^T R Y [[W]]^WENO at the interface between tile
 // nodes iL (= i) and iR (= i+1); st[t] are the tile indices of nodes
 // i-2..i+3.  Interface metrics, averages and R follow Section 3.4.
-template <int N, int D, int NN, typename R>
+template <int N, int D, int NN, int RC, typename R>
 __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D, NN>& S,
                                             const int st[6], const Weno<R>& Wc, R* Dout)
 {
@@ -95,11 +96,11 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
     const int iL = st[2], iR = st[3];
     // interface metric: mean of the two nodes
     R n[D];
-    const R nt = R(0.5) * (R(S.m[0][iL]) + R(S.m[0][iR]));
+    const R nt = R(S.m[0][iL]) + R(S.m[0][iR]);
     R nn2 = R(0);
 #pragma unroll
     for (int j = 0; j < D; j++) {
-        n[j] = R(0.5) * (R(S.m[1 + j][iL]) + R(S.m[1 + j][iR]));
+        n[j] = R(S.m[1 + j][iL]) + R(S.m[1 + j][iR]);
         nn2 += n[j] * n[j];
     }
     const bool nz = nn2 > R(0);
@@ -181,7 +182,7 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
     // those count as sign 0)
     auto weno_field = [&](const R (&w)[6]) -> R {
         R jump;
-        const R jw = mr5_jump<R>(w[0], w[1], w[2], w[3], w[4], w[5], Wc, jump);
+        const R jw = mr5_jump<R, RC == 1>(w[0], w[1], w[2], w[3], w[4], w[5], Wc, jump);
         const bool y = (jw * jump > R(0)) && (fabs(jump) > Wc.zero_tol * (fabs(w[2]) + fabs(w[3])));
         return y ? jw : R(0);
     };
@@ -268,11 +269,12 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
 // lidx(l, c) is the tile index of node l of line c, xidx(s, c) the X index
 // of slot s of line c, line_ok(c) whether line c exists; f_ok says that
 // this thread's interface (fi, fc) exists and its six nodes are loaded.
-// With XALIAS, X overlays the node quantities of S (all but the metrics):
+// RC selects the reconstruction of the dissipation (0: multi-resolution
+// WENO, 1: classical WENO5).  With XALIAS, X overlays the node quantities of S (all but the metrics):
 // every flux is then formed in registers first and X is written only after
 // a barrier that ends all node reads.  Every thread of the block must call
 // this (it holds barriers).
-template <int N, int D, int NN, int TL, int TC, bool XALIAS, typename R, typename LI, typename XI,
+template <int N, int D, int NN, int TL, int TC, bool XALIAS, int RC, typename R, typename LI, typename XI,
           typename LOK>
 __device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<N, D, NN>& S,
                                                  R (*X)[(TL + 4) * TC], LI lidx, XI xidx,
@@ -285,14 +287,11 @@ __device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<
     if (f_ok) {
         R F[NC];
         if (ph.dissipation) {
-            Weno<R> Wc;
-            Wc.chi1 = R(ph.chi[0]); Wc.chi2 = R(ph.chi[1]); Wc.chi3 = R(ph.chi[2]);
-            Wc.eps = R(ph.eps); Wc.ichi3 = R(ph.ichi3);
-            Wc.zero_tol = sizeof(R) == 8 ? R(1e-12) : R(4e-6);
+            const Weno<R> Wc = make_weno<R>(ph.chi, ph.eps, sizeof(R) == 8 ? 1e-12 : 4e-6);
             int st[6];
 #pragma unroll
             for (int q = 0; q < 6; q++) st[q] = lidx(fl - 2 + q, fc);
-            dissipation<N, D, NN, R>(ph, S, st, Wc, G);
+            dissipation<N, D, NN, RC, R>(ph, S, st, Wc, G);
         } else {
 #pragma unroll
             for (int cc = 0; cc < NC; cc++) G[cc] = R(0);

@@ -85,7 +85,7 @@ struct BatchTiling {
 };
 
 int batch_threads(int T);
-hipError_t batch_occupancy(int nspec, int mixed, int T, int* blocks_per_cu);
+hipError_t batch_occupancy(int nspec, int mixed, int recon, int T, int* blocks_per_cu);
 hipError_t launch_stage_batched(const Phys& ph, const Geo* geos, int mixed, const BatchTiling& tl,
                                 const BatchTables& tb, double ca, double cb, const double* dt_dev,
                                 unsigned* status, hipStream_t s);

@@ -20,7 +20,7 @@
 
 namespace es {
 
-template <int N, int D, int K, int TL, int TC, int MODE, typename R>
+template <int N, int D, int K, int TL, int TC, int MODE, typename R, int RC>
 __global__ void __launch_bounds__(256)
 k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restrict__ Jv,
           const double* __restrict__ jxx, const double* __restrict__ jxt,
@@ -84,9 +84,9 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
         const long gi = s_base[c] + along * sK;
         const int li = lidx(l, c);
         bad |= node_state<N, D, NN>(ph, S, li, JU, Jv, P, gi);
-        S.m[0][li] = jxt ? jxt[(long)K * P + gi] * itd : 0.0;
+        S.m[0][li] = jxt ? 0.5 * (jxt[(long)K * P + gi] * itd) : 0.0;
 #pragma unroll
-        for (int j = 0; j < D; j++) S.m[1 + j][li] = jxx[(long)(K * D + j) * P + gi];
+        for (int j = 0; j < D; j++) S.m[1 + j][li] = 0.5 * jxx[(long)(K * D + j) * P + gi];
     }
     if (bad) atomicOr(status, bad);
     __syncthreads();
@@ -96,7 +96,7 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
     const int fc = t % TC;
     // node fi + 5 must be inside the padded grid (ragged last segment)
     const bool f_ok = (t < NI) && (line0 + fc < nlines) && (g.ng + seg0 + fi + 2 < g.np[K]);
-    interface_fluxes<N, D, NN, TL, TC, true, R>(ph, S, X, lidx, xidx,
+    interface_fluxes<N, D, NN, TL, TC, true, RC, R>(ph, S, X, lidx, xidx,
                                           [&](int c) { return line0 + c < nlines; }, fi, fc, f_ok,
                                           t - (int)(blockIdx.x & 3) * 64);
 
@@ -113,7 +113,7 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
                 gcl += ph.alpha[m - 1] * (S.m[0][lidx(l + m, c)] - S.m[0][lidx(l - m, c)]);
             const long gi = s_base[c] + (g.ng + seg0 + lo) * sK;
             const double h = g.idxi[K];
-            const double dJ = -0.5 * gcl * h;
+            const double dJ = -gcl * h;   // S.m holds half the metrics
 #pragma unroll
             for (int cc = 0; cc < NC; cc++) {
                 const double d = -(double)(X[cc][xidx(lo + 2, c)] - X[cc][xidx(lo + 1, c)]) * h;
@@ -146,7 +146,7 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
 // --------------------------------------------------------------------------
 // host-side launch
 // --------------------------------------------------------------------------
-template <int N, int D, int K, int MODE, typename R>
+template <int N, int D, int K, int MODE, typename R, int RC>
 static hipError_t launch_dir(const Phys& ph, const Geo& g, const double* JU, const double* J,
                              const double* jxx, const double* jxt, double* accU, double* accJ,
                              const RkArgs& rk, unsigned* status, hipStream_t s)
@@ -159,29 +159,29 @@ static hipError_t launch_dir(const Phys& ph, const Geo& g, const double* JU, con
     const long nblk = nseg * ((nlines + TC - 1) / TC);
     if (nblk > 0x7fffffffL || nlines + TC > 0x7fffffffL) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)nblk);
-    hipLaunchKernelGGL((k_rhs_dir<N, D, K, TL, TC, MODE, R>), grid, dim3(256), 0, s, ph, g, JU, J,
+    hipLaunchKernelGGL((k_rhs_dir<N, D, K, TL, TC, MODE, R, RC>), grid, dim3(256), 0, s, ph, g, JU, J,
                        jxx, jxt, accU, accJ, rk, status);
     return hipGetLastError();
 }
 
-template <int N, int D, typename R>
+template <int N, int D, typename R, int RC>
 static hipError_t rhs_all(const Phys& ph, const Geo& g, const double* JU, const double* J,
                           const double* jxx, const double* jxt, double* outU, double* outJ,
                           const RkArgs* rk, unsigned* status, hipStream_t s)
 {
     RkArgs none{nullptr, nullptr, nullptr, 0.0, 0.0};
     if (rk) none.tdiv = rk->tdiv;
-    hipError_t e = launch_dir<N, D, 0, MODE_WRITE, R>(ph, g, JU, J, jxx, jxt, outU, outJ, none,
+    hipError_t e = launch_dir<N, D, 0, MODE_WRITE, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none,
                                                       status, s);
     if (e != hipSuccess) return e;
     if constexpr (D == 2) {
-        if (rk) return launch_dir<N, D, 1, MODE_RK, R>(ph, g, JU, J, jxx, jxt, outU, outJ, *rk, status, s);
-        return launch_dir<N, D, 1, MODE_ADD, R>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
+        if (rk) return launch_dir<N, D, 1, MODE_RK, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, *rk, status, s);
+        return launch_dir<N, D, 1, MODE_ADD, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
     } else {
-        e = launch_dir<N, D, 1, MODE_ADD, R>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
+        e = launch_dir<N, D, 1, MODE_ADD, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
         if (e != hipSuccess) return e;
-        if (rk) return launch_dir<N, D, 2, MODE_RK, R>(ph, g, JU, J, jxx, jxt, outU, outJ, *rk, status, s);
-        return launch_dir<N, D, 2, MODE_ADD, R>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
+        if (rk) return launch_dir<N, D, 2, MODE_RK, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, *rk, status, s);
+        return launch_dir<N, D, 2, MODE_ADD, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
     }
 }
 
@@ -189,10 +189,14 @@ hipError_t launch_rhs(const Phys& ph, const Geo& g, int mixed, const double* JU,
                       const double* jxx, const double* jxt, double* outU, double* outJ,
                       const RkArgs* rk, unsigned* status, hipStream_t s)
 {
-#define ES_RHS_CASE(NN_, DD_)                                                                     \
-    if (ph.nspec == NN_ && g.dim == DD_) {                                                        \
-        if (mixed) return rhs_all<NN_, DD_, float>(ph, g, JU, J, jxx, jxt, outU, outJ, rk, status, s); \
-        return rhs_all<NN_, DD_, double>(ph, g, JU, J, jxx, jxt, outU, outJ, rk, status, s);     \
+#define ES_RHS_CASE(NN_, DD_)                                                                          \
+    if (ph.nspec == NN_ && g.dim == DD_) {                                                             \
+        if (ph.recon == 1) {   /* classical WENO5: FP64 only (checked at create) */                 \
+            if (mixed) return hipErrorInvalidValue;                                                    \
+            return rhs_all<NN_, DD_, double, 1>(ph, g, JU, J, jxx, jxt, outU, outJ, rk, status, s);   \
+        }                                                                                              \
+        if (mixed) return rhs_all<NN_, DD_, float, 0>(ph, g, JU, J, jxx, jxt, outU, outJ, rk, status, s); \
+        return rhs_all<NN_, DD_, double, 0>(ph, g, JU, J, jxx, jxt, outU, outJ, rk, status, s);       \
     }
     ES_RHS_CASE(1, 2)
     ES_RHS_CASE(2, 2)

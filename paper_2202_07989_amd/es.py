@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libes.so")
 ES_OK, ES_EINVAL, ES_EUNSUPPORTED, ES_EHIP, ES_ENONPHYS, ES_ETANGLE = 0, -1, -2, -3, -4, -5
 ES_ST_NONPHYS, ES_ST_TANGLE = 1, 2
 ES_FP64, ES_MIXED = 0, 1
+ES_WENO_MR, ES_WENO_JS = 0, 1
 ES_METRICS_VCL_ONLY = 1
 
 
@@ -33,7 +34,7 @@ class EsGrid(C.Structure):
         ("dxi", C.c_double * 3), ("len", C.c_double * 3), ("w", C.c_int),
         ("gamma", C.c_double * 2), ("cv", C.c_double * 2), ("pinf", C.c_double * 2),
         ("chi", C.c_double * 3), ("weno_eps", C.c_double), ("dissipation", C.c_int),
-        ("precision", C.c_int),
+        ("precision", C.c_int), ("reconstruction", C.c_int),
     ]
 
 
@@ -123,6 +124,7 @@ def make_grid(spec, precision=ES_FP64) -> EsGrid:
         g.chi[m] = spec["chi"][m]
     g.weno_eps = spec.get("weno_eps", 1e-10)
     g.dissipation = spec.get("dissipation", 1)
+    g.reconstruction = spec.get("reconstruction", ES_WENO_MR)
     g.precision = precision
     return g
 

@@ -28,14 +28,14 @@ WATER_AIR = dict(gamma=(4.4, 1.4), cv=(1.0, 1.0), pinf=(6.0e8, 0.0))
 # workload specs
 # --------------------------------------------------------------------------
 def make_spec(dim, nspec, n, *, box=None, gamma=(1.4,), cv=(1.0,), pinf=(0.0,),
-              chi=CHI_DEFAULT, w=3, ng=3, dissipation=1, weno_eps=1e-10):
+              chi=CHI_DEFAULT, w=3, ng=3, dissipation=1, weno_eps=1e-10, reconstruction=0):
     n = tuple(n) + (1,) * (3 - len(n))
     box = box or (1.0,) * dim
     box = tuple(box) + (1.0,) * (3 - len(box))
     dxi = tuple(box[k] / n[k] if k < dim else 1.0 for k in range(3))
     return dict(dim=dim, nspec=nspec, n=n, ng=ng, dxi=dxi, len=box, w=w,
                 gamma=tuple(gamma), cv=tuple(cv), pinf=tuple(pinf), chi=tuple(chi),
-                weno_eps=weno_eps, dissipation=dissipation)
+                weno_eps=weno_eps, dissipation=dissipation, reconstruction=reconstruction)
 
 
 def spec_c1(n=64):

@@ -44,7 +44,8 @@ def test_invalid_arguments_rejected_before_any_launch(lib):
     h = C.c_void_p()
     for bad, code in (("dim", es.ES_EUNSUPPORTED), ("nspec", es.ES_EUNSUPPORTED), ("w", es.ES_EUNSUPPORTED),
                       ("ng", es.ES_EUNSUPPORTED), ("dxi", es.ES_EINVAL), ("gamma", es.ES_EINVAL),
-                      ("chi", es.ES_EINVAL), ("precision", es.ES_EUNSUPPORTED)):
+                      ("chi", es.ES_EINVAL), ("precision", es.ES_EUNSUPPORTED),
+                      ("reconstruction", es.ES_EUNSUPPORTED), ("js-mixed", es.ES_EUNSUPPORTED)):
         g = es.make_grid(sp)
         if bad == "dim":
             g.dim = 4
@@ -62,6 +63,10 @@ def test_invalid_arguments_rejected_before_any_launch(lib):
             g.chi[1] = -0.1
         elif bad == "precision":
             g.precision = 7
+        elif bad == "reconstruction":
+            g.reconstruction = 2
+        elif bad == "js-mixed":
+            g.reconstruction, g.precision = es.ES_WENO_JS, es.ES_MIXED
         assert es.lib.es_create(C.byref(g), C.byref(h)) == code, bad
     assert es.lib.es_create(None, C.byref(h)) == es.ES_EINVAL
     null = None

@@ -192,13 +192,15 @@ def test_ec_scheme_conserves_entropy(dim, nspec, pinf):
     assert abs(rate) < 1e-12 * entropy_scale(o, sp, JU, J, dJU, dJ)
 
 
+@pytest.mark.parametrize("recon", [0, 1])
 @pytest.mark.parametrize("dim,nspec,pinf", [(2, 1, (0.0,)), (2, 2, (6e8, 0.0)), (3, 2, (100.0, 0.0))])
-def test_es_scheme_entropy_production(dim, nspec, pinf):
+def test_es_scheme_entropy_production(dim, nspec, pinf, recon):
     """The ES flux adds -s/2 sum_m Y_mm [[W_m]][[W_m]]^WENO <= 0 per interface
-    (eq HOstable with the sign matrix), nothing else."""
+    (eq HOstable with the sign matrix), nothing else; with either
+    reconstruction (multi-resolution, or the classical WENO5 of MM-WENOJS)."""
     n = (14, 12) if dim == 2 else (8, 9, 7)
     kw = dict(gamma=(4.4, 1.4)[:nspec] if nspec == 2 else (1.4,), cv=(1.0, 2.0)[:nspec],
-              pinf=pinf, chi=I.CHI_SHOCK)
+              pinf=pinf, chi=I.CHI_SHOCK, reconstruction=recon, weno_eps=1e-6 if recon else 1e-10)
     sp_es = I.make_spec(dim, nspec, n, dissipation=1, **kw)
     sp_ec = I.make_spec(dim, nspec, n, dissipation=0, **kw)
     o_es, o_ec = oracle.Oracle(sp_es), oracle.Oracle(sp_ec)
@@ -251,13 +253,15 @@ def test_rhs_points_matches_rhs():
 
 
 # -- Section 5: design order on smooth advection (config-1 mesh) ---------------
-@pytest.mark.parametrize("dissipation,min_order", [(1, 4.5), (0, 5.0)])
-def test_design_order_smooth_advection(dissipation, min_order):
+@pytest.mark.parametrize("dissipation,recon,min_order", [(1, 0, 4.5), (0, 0, 5.0), (1, 1, 4.5)])
+def test_design_order_smooth_advection(dissipation, recon, min_order):
     T = 0.04
     errs = []
     for n in (16, 32, 64):
         sp = I.spec_c1(n)
         sp["dissipation"] = dissipation
+        if recon:
+            sp["reconstruction"], sp["weno_eps"] = recon, 1e-6
         o = oracle.Oracle(sp)
         JU, J, x = I.init_c1(sp)
         dt0 = 0.5 * (1.0 / n) ** (5.0 / 3.0)

@@ -430,6 +430,80 @@ def test_mr5_mirror_symmetry():
         assert o.mr5(q[::-1].copy(), I.CHI_SHOCK) == pytest.approx(o.mr5(qm, I.CHI_SHOCK), rel=1e-12, abs=1e-12)
 
 
+# -- Section 5 comparison variant: classical WENO5 (Jiang & Shu) ---------------
+def _cell_average_poly(q, cells):
+    """Polynomial of degree len(cells) - 1 whose averages over the unit cells
+    centred at the given offsets equal q at those offsets (q indexed from -2)."""
+    P = np.polynomial.Polynomial
+    deg = len(cells) - 1
+    A = np.array([[((j + 0.5) ** (e + 1) - (j - 0.5) ** (e + 1)) / (e + 1) for e in range(deg + 1)]
+                  for j in cells])
+    return P(np.linalg.solve(A, np.array([q[2 + j] for j in cells])))
+
+
+def _js_linear_weights():
+    """d_k with sum_k d_k p_k(1/2) = p_full(1/2) for every data set: solved
+    from the candidates' and the full stencil's face values as linear forms."""
+    E = np.eye(5)
+    full = np.array([_cell_average_poly(E[i], range(-2, 3))(0.5) for i in range(5)])
+    cand = np.array([[_cell_average_poly(E[i], range(k - 2, k + 1))(0.5) for i in range(5)] for k in range(3)])
+    d, *_ = np.linalg.lstsq(cand.T, full, rcond=None)
+    assert np.allclose(cand.T @ d, full, atol=1e-14)
+    return d
+
+
+def test_js5_linear_weights():
+    """The linear weights of the three quadratic candidates are (1/10, 6/10, 3/10)."""
+    assert np.allclose(_js_linear_weights(), [0.1, 0.6, 0.3], atol=1e-14)
+
+
+def test_js5_against_definition():
+    """Rebuild the classical WENO5 value from its definition: quadratic
+    candidates from the cell-average conditions on the three sub-stencils,
+    smoothness indicators as sum_l int over the central cell of the squared
+    l-th derivatives, weights d_k / (eps + beta_k)^2 normalised."""
+    o = oracle.Oracle(spec(2, 1))
+    d = _js_linear_weights()
+    rng = np.random.default_rng(24)
+    for eps in (1e-6, 1e-10):
+        for trial in range(200):
+            if trial % 3 == 0:
+                q = rng.uniform(-1, 1, 5)
+            elif trial % 3 == 1:
+                q = np.where(np.arange(5) < rng.integers(1, 5), 1.0, 0.0) + 1e-3 * rng.uniform(-1, 1, 5)
+            else:
+                q = np.sin(0.3 * np.arange(-2, 3) + rng.uniform(0, 6)) * 2
+            ps = [_cell_average_poly(q, range(k - 2, k + 1)) for k in range(3)]
+            beta = np.array([_beta_central(pk, 2) for pk in ps])
+            a = d / (eps + beta) ** 2
+            ref = float(np.dot(a / a.sum(), [pk(0.5) for pk in ps]))
+            got = o.js5(q, eps=eps)
+            assert got == pytest.approx(ref, rel=1e-9, abs=1e-9 * (np.abs(q).max() + 1e-300)), (q, eps)
+
+
+def test_js5_linear_limit_quartic_and_mirror():
+    """With eps >> beta the weights are linear: exact for cell averages of any
+    quartic at the right face; on the mirrored sequence, at the left face."""
+    o = oracle.Oracle(spec(2, 1))
+    rng = np.random.default_rng(25)
+    P = np.polynomial.Polynomial
+    for _ in range(20):
+        p = P(rng.uniform(-1, 1, 5))
+        ip = p.integ()
+        q = np.array([ip(j + 0.5) - ip(j - 0.5) for j in range(-2, 3)])
+        assert o.js5(q, eps=1e30) == pytest.approx(p(0.5), rel=1e-12, abs=1e-12)
+        assert o.js5(q[::-1].copy(), eps=1e30) == pytest.approx(p(-0.5), rel=1e-12, abs=1e-12)
+    assert o.js5(np.full(5, -2.5), eps=1e-6) == pytest.approx(-2.5, rel=1e-15)
+
+
+def test_js5_eno_at_a_step():
+    """At a step the weights of the candidates that straddle it vanish: the
+    face value comes from the smooth sub-stencil (to O(eps^2) weight ratios)."""
+    o = oracle.Oracle(spec(2, 1))
+    assert abs(o.js5(np.array([0.0, 0.0, 0.0, 1.0, 1.0]), eps=1e-6)) < 1e-10
+    assert o.js5(np.array([0.0, 0.0, 1.0, 1.0, 1.0]), eps=1e-6) == pytest.approx(1.0, abs=1e-10)
+
+
 # -- Section 5: SSP-RK3 ----------------------------------------------------------
 def test_rk3_stability_polynomial_and_abscissae():
     o = oracle.Oracle(spec(2, 1))
