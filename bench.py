@@ -273,6 +273,79 @@ def accuracy_study(args):
     print(json.dumps(out), flush=True)
 
 
+def vortex_study(args):
+    """The isentropic-vortex workloads (Section 5, Examples 5.1 and 5.5) on a
+    moving mesh with the gradient + Laplacian monitor: l1 and linf errors in
+    rho against the exact solution at the nodes, and their orders, 2D at
+    t = 4 (N = 40..320) and 3D at t = 0.1 (N = 20..160), with the time step
+    C_CFL (Delta xi / L)^(5/3); then the total entropy sum_i J eta dV of the
+    EC and ES schemes over time at 2D N = 160."""
+    import numpy as np
+    import torch
+
+    from paper_2202_07989_amd import es
+    from paper_2202_07989_amd import inputs as I
+
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    def run(dim, n, t_end, dissipation=1, n_entropy=0, move=True):
+        sp = I.spec_vortex(dim, n)
+        sp["dissipation"] = dissipation
+        JU, J, x = I.init_vortex(sp)
+        ctx = es.Context(sp)
+        gU, gJ, gx = dev(JU), dev(J), dev(x)
+        ctx.es_fill_ghosts(gU, 2 + dim)
+        ctx.es_fill_ghosts(gJ, 1)
+        ctx.es_fill_ghosts_x(gx)
+        mon = I.vortex_monitor()
+        dt0 = (0.4 if dim == 2 else 0.3) * (1.0 / n) ** (5.0 / 3.0)
+        ns = int(np.ceil(t_end / dt0))
+        dt = t_end / ns
+        ent = torch.zeros(1, dtype=torch.float64, device="cuda")
+        series = []
+        every = max(1, ns // n_entropy) if n_entropy else 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(ns):
+            if every and s % every == 0:
+                ctx.es_entropy(gU, gJ, ent)
+                series.append((s * dt, float(ent.item())))
+            ctx.es_step(gU, gJ, gx, mon=mon if move else None, dt_fixed=dt, move_mesh=move)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if every:
+            ctx.es_entropy(gU, gJ, ent)
+            series.append((ns * dt, float(ent.item())))
+        rc, _ = ctx.es_status()
+        Iin = I.interior(sp)
+        hU, hJ, hx = (a.cpu().numpy() for a in (gU, gJ, gx))
+        rho = hU[Iin][0] / hJ[Iin][0]
+        ex, _, _ = I.vortex_prims(dim, [hx[Iin][k] for k in range(dim)], t_end)
+        err = np.abs(rho - ex)
+        print(f"[vortex] {dim}D N={n} {'moving' if move else 'fixed'} steps={ns} l1={err.mean():.3e} "
+              f"linf={err.max():.3e} "
+              f"{wall:.1f}s status={rc}", file=sys.stderr, flush=True)
+        return dict(n=n, steps=ns, l1=float(err.mean()), linf=float(err.max()), ms_per_step=1e3 * wall / ns,
+                    status=rc), series
+
+    out = {"mode": "vortex"}
+    for dim, t_end, Ns, move in ((2, 4.0, (40, 80, 160, 320), True), (2, 4.0, (40, 80, 160, 320), False),
+                                 (3, 0.1, (20, 40, 80, 160), True)):
+        rows = [run(dim, n, t_end, move=move)[0] for n in Ns]
+        for a, b in zip(rows[:-1], rows[1:]):
+            b["order_l1"] = float(np.log2(a["l1"] / b["l1"]))
+            b["order_linf"] = float(np.log2(a["linf"] / b["linf"]))
+        out[f"{dim}d_{'moving' if move else 'fixed'}"] = {"t": t_end, "rows": rows}
+    ent = {}
+    for name, diss in (("EC", 0), ("ES", 1)):
+        _, series = run(2, 160, 4.0, dissipation=diss, n_entropy=40)
+        ent[name] = series
+    out["entropy_2d_160"] = {k: {"t": [t for t, _ in v], "total": [e for _, e in v],
+                                 "rel_change_end": (v[-1][1] - v[0][1]) / abs(v[0][1])}
+                             for k, v in ent.items()}
+    print(json.dumps(out), flush=True)
+
+
 def batch_study(args):
     """The batched form: 64 independent 2D two-species instances of uneven
     size (seeded, 128^2..1024^2, 4-quadrant Riemann data, fixed uniform
@@ -400,11 +473,12 @@ def main():
                     help="both: FP64 gives the reported value, the mixed form is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=10)
-    ap.add_argument("--mode", choices=["step", "stage", "accuracy", "batch"], default="step",
+    ap.add_argument("--mode", choices=["step", "stage", "accuracy", "batch", "vortex"], default="step",
                     help="stage: only the fused-RK-stage loop and a 2 GiB device copy (for "
                          "rocprofv3 counter runs; the copy calibrates FETCH_SIZE/WRITE_SIZE); "
                          "accuracy: FP64 vs mixed (and vs an oracle reference file) after --steps steps; "
-                         "batch: the 64-instance batched 2D form, FP64 and mixed, vs sequential launches")
+                         "batch: the 64-instance batched 2D form, FP64 and mixed, vs sequential launches; "
+                         "vortex: the isentropic-vortex convergence and entropy studies")
     ap.add_argument("--count", type=int, default=64, help="batch mode: number of instances")
     ap.add_argument("--reconstruction", choices=["mr", "js"], default="mr",
                     help="step/stage modes: multi-resolution WENO (the method) or the classical "
@@ -432,6 +506,9 @@ def main():
         return
     if args.mode == "batch":
         batch_study(args)
+        return
+    if args.mode == "vortex":
+        vortex_study(args)
         return
     if args.mode == "stage":
         sp = spec_for(args, I, n)

@@ -84,7 +84,18 @@ typedef struct {
     double alpha[4];   /* alpha_k >= 0                                          */
     int n_smooth;      /* low-pass filter passes                                */
     int n_sweeps;      /* Jacobi iterations mu (1..4096)                        */
+    int form;          /* ES_MONITOR_GRAD2 or ES_MONITOR_GRAD_LAP (below)       */
+    double beta[4];    /* Laplacian weights of ES_MONITOR_GRAD_LAP, >= 0        */
 } es_monitor;
+
+/* monitor forms: ES_MONITOR_GRAD2 is eq monitor, Theta = (1 + sum_k alpha_k
+ * (|grad sigma_k| / max|grad sigma_k|)^2)^(1/2); ES_MONITOR_GRAD_LAP is the
+ * form of the isentropic-vortex examples (Section 5), Theta = (1 + sum_k
+ * alpha_k |grad sigma_k| / max|grad sigma_k| + beta_k |lap sigma_k| /
+ * max|lap sigma_k|)^(1/2), at most two variables.  grad and lap are
+ * second-order central differences in xi; a term whose maximum is 0 is
+ * dropped. */
+enum { ES_MONITOR_GRAD2 = 0, ES_MONITOR_GRAD_LAP = 1 };
 
 typedef struct es_ctx es_ctx;
 

@@ -42,7 +42,7 @@ class Grid(C.Structure):
 class Monitor(C.Structure):
     _fields_ = [
         ("nsig", C.c_int), ("sigma", C.c_int * 4), ("alpha", C.c_double * 4),
-        ("n_smooth", C.c_int), ("n_sweeps", C.c_int),
+        ("n_smooth", C.c_int), ("n_sweeps", C.c_int), ("form", C.c_int), ("beta", C.c_double * 4),
     ]
 
 
@@ -137,6 +137,9 @@ def monitor(spec) -> Monitor:
         m.alpha[t] = al[t]
     m.n_smooth = spec.get("n_smooth", 3)
     m.n_sweeps = spec.get("n_sweeps", 10)
+    m.form = spec.get("form", 0)
+    for t, b in enumerate(spec.get("beta", [])):
+        m.beta[t] = b
     return m
 
 

@@ -729,7 +729,8 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
     double R[MAXC * MAXC], s, Tv[3][3];
     frame_of(g, &q[2], &q[3], mbar, R, &s, Tv);
 
-    double W[6][MAXC];
+    double W[6][MAXC], Wmag[MAXC];
+    for (int c = 0; c < nc; c++) Wmag[c] = 0.0;
     for (int t = 0; t < 6; t++) {
         double V[MAXC], TV[MAXC];
         entropy_vars_of(g, &q[t], V);
@@ -741,6 +742,9 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
         for (int c = 0; c < nc; c++) {
             W[t][c] = 0.0;
             for (int e = 0; e < nc; e++) W[t][c] += R[e * nc + c] * TV[e];   /* R^T */
+            /* size of the terms that make W_i and W_{i+1} (the jump's nodes) */
+            if (t == 2 || t == 3)
+                for (int e = 0; e < nc; e++) Wmag[c] += fabs(R[e * nc + c]) * fabs(TV[e]);
         }
     }
     double Z[MAXC], pr = 0.0;
@@ -752,9 +756,11 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
         double JW = Wplus - Wminus;
         double jump = W[3][c] - W[2][c];
         /* reading of sign(0) at working precision: a jump below 1e-12 of
-           |W_i| + |W_{i+1}| is zero (across a contact the acoustic jumps
-           vanish up to rounding), so Y_mm = 0 there */
-        int Y = (JW * jump > 0.0) && (fabs(jump) > 1.0e-12 * (fabs(W[2][c]) + fabs(W[3][c])));
+           the size of the terms that form W_i and W_{i+1}, sum_e |R_ec|
+           |(T V)_e| at both nodes, is zero (across a contact the acoustic
+           jumps vanish up to rounding, in an isentropic flow the entropy
+           field's jumps do), so Y_mm = 0 there */
+        int Y = (JW * jump > 0.0) && (fabs(jump) > 1.0e-12 * Wmag[c]);
         Z[c] = Y ? JW : 0.0;
         if (Y) pr += 0.5 * s * jump * JW;
     }
@@ -927,6 +933,11 @@ int orc_max_wavespeed(const orc_grid *g, const double *JU, const double *J,
 /* Monitor (eq monitor): Theta = (1 + sum_k alpha_k (|grad sigma_k| /        */
 /*   max |grad sigma_k|)^2)^(1/2).  Readings: grad_xi by second-order       */
 /*   central differences; a term whose max is 0 is dropped.                 */
+/* Form 1, the monitor of the isentropic-vortex examples (Section 5):       */
+/*   Theta = (1 + sum_k alpha_k |grad sigma_k| / max |grad sigma_k|          */
+/*   + beta_k |lap sigma_k| / max |lap sigma_k|)^(1/2), lap_xi by the        */
+/*   second-order central difference sum_k (s_{i+e_k} - 2 s_i + s_{i-e_k})  */
+/*   / dxi_k^2 (the same reading as grad_xi).                               */
 /* Low-pass filter (Remark 4.1): Theta <- sum_{j in {0,+-1}^d}               */
 /*   (1/2)^(|j|_1 + d) Theta_{i+j}, applied n_smooth times out of place.     */
 /* Jacobi iteration: x^{[nu+1]}_i = sum_k (Theta_{k+1/2} x^{[nu]}_{i+e_k}    */
@@ -974,10 +985,12 @@ int orc_monitor_fn(const orc_grid *g, const orc_monitor *mo, const double *JU,
                    const double *J, double *theta)
 {
     if (!valid_grid(g) || !mo || mo->nsig < 1 || mo->nsig > 4) return ORC_EINVAL;
+    if (mo->form != 0 && (mo->form != 1 || mo->nsig > 2)) return ORC_EINVAL;
     long P = orc_npoints(g);
     int d = g->dim;
     double *grad = (double *)calloc((size_t)mo->nsig * P, sizeof(double));
-    double gmax[4] = {0, 0, 0, 0};
+    double *lap = (double *)calloc((size_t)mo->nsig * P, sizeof(double));
+    double gmax[4] = {0, 0, 0, 0}, lmax[4] = {0, 0, 0, 0};
     for (int s = 0; s < mo->nsig; s++)
         for (int i2 = lo_(g, 2); i2 < hi_(g, 2); i2++)
             for (int i1 = lo_(g, 1); i1 < hi_(g, 1); i1++)
@@ -992,20 +1005,33 @@ int orc_monitor_fn(const orc_grid *g, const orc_monitor *mo, const double *JU,
                     }
                     grad[s * P + i] = sqrt(g2);
                     if (grad[s * P + i] > gmax[s]) gmax[s] = grad[s * P + i];
+                    if (mo->form == 1) {
+                        double sc = sigma_at(g, JU, J, i, mo->sigma[s]), l = 0.0;
+                        for (int k = 0; k < d; k++) {
+                            long st = stride_(g, k);
+                            l += (sigma_at(g, JU, J, i + st, mo->sigma[s]) - 2.0 * sc
+                                  + sigma_at(g, JU, J, i - st, mo->sigma[s])) / (g->dxi[k] * g->dxi[k]);
+                        }
+                        lap[s * P + i] = fabs(l);
+                        if (lap[s * P + i] > lmax[s]) lmax[s] = lap[s * P + i];
+                    }
                 }
     for (int i2 = lo_(g, 2); i2 < hi_(g, 2); i2++)
         for (int i1 = lo_(g, 1); i1 < hi_(g, 1); i1++)
             for (int i0 = lo_(g, 0); i0 < hi_(g, 0); i0++) {
                 long i = at(g, i0, i1, i2);
                 double th = 1.0;
-                for (int s = 0; s < mo->nsig; s++)
+                for (int s = 0; s < mo->nsig; s++) {
                     if (gmax[s] > 0.0) {
                         double r = grad[s * P + i] / gmax[s];
-                        th += mo->alpha[s] * r * r;
+                        th += mo->form == 1 ? mo->alpha[s] * r : mo->alpha[s] * r * r;
                     }
+                    if (mo->form == 1 && lmax[s] > 0.0) th += mo->beta[s] * (lap[s * P + i] / lmax[s]);
+                }
                 theta[i] = sqrt(th);
             }
     free(grad);
+    free(lap);
     orc_fill_ghosts(g, theta, 1);
     double *tmp = (double *)calloc(P, sizeof(double));
     for (int s = 0; s < mo->n_smooth; s++) {

@@ -62,6 +62,9 @@ typedef struct {
     double alpha[4];   /* alpha_k                                              */
     int n_smooth;      /* low-pass filter passes                               */
     int n_sweeps;      /* Jacobi iterations mu                                 */
+    int form;          /* 0: eq monitor; 1: the isentropic-vortex form with a  */
+                       /*    Laplacian term (Section 5), at most two variables */
+    double beta[4];    /* Laplacian weights of form 1                          */
 } orc_monitor;
 
 /* ---- pointwise pieces (exposed for the pins) ---------------------------- */

@@ -180,6 +180,8 @@ MonitorP monitor_params(const es_monitor* m)
     }
     mo.n_smooth = m->n_smooth;
     mo.n_sweeps = m->n_sweeps;
+    mo.form = m->form;
+    for (int s = 0; s < m->nsig; s++) mo.beta[s] = m->form == ES_MONITOR_GRAD_LAP ? m->beta[s] : 0.0;
     return mo;
 }
 
@@ -189,6 +191,12 @@ int check_monitor(const es_monitor* m)
         return ES_EINVAL;
     for (int s = 0; s < m->nsig; s++)
         if (m->sigma[s] < 0 || m->sigma[s] > 3 || !(m->alpha[s] >= 0.0)) return ES_EINVAL;
+    if (m->form != ES_MONITOR_GRAD2 && m->form != ES_MONITOR_GRAD_LAP) return ES_EINVAL;
+    if (m->form == ES_MONITOR_GRAD_LAP) {
+        if (m->nsig > 2) return ES_EINVAL;   // gradient and Laplacian maxima share four channels
+        for (int s = 0; s < m->nsig; s++)
+            if (!(m->beta[s] >= 0.0)) return ES_EINVAL;
+    }
     return ES_OK;
 }
 

@@ -410,6 +410,36 @@ __device__ __forceinline__ void frame_project_main(const Frame<N, D, R>& F, cons
     }
 }
 
+// size of the terms that make the fields of frame_project_main at one node,
+// sum_e |R_ec| |y_e| (R_ec the entries of R^T multiplying y_e), added to
+// Mm (same field order); yr holds all D rotated momentum variables
+template <int N, int D, typename R>
+__device__ __forceinline__ void frame_mag_main(const Frame<N, D, R>& F, const R* ysp, const R* yr, R yE, R* Mm)
+{
+    R vt = R(0);   // sum over the tangential rows of |vh_j| |y_{N+j}|
+#pragma unroll
+    for (int j = 1; j < D; j++) vt += fabs(F.vh[j]) * fabs(yr[j]);
+    const R aE = fabs(yE), a0 = fabs(yr[0]);
+    const R cv0 = F.c * F.vh[0];
+    if constexpr (N == 1) {
+        const R ay = fabs(ysp[0]);
+        Mm[0] += F.sa * (ay + fabs(F.vh[0] - F.c) * a0 + vt + fabs(F.H - cv0) * aE);
+        Mm[1] += F.se * (ay + fabs(F.vh[0]) * a0 + vt + fabs(F.K) * aE);
+        Mm[2] += F.sa * (ay + fabs(F.vh[0] + F.c) * a0 + vt + fabs(F.H + cv0) * aE);
+    } else {
+        const R ay0 = fabs(ysp[0]), ay1 = fabs(ysp[1]);
+        const R vall = fabs(F.vh[0]) * a0 + vt;
+        Mm[0] += F.s2a * (fabs(F.Y[0]) * ay0 + fabs(F.Y[1]) * ay1 + fabs(F.vh[0] - F.c) * a0 + vt +
+                          fabs(F.H - cv0) * aE);
+        Mm[1] += fabs(F.d11) * ay0 + fabs(F.d21) * ay1 + fabs(F.d11 + F.d21) * vall +
+                 fabs(F.d11 * F.e2[0] + F.d21 * F.e2[1]) * aE;
+        Mm[2] += fabs(F.d12) * ay0 + fabs(F.d22) * ay1 + fabs(F.d12 + F.d22) * vall +
+                 fabs(F.d12 * F.e2[0] + F.d22 * F.e2[1]) * aE;
+        Mm[3] += F.s2a * (fabs(F.Y[0]) * ay0 + fabs(F.Y[1]) * ay1 + fabs(F.vh[0] + F.c) * a0 + vt +
+                          fabs(F.H + cv0) * aE);
+    }
+}
+
 // out = R z
 template <int N, int D, typename R>
 __device__ __forceinline__ void frame_expand(const Frame<N, D, R>& F, const R* z, R* out)

@@ -178,16 +178,21 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
     R Z[NC];
     // MR-WENO on one scaled characteristic field, sign matrix Y: the WENO
     // jump and the jump agree in sign, and the jump is not zero to working
-    // precision (across a contact the acoustic jumps vanish up to rounding;
-    // those count as sign 0)
-    auto weno_field = [&](const R (&w)[6]) -> R {
+    // precision, i.e. above zero_tol times mag, the size of the terms that
+    // make W_i and W_{i+1} (sum_e |R_ec| |(T V)_e| at both nodes).  Across a
+    // contact the acoustic jumps vanish up to rounding, in an isentropic flow
+    // the entropy field's do; those count as sign 0.
+    auto weno_field = [&](const R (&w)[6], R mag) -> R {
         R jump;
         const R jw = mr5_jump<R, RC == 1>(w[0], w[1], w[2], w[3], w[4], w[5], Wc, jump);
-        const bool y = (jw * jump > R(0)) && (fabs(jump) > Wc.zero_tol * (fabs(w[2]) + fabs(w[3])));
+        const bool y = (jw * jump > R(0)) && (fabs(jump) > Wc.zero_tol * mag);
         return y ? jw : R(0);
     };
     {
-        R Wt[D - 1][6];
+        R Wt[D - 1][6], Mt[D - 1];
+        const R sct = (N == 1) ? F.st : F.sq * F.c;   // scale of the tangential columns
+#pragma unroll
+        for (int j = 0; j < D - 1; j++) Mt[j] = R(0);
 #pragma unroll
         for (int t = 0; t < 6; t++) {
             const int q = st[t];
@@ -204,8 +209,22 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
 #pragma unroll
             for (int j = 0; j < D - 1; j++) Wt[j][t] = wt[j];
         }
+        // term sizes at nodes i and i+1, from values reloaded from LDS (the
+        // loop's values are not kept live for them)
+        asm volatile("" ::: "memory");
 #pragma unroll
-        for (int j = 0; j < D - 1; j++) Z[N + 1 + j] = weno_field(Wt[j]);
+        for (int t = 2; t <= 3; t++) {
+            const int q = st[t];
+            const R bq = R(S.b[q]);
+            R vq[D], vr[D];
+#pragma unroll
+            for (int j = 0; j < D; j++) vq[j] = R(S.v[j][q]);
+            rot_apply<D, R>(T, vq, vr);
+#pragma unroll
+            for (int j = 0; j < D - 1; j++) Mt[j] += sct * (fabs(bq * vr[j + 1]) + fabs(F.vh[j + 1]) * fabs(bq));
+        }
+#pragma unroll
+        for (int j = 0; j < D - 1; j++) Z[N + 1 + j] = weno_field(Wt[j], Mt[j]);
     }
     // the second group reloads its node values from LDS rather than keeping
     // the first group's loads live across the first group's WENO
@@ -213,6 +232,36 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
     {
         constexpr int NM = N + 2;          // fields 0..N and NC - 1
         R Wm[NM][6];
+        float Mm[NM];   // threshold scales only: single precision suffices
+        {
+        R Ma[NM];
+#pragma unroll
+        for (int c = 0; c < NM; c++) Ma[c] = R(0);
+#pragma unroll
+        for (int t = 2; t <= 3; t++) {
+            const int q = st[t];
+            const R bq = R(S.b[q]);
+            R vq[D], yr[D];
+            R v2 = R(0);
+#pragma unroll
+            for (int j = 0; j < D; j++) {
+                vq[j] = R(S.v[j][q]);
+                v2 += vq[j] * vq[j];
+            }
+            R ys[N];
+            const double lbq = S.lb[q];
+#pragma unroll
+            for (int l = 0; l < N; l++)
+                ys[l] = R(ph.cv[l] * lbq + ph.Rg[l] * S.lrho[l][q] + ph.cvgam[l]) - R(0.5) * bq * v2;
+            rot_apply<D, R>(T, vq, yr);
+#pragma unroll
+            for (int j = 0; j < D; j++) yr[j] *= bq;
+            frame_mag_main<N, D, R>(F, ys, yr, -bq, Ma);
+        }
+#pragma unroll
+        for (int c = 0; c < NM; c++) Mm[c] = float(Ma[c]);
+        }
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int t = 0; t < 6; t++) {
             const int q = st[t];
@@ -237,8 +286,8 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
             for (int c = 0; c < NM; c++) Wm[c][t] = wm[c];
         }
 #pragma unroll
-        for (int c = 0; c <= N; c++) Z[c] = weno_field(Wm[c]);
-        Z[NC - 1] = weno_field(Wm[N + 1]);
+        for (int c = 0; c <= N; c++) Z[c] = weno_field(Wm[c], R(Mm[c]));
+        Z[NC - 1] = weno_field(Wm[N + 1], R(Mm[N + 1]));
     }
     R RZ[NC];
     frame_expand<N, D, R>(F, Z, RZ);
@@ -287,7 +336,10 @@ __device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<
     if (f_ok) {
         R F[NC];
         if (ph.dissipation) {
-            const Weno<R> Wc = make_weno<R>(ph.chi, ph.eps, sizeof(R) == 8 ? 1e-12 : 4e-6);
+            // zero tolerance of the sign test, relative to the size of the
+            // terms of W: ~4500 u in FP64; in FP32, where W carries about
+            // 3 u of that size in rounding, 1e-6 (~17 u)
+            const Weno<R> Wc = make_weno<R>(ph.chi, ph.eps, sizeof(R) == 8 ? 1e-12 : 1e-6);
             int st[6];
 #pragma unroll
             for (int q = 0; q < 6; q++) st[q] = lidx(fl - 2 + q, fc);

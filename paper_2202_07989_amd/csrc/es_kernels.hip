@@ -718,7 +718,9 @@ hipError_t entropy_sum(const Phys& ph, const Geo& g, const double* JU, const dou
 // mesh redistribution (Section 4)
 // ---------------------------------------------------------------------------
 // |grad_xi sigma| by second-order central differences, for each monitor
-// variable; per-block maxima into part[s * RED_BLOCKS + block]
+// variable; per-block maxima into part[s * RED_BLOCKS + block].  The form
+// with a Laplacian term also writes |lap_xi sigma| (second-order central
+// differences) as channel nsig + s.
 template <int N, int D>
 __device__ __forceinline__ double sigma_of(const Phys& ph, const double* JU, const double* Jv, long P,
                                            long i, int sig)
@@ -749,22 +751,30 @@ __global__ void k_monitor_grad(Phys ph, Geo g, MonitorP mo, const double* __rest
         int i0, i1, i2;
         const long i = interior_node(g, q, i0, i1, i2);
         for (int s = 0; s < mo.nsig; s++) {
-            double g2 = 0.0;
+            double g2 = 0.0, lap = 0.0;
+            const double sc = mo.form ? sigma_of<N, D>(ph, JU, Jv, P, i, mo.sigma[s]) : 0.0;
 #pragma unroll
             for (int k = 0; k < D; k++) {
                 const long st = dir_stride(g, k);
-                const double dk = (sigma_of<N, D>(ph, JU, Jv, P, i + st, mo.sigma[s]) -
-                                   sigma_of<N, D>(ph, JU, Jv, P, i - st, mo.sigma[s])) / (2.0 * g.dxi[k]);
+                const double sp = sigma_of<N, D>(ph, JU, Jv, P, i + st, mo.sigma[s]);
+                const double sm = sigma_of<N, D>(ph, JU, Jv, P, i - st, mo.sigma[s]);
+                const double dk = (sp - sm) / (2.0 * g.dxi[k]);
                 g2 += dk * dk;
+                lap += (sp - 2.0 * sc + sm) / (g.dxi[k] * g.dxi[k]);
             }
             const double gv = sqrt(g2);
             grad[s * P + i] = gv;
             gm[s] = fmax(gm[s], gv);
+            if (mo.form) {
+                grad[(mo.nsig + s) * P + i] = fabs(lap);
+                gm[mo.nsig + s] = fmax(gm[mo.nsig + s], fabs(lap));
+            }
         }
     }
+    const int nch = mo.form ? 2 * mo.nsig : mo.nsig;
     for (int s = 0; s < 4; s++) {
         const double r = block_reduce<RED_MAX>(gm[s]);
-        if (threadIdx.x == 0 && s < mo.nsig) part[s * RED_BLOCKS + blockIdx.x] = r;
+        if (threadIdx.x == 0 && s < nch) part[s * RED_BLOCKS + blockIdx.x] = r;
     }
 }
 
@@ -798,23 +808,33 @@ k_monitor_grad3(Phys ph, Geo g, MonitorP mo, const double* __restrict__ JU, cons
             double s0 = sigma_of<N, D>(ph, JU, Jv, P, i, sg);
             for (int z = zc0; z < zc1; z++, i += sz) {
                 const double sp = sigma_of<N, D>(ph, JU, Jv, P, i + sz, sg);
-                const double d0 = (sigma_of<N, D>(ph, JU, Jv, P, i + 1, sg) -
-                                   sigma_of<N, D>(ph, JU, Jv, P, i - 1, sg)) * ih[0];
-                const double d1 = (sigma_of<N, D>(ph, JU, Jv, P, i + sy, sg) -
-                                   sigma_of<N, D>(ph, JU, Jv, P, i - sy, sg)) * ih[1];
+                const double xp = sigma_of<N, D>(ph, JU, Jv, P, i + 1, sg);
+                const double xm = sigma_of<N, D>(ph, JU, Jv, P, i - 1, sg);
+                const double yp = sigma_of<N, D>(ph, JU, Jv, P, i + sy, sg);
+                const double ym = sigma_of<N, D>(ph, JU, Jv, P, i - sy, sg);
+                const double d0 = (xp - xm) * ih[0];
+                const double d1 = (yp - ym) * ih[1];
                 const double d2 = (sp - sm) * ih[2];
                 const double gv = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
                 grad[s * P + i] = gv;
                 gm[s] = fmax(gm[s], gv);
+                if (mo.form) {   // the same sum as k_monitor_grad: directions 0, 1, 2 in order
+                    double lap = (xp - 2.0 * s0 + xm) / (g.dxi[0] * g.dxi[0]);
+                    lap += (yp - 2.0 * s0 + ym) / (g.dxi[1] * g.dxi[1]);
+                    lap += (sp - 2.0 * s0 + sm) / (g.dxi[2] * g.dxi[2]);
+                    grad[(mo.nsig + s) * P + i] = fabs(lap);
+                    gm[mo.nsig + s] = fmax(gm[mo.nsig + s], fabs(lap));
+                }
                 sm = s0;
                 s0 = sp;
             }
         }
     }
     const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const int nch = mo.form ? 2 * mo.nsig : mo.nsig;
     for (int s = 0; s < 4; s++) {
         const double r = block_reduce<RED_MAX>(gm[s]);
-        if (threadIdx.x == 0 && s < mo.nsig) part[s * RED_BLOCKS + blk] = r;
+        if (threadIdx.x == 0 && s < nch) part[s * RED_BLOCKS + blk] = r;
     }
 }
 
@@ -860,8 +880,10 @@ __global__ void k_theta(Geo g, MonitorP mo, const double* __restrict__ grad, con
             const double G = gmax[s];
             if (G > 0.0) {
                 const double r = grad[s * P + i] / G;
-                th += mo.alpha[s] * r * r;
+                th += mo.form ? mo.alpha[s] * r : mo.alpha[s] * r * r;
             }
+            if (mo.form && gmax[mo.nsig + s] > 0.0)
+                th += mo.beta[s] * (grad[(mo.nsig + s) * P + i] / gmax[mo.nsig + s]);
         }
         theta[i] = sqrt(th);
     }
@@ -1060,7 +1082,7 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, c
         hipLaunchKernelGGL(k_monitor_grad3<2>, jgrid, dim3(256), 0, s, ph, g, mo, JU, J, w.grad, w.part, jchunk);
     else
         ES_DISPATCH_ND(ph, g, launch_monitor, ph, g, mo, JU, J, w.grad, w.part, nb, s);
-    for (int q = 0; q < mo.nsig; q++)
+    for (int q = 0; q < (mo.form ? 2 * mo.nsig : mo.nsig); q++)
         hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part + q * RED_BLOCKS,
                            march ? jblocks : nb, w.scal + q, 0, 0.0, status);
     hipLaunchKernelGGL(k_theta, dim3(gi), dim3(256), 0, s, g, mo, w.grad, w.scal, w.th0);

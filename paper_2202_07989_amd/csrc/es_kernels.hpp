@@ -15,6 +15,8 @@ struct MonitorP {
     int sigma[4];
     double alpha[4];
     int n_smooth, n_sweeps;
+    int form;          // 0: eq monitor; 1: gradient + Laplacian (channels nsig..2 nsig - 1)
+    double beta[4];
 };
 
 struct MeshWork {

@@ -19,6 +19,7 @@ ES_OK, ES_EINVAL, ES_EUNSUPPORTED, ES_EHIP, ES_ENONPHYS, ES_ETANGLE = 0, -1, -2,
 ES_ST_NONPHYS, ES_ST_TANGLE = 1, 2
 ES_FP64, ES_MIXED = 0, 1
 ES_WENO_MR, ES_WENO_JS = 0, 1
+ES_MONITOR_GRAD2, ES_MONITOR_GRAD_LAP = 0, 1
 ES_METRICS_VCL_ONLY = 1
 
 
@@ -41,7 +42,7 @@ class EsGrid(C.Structure):
 class EsMonitor(C.Structure):
     _fields_ = [
         ("nsig", C.c_int), ("sigma", C.c_int * 4), ("alpha", C.c_double * 4),
-        ("n_smooth", C.c_int), ("n_sweeps", C.c_int),
+        ("n_smooth", C.c_int), ("n_sweeps", C.c_int), ("form", C.c_int), ("beta", C.c_double * 4),
     ]
 
 
@@ -136,6 +137,9 @@ def make_monitor(mon) -> EsMonitor:
     for t in range(len(sig)):
         m.sigma[t], m.alpha[t] = sig[t], al[t]
     m.n_smooth, m.n_sweeps = mon.get("n_smooth", 3), mon.get("n_sweeps", 10)
+    m.form = mon.get("form", ES_MONITOR_GRAD2)
+    for t, b in enumerate(mon.get("beta", [])):
+        m.beta[t] = b
     return m
 
 

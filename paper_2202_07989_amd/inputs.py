@@ -154,6 +154,73 @@ def init_c1(spec, amp=0.1):
 
 
 # --------------------------------------------------------------------------
+# isentropic vortex (Section 5, Examples 5.1 and 5.5): a smooth isentropic
+# vortex of strength eps = 5 carried by a uniform flow on the periodic box
+# [-10, 10]^d, one ideal-gas species (Gamma 1.4, c_v 1, p_inf 0).  2D: centre
+# (-2, -2) at t = 0, mean flow (1, 1).  3D: the cylindrical vortex turned
+# onto the diagonal through the maps xhat = (-x1 + x2, x1 - x3) (wrapped to
+# [-10, 10)^2) and xtilde = (xhat1 + 2 xhat2, sqrt(3) xhat1)/sqrt(6), with the
+# velocity map of Example 5.5.  T = 1 - eps^2/(8 Gamma pi^2) e^(1 - r^2),
+# rho = T^(1/(Gamma-1)), p = (Gamma - 1) rho T.  The exact solution is the
+# initial field translated by the mean velocity.  The mesh starts uniform,
+# x = xi - 10.
+# --------------------------------------------------------------------------
+VORTEX_EPS = 5.0
+
+
+def spec_vortex(dim, n):
+    return make_spec(dim, 1, (n,) * dim, box=(20.0,) * dim, gamma=(1.4,), cv=(1.0,), pinf=(0.0,))
+
+
+def vortex_mean_velocity(dim):
+    if dim == 2:
+        return (1.0, 1.0)
+    s2, s3, s6 = math.sqrt(2.0), math.sqrt(3.0), math.sqrt(6.0)
+    return ((1.0 - s3 + s2) / s6, (1.0 + s3 + s2) / s6, (-2.0 + s2) / s6)
+
+
+def _wrap20(a):
+    return (a + 10.0) % 20.0 - 10.0
+
+
+def vortex_prims(dim, x, t=0.0, eps=VORTEX_EPS, gamma=1.4):
+    """rho, [v_1..v_d], p of the exact solution at physical points x (list
+    of d arrays) and time t."""
+    vm = vortex_mean_velocity(dim)
+    y = [x[k] - vm[k] * t for k in range(dim)]
+    if dim == 2:
+        a, b = _wrap20(y[0] + 2.0), _wrap20(y[1] + 2.0)
+        r2 = a * a + b * b
+        f = eps / (2.0 * math.pi) * np.exp(0.5 * (1.0 - r2))
+        v = [1.0 + f * b, 1.0 - f * a]
+    else:
+        s2, s3, s6 = math.sqrt(2.0), math.sqrt(3.0), math.sqrt(6.0)
+        h1, h2 = _wrap20(-y[0] + y[1]), _wrap20(y[0] - y[2])
+        t1, t2 = (h1 + 2.0 * h2) / s6, s3 * h1 / s6
+        r2 = t1 * t1 + t2 * t2
+        f = eps / (2.0 * math.pi) * np.exp(0.5 * (1.0 - r2))
+        w1, w2 = 1.0 + f * t2, 1.0 - f * t1
+        v = [(w1 - s3 * w2 + s2) / s6, (w1 + s3 * w2 + s2) / s6, (-2.0 * w1 + s2) / s6]
+    T = 1.0 - eps ** 2 / (8.0 * gamma * math.pi ** 2) * np.exp(1.0 - r2)
+    rho = T ** (1.0 / (gamma - 1.0))
+    return rho, v, (gamma - 1.0) * rho * T
+
+
+def init_vortex(spec):
+    d = spec["dim"]
+    x = [xi - 10.0 for xi in xi_nodes(spec)]
+    rho, v, p = vortex_prims(d, x, 0.0)
+    U = conserved(spec, [rho], v, p)
+    return assemble(spec, U, np.ones_like(rho), x)
+
+
+def vortex_monitor(n_sweeps=10, n_smooth=3):
+    """The monitor of the vortex examples: Theta = (1 + 20 |grad rho_1| / max
+    + 10 |lap rho_1| / max)^(1/2)."""
+    return dict(sigma=[1], alpha=[20.0], beta=[10.0], form=1, n_smooth=n_smooth, n_sweeps=n_sweeps)
+
+
+# --------------------------------------------------------------------------
 # shock-bubble data (C2, C3): water with a trace of air, an air bubble with a
 # trace of water, and a planar Mach-M_s shock in the water.
 # Post-shock state: stiffened-gas normal-shock relations for a shock moving

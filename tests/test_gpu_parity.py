@@ -108,7 +108,12 @@ def test_wavespeed_parity(name):
 @pytest.mark.parametrize("name,mon", [("2d-n2-bubble", dict(sigma=[0], alpha=[1200.0], n_smooth=3, n_sweeps=10)),
                                       ("2d-n1", dict(sigma=[0, 3], alpha=[50.0, 20.0], n_smooth=5, n_sweeps=7)),
                                       ("3d-n2-bubble", dict(sigma=[0], alpha=[1200.0], n_smooth=3, n_sweeps=5)),
-                                      ("3d-n2-random", dict(sigma=[1, 2], alpha=[300.0, 300.0], n_smooth=2, n_sweeps=6))])
+                                      ("3d-n2-random", dict(sigma=[1, 2], alpha=[300.0, 300.0], n_smooth=2, n_sweeps=6)),
+                                      # the gradient + Laplacian monitor of the vortex examples
+                                      ("2d-n2-bubble", dict(sigma=[0], alpha=[20.0], beta=[10.0], form=1,
+                                                            n_smooth=3, n_sweeps=10)),
+                                      ("3d-n2-random", dict(sigma=[1, 3], alpha=[20.0, 5.0], beta=[10.0, 2.0],
+                                                            form=1, n_smooth=2, n_sweeps=6))])
 def test_mesh_redistribute_parity(name, mon):
     say(f"[mesh parity] {name} {mon}")
     sp, o, JU, J, x, disp, jx, jt = prepared(name)

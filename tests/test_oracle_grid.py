@@ -280,6 +280,44 @@ def test_design_order_smooth_advection(dissipation, recon, min_order):
 
 # -- Section 4: mesh redistribution --------------------------------------------
 @pytest.mark.parametrize("dim", [2, 3])
+def test_vortex_monitor_closed_form(dim):
+    """The monitor of the isentropic-vortex examples (form 1), unfiltered, on
+    rho = 1.5 + 0.5 sin(kappa xi_0): the second-order central differences of
+    a sine are exact in closed form, |grad| = 0.5 |cos(kappa xi_0)| sin(kappa h)/h
+    and |lap| = 0.5 |sin(kappa xi_0)| (2 - 2 cos(kappa h))/h^2, so Theta^2 =
+    1 + 20 |grad|/max|grad| + 10 |lap|/max|lap| node by node; the maxima are
+    over the grid nodes.  An exactly constant field drops both terms (Theta = 1)."""
+    n = (24, 20) if dim == 2 else (16, 12, 10)
+    sp = I.make_spec(dim, 1, n, box=(20.0,) * dim)
+    o = oracle.Oracle(sp)
+    JU, J, x = I.init_random(sp, seed=41, noise=0.0)
+    ghosts_all(o, JU, J, x)
+    Iin = I.interior(sp)
+    xi0 = I.xi_nodes(sp)[0]
+    h = sp["dxi"][0]
+    kap = 2.0 * np.pi / (sp["n"][0] * h)
+    rho = 1.5 + 0.5 * np.sin(kap * xi0)
+    JU[0][Iin[1:]] = J[0][Iin[1:]] * rho
+    o.fill_ghosts(JU, o.nc)
+    mon = dict(sigma=[0], alpha=[20.0], beta=[10.0], form=1, n_smooth=0, n_sweeps=1)
+    rc, th = o.monitor_fn(mon, JU, J)
+    assert rc == 0
+    gr = 0.5 * np.abs(np.cos(kap * xi0)) * np.sin(kap * h) / h
+    lp = 0.5 * np.abs(np.sin(kap * xi0)) * (2.0 - 2.0 * np.cos(kap * h)) / h ** 2
+    ref = np.sqrt(1.0 + 20.0 * gr / gr.max() + 10.0 * lp / lp.max())
+    np.testing.assert_allclose(th[Iin][0], ref, rtol=1e-12)
+    # (J = 1, so that rho = JU/J is exactly constant: the normalisation by
+    # the maximum would lift rounding-level gradients to O(1))
+    J[...] = 1.0
+    JU[0][...] = 1.25
+    rc, th = o.monitor_fn(mon, JU, J)
+    np.testing.assert_array_equal(th[Iin][0], 1.0)
+    # more than two variables is not a valid form-1 monitor
+    rc, _ = o.monitor_fn(dict(mon, sigma=[0, 3, 0], alpha=[1.0] * 3, beta=[1.0] * 3), JU, J)
+    assert rc != 0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
 def test_mesh_uniform_fixed_point_and_filter(dim):
     n = (16, 12) if dim == 2 else (6, 7, 8)
     sp = I.make_spec(dim, 1, n)
