@@ -123,6 +123,15 @@ int es_metrics(es_ctx *c, const double *x_n, const double *disp, double c_s,
                const double *dt_dev, double *jxi_x, double *jxi_t, int flags,
                void *stream);
 
+/* Section 3.2: the discrete Jacobian of the mesh x (ghost layers valid) from
+ * its metrics jxi_x (es_metrics of the same mesh), J = (1/d) sum_k sum_j
+ * delta_k[x_j]/dxi_k J dxi_k/dx_j (the cofactor expansion of det dx/dxi along
+ * each column k, averaged; delta_k the 2w-order central difference), at
+ * interior nodes, ghost layers filled.  Sets J at t = 0 on a mesh that is not
+ * uniform (an adapted initial mesh); afterwards J follows eq semi_J.  J is
+ * one array of the padded size; it may alias neither x nor jxi_x (ES_EINVAL). */
+int es_jacobian(es_ctx *c, const double *x, const double *jxi_x, double *J, void *stream);
+
 /* Sections 3.1-3.4, eq semi_U / eq semi_J with the ES flux eq HOstable (or
  * the EC flux eq ECFlux_curv_2p when dissipation = 0): the semi-discrete
  * right-hand side d(JU)/dt, dJ/dt at interior nodes.  Inputs need valid

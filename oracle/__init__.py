@@ -71,6 +71,7 @@ def lib():
             "orc_interface_frame": (C.c_int, [_G, _D, _D, _D, _D, _D]),
             "orc_mr5": (C.c_double, [_D, _D, C.c_double]),
             "orc_js5": (C.c_double, [_D, C.c_double]),
+            "orc_jacobian": (C.c_int, [_G, _D, _D, _D]),
             "orc_npoints": (C.c_long, [_G]),
             "orc_fill_ghosts": (None, [_G, _D, C.c_int]),
             "orc_fill_ghosts_x": (None, [_G, _D]),
@@ -229,6 +230,12 @@ class Oracle:
         rc = self.L.orc_metrics(self.gp, _p(x), _p(disp), c_s, dt, _p(jx), _p(jt))
         assert rc == 0, rc
         return jx, jt
+
+    def jacobian(self, x, jx):
+        J = np.zeros((1,) + x.shape[1:])
+        rc = self.L.orc_jacobian(self.gp, _p(x), _p(jx), _p(J))
+        assert rc == 0, rc
+        return J
 
     def rhs(self, JU, J, jx, jt):
         dJU = np.zeros_like(JU)

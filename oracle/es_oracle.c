@@ -617,6 +617,31 @@ static double nested(const orc_grid *g, const double *xs, long i, int a, int b, 
     return 0.5 * s;
 }
 
+/* Discrete Jacobian of the mesh (Section 3.2: J is the determinant of the  */
+/* Jacobian matrix dx/dxi, whose cofactor rows are the metrics J dxi_k/dx):  */
+/* by the cofactor expansion along each column k, det = sum_j dx_j/dxi_k     */
+/* J dxi_k/dx_j; reading: dx_j/dxi_k by the same 2w-order difference as the  */
+/* metrics, averaged over k.  Used only to set J on a non-uniform mesh at    */
+/* t = 0; afterwards J follows eq semi_J.                                   */
+int orc_jacobian(const orc_grid *g, const double *x, const double *jxi_x, double *J)
+{
+    if (!valid_grid(g) || !x || !jxi_x || !J) return ORC_EINVAL;
+    int d = g->dim;
+    long P = orc_npoints(g);
+    for (int i2 = lo_(g, 2); i2 < hi_(g, 2); i2++)
+        for (int i1 = lo_(g, 1); i1 < hi_(g, 1); i1++)
+            for (int i0 = lo_(g, 0); i0 < hi_(g, 0); i0++) {
+                long i = at(g, i0, i1, i2);
+                double s = 0.0;
+                for (int k = 0; k < d; k++)
+                    for (int j = 0; j < d; j++)
+                        s += delta_k(g, x + j * P, i, k) / g->dxi[k] * jxi_x[(k * d + j) * P + i];
+                J[i] = s / d;
+            }
+    orc_fill_ghosts(g, J, 1);
+    return ORC_OK;
+}
+
 int orc_metrics(const orc_grid *g, const double *x_n, const double *disp,
                 double c_s, double dt, double *jxi_x, double *jxi_t)
 {

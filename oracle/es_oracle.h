@@ -98,6 +98,9 @@ void   orc_fill_ghosts(const orc_grid *g, double *a, int ncomp);
 void   orc_fill_ghosts_x(const orc_grid *g, double *x);
 int    orc_metrics(const orc_grid *g, const double *x_n, const double *disp,
                    double c_s, double dt, double *jxi_x, double *jxi_t);
+/* discrete Jacobian of a mesh from its metrics (for J at t = 0 on a mesh
+ * that is not uniform): J = (1/d) sum_k sum_j delta_k[x_j]/dxi_k J dxi_k/dx_j */
+int    orc_jacobian(const orc_grid *g, const double *x, const double *jxi_x, double *J);
 int    orc_rhs(const orc_grid *g, const double *JU, const double *J,
                const double *jxi_x, const double *jxi_t, double *dJU, double *dJ);
 int    orc_rhs_points(const orc_grid *g, const double *JU, const double *J,

@@ -270,6 +270,13 @@ int es_metrics(es_ctx* c, const double* x_n, const double* disp, double c_s, con
     return hip_rc(metrics(c->ph, c->geo, x_n, disp, c_s, dt_dev, jxi_x, jxi_t, vcl_only, c->G, S(stream)));
 }
 
+int es_jacobian(es_ctx* c, const double* x, const double* jxi_x, double* J, void* stream)
+{
+    if (!c || !x || !jxi_x || !J) return ES_EINVAL;
+    if (J == x || J == jxi_x) return ES_EINVAL;
+    return hip_rc(jacobian(c->ph, c->geo, x, jxi_x, J, S(stream)));
+}
+
 int es_rhs(es_ctx* c, const double* JU, const double* J, const double* jxi_x, const double* jxi_t,
            double* dJU, double* dJ, void* stream)
 {

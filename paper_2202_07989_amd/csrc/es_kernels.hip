@@ -402,6 +402,40 @@ __global__ void k_vcl(Geo g, const double* __restrict__ disp, const double* __re
     }
 }
 
+// discrete Jacobian of the mesh: J = (1/d) sum_k sum_j dx_j/dxi_k J dxi_k/dx_j
+// (the cofactor expansion of det dx/dxi along each column k, averaged),
+// dx_j/dxi_k by the 2w-order central difference of the metrics
+__global__ void k_jacobian(Geo g, Phys ph, const double* __restrict__ x, const double* __restrict__ jxx,
+                           double* __restrict__ J)
+{
+    const long P = g.P;
+    const int d = g.dim;
+    const long nint = n_interior(g);
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+        double s = 0.0;
+        for (int k = 0; k < d; k++) {
+            const long st = dir_stride(g, k);
+            for (int j = 0; j < d; j++) {
+                const double* a = x + j * P;
+                double dk = 0.0;
+                for (int m = 1; m <= ph.w; m++) dk += ph.alpha[m - 1] * (a[i + m * st] - a[i - m * st]);
+                s += 0.5 * dk / g.dxi[k] * jxx[(k * d + j) * P + i];
+            }
+        }
+        J[i] = s / d;
+    }
+}
+
+hipError_t jacobian(const Phys& ph, const Geo& g, const double* x, const double* jxx, double* J, hipStream_t s)
+{
+    const long nint = (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1);
+    hipLaunchKernelGGL(k_jacobian, dim3(grid_for(nint)), dim3(256), 0, s, g, ph, x, jxx, J);
+    const hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : fill_ghosts(g, J, 1, 0, s);
+}
+
 hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double* disp, double cs,
                    const double* dt_dev, double* jxx, double* jxt, int vcl_only, double* G,
                    hipStream_t s)

@@ -36,6 +36,7 @@ hipError_t copy(const double* src, double* dst, long n, hipStream_t s);
 hipError_t fill_value(double* dst, long n, double v, hipStream_t s);
 hipError_t add_inplace(double* a, const double* b, long n, hipStream_t s);
 hipError_t set_scalar(double* dst, double v, hipStream_t s);
+hipError_t jacobian(const Phys& ph, const Geo& g, const double* x, const double* jxx, double* J, hipStream_t s);
 hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double* disp, double cs,
                    const double* dt_dev, double* jxx, double* jxt, int vcl_only, double* G,
                    hipStream_t s);

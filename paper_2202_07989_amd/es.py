@@ -57,6 +57,7 @@ _SIGS = {
     "es_rk_stage": [_P, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "max_wavespeed": [_P, _P, _P, _P, C.c_double, _P, _P, _P],
     "mesh_redistribute": [_P, C.POINTER(EsMonitor), _P, _P, _P, _P, _P, _P, _P],
+    "es_jacobian": [_P, _P, _P, _P, _P],
     "es_entropy": [_P, _P, _P, _P, _P],
     "es_entropy_rate": [_P, _P, _P, _P, _P, _P, _P],
     "es_step": [_P, C.POINTER(EsMonitor), C.c_double, C.c_double, C.c_int, _P, _P, _P, _P, _P, _P],
@@ -199,6 +200,9 @@ class Context:
         _check("mesh_redistribute", lib.mesh_redistribute(self.h, C.byref(m), _ptr(JU), _ptr(J),
                                                           _ptr(x_n), _ptr(disp), _ptr(dtau_dev),
                                                           _ptr(resid_dev), _stream(stream)))
+
+    def es_jacobian(self, x, jxi_x, J, stream=None):
+        _check("es_jacobian", lib.es_jacobian(self.h, _ptr(x), _ptr(jxi_x), _ptr(J), _stream(stream)))
 
     def es_entropy(self, JU, J, total_dev, stream=None):
         _check("es_entropy", lib.es_entropy(self.h, _ptr(JU), _ptr(J), _ptr(total_dev), _stream(stream)))

@@ -279,6 +279,41 @@ def test_design_order_smooth_advection(dissipation, recon, min_order):
 
 
 # -- Section 4: mesh redistribution --------------------------------------------
+def test_jacobian_affine_exact_and_sixth_order():
+    """The discrete Jacobian of a mesh: exact (to rounding) on an affine mesh
+    of either dimension, where the central differences are exact, and order
+    6 against the analytic Jacobian of the curvilinear C1 mesh."""
+    rng = np.random.default_rng(51)
+    for dim in (2, 3):
+        n = (10, 9) if dim == 2 else (8, 7, 9)
+        sp = I.make_spec(dim, 1, n)
+        o = oracle.Oracle(sp)
+        A = np.eye(dim) + 0.3 * rng.uniform(-1, 1, (dim, dim))
+        xi = I.xi_nodes(sp)
+        x = I.zeros(sp, dim)
+        Iin = I.interior(sp)
+        for k in range(dim):
+            x[k][Iin[1:]] = sum(A[k, j] * xi[j] for j in range(dim))
+        # periodic images of an affine map: x(xi + L e_j) = x(xi) + L A e_j, so
+        # the ghost layers are filled by extrapolating the affine map
+        pad = padded_xi(sp)
+        for k in range(dim):
+            x[k] = sum(A[k, j] * pad[j] for j in range(dim))
+        jx, _ = o.metrics(x)
+        Jd = o.jacobian(x, jx)
+        np.testing.assert_allclose(Jd[Iin], np.linalg.det(A), rtol=1e-12)
+    errs = []
+    for n in (16, 32):
+        sp = I.spec_c1(n)
+        o = oracle.Oracle(sp)
+        JU, J, x = I.init_c1(sp)
+        o.fill_ghosts_x(x)
+        jx, _ = o.metrics(x)
+        Iin = I.interior(sp)
+        errs.append(np.abs(o.jacobian(x, jx)[Iin] - J[Iin]).max())
+    assert np.log2(errs[0] / errs[1]) > 5.5, errs
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_vortex_monitor_closed_form(dim):
     """The monitor of the isentropic-vortex examples (form 1), unfiltered, on
