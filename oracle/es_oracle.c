@@ -754,11 +754,18 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
     double R[MAXC * MAXC], s, Tv[3][3];
     frame_of(g, &q[2], &q[3], mbar, R, &s, Tv);
 
-    double W[6][MAXC], Wmag[MAXC];
-    for (int c = 0; c < nc; c++) Wmag[c] = 0.0;
+    double W[6][MAXC], Wmag[MAXC], arow[MAXC];
+    for (int e = 0; e < nc; e++) arow[e] = 0.0;
     for (int t = 0; t < 6; t++) {
         double V[MAXC], TV[MAXC];
         entropy_vars_of(g, &q[t], V);
+        if (t == 2 || t == 3) {   /* row magnitudes: |V_l|; sum_j |V_{N+j}| >= |(T V)_{N+a}|; |V_E| */
+            double vm = 0.0;
+            for (int j = 0; j < d; j++) vm += fabs(V[N + j]);
+            for (int l = 0; l < N; l++) arow[l] += fabs(V[l]);
+            for (int a = 0; a < d; a++) arow[N + a] += vm;
+            arow[nc - 1] += fabs(V[nc - 1]);
+        }
         for (int c = 0; c < nc; c++) TV[c] = V[c];
         for (int a = 0; a < d; a++) {
             TV[N + a] = 0.0;
@@ -767,10 +774,18 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
         for (int c = 0; c < nc; c++) {
             W[t][c] = 0.0;
             for (int e = 0; e < nc; e++) W[t][c] += R[e * nc + c] * TV[e];   /* R^T */
-            /* size of the terms that make W_i and W_{i+1} (the jump's nodes) */
-            if (t == 2 || t == 3)
-                for (int e = 0; e < nc; e++) Wmag[c] += fabs(R[e * nc + c]) * fabs(TV[e]);
         }
+    }
+    /* bound on the size of the terms that make W_i and W_{i+1}:
+       sum_e |R_ec| |(T V)_e| <= max_l |R_lc| sum_l arow_l (species rows)
+       + sum_e |R_ec| arow_e (momentum and energy rows), both nodes summed */
+    double ysum = 0.0;
+    for (int l = 0; l < N; l++) ysum += arow[l];
+    for (int c = 0; c < nc; c++) {
+        double rmax = 0.0;
+        for (int l = 0; l < N; l++) if (fabs(R[l * nc + c]) > rmax) rmax = fabs(R[l * nc + c]);
+        Wmag[c] = rmax * ysum;
+        for (int e = N; e < nc; e++) Wmag[c] += fabs(R[e * nc + c]) * arow[e];
     }
     double Z[MAXC], pr = 0.0;
     for (int c = 0; c < nc; c++) {
@@ -781,8 +796,10 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
         double JW = Wplus - Wminus;
         double jump = W[3][c] - W[2][c];
         /* reading of sign(0) at working precision: a jump below 1e-12 of
-           the size of the terms that form W_i and W_{i+1}, sum_e |R_ec|
-           |(T V)_e| at both nodes, is zero (across a contact the acoustic
+           a bound on the size of the terms that form W_i and W_{i+1},
+           max_l |R_lc| sum_l |V_l| plus sum_e |R_ec| a_e over the momentum
+           rows (a_e = sum_j |V_{N+j}|) and the energy row (|V_E|), summed
+           over both nodes, is zero (across a contact the acoustic
            jumps vanish up to rounding, in an isentropic flow the entropy
            field's jumps do), so Y_mm = 0 there */
         int Y = (JW * jump > 0.0) && (fabs(jump) > 1.0e-12 * Wmag[c]);

@@ -410,33 +410,30 @@ __device__ __forceinline__ void frame_project_main(const Frame<N, D, R>& F, cons
     }
 }
 
-// size of the terms that make the fields of frame_project_main at one node,
-// sum_e |R_ec| |y_e| (R_ec the entries of R^T multiplying y_e), added to
-// Mm (same field order); yr holds all D rotated momentum variables
+// zero-tolerance scale of the fields of frame_project_main (same order):
+// max over the species rows of |R_lc| times ay (the species magnitudes
+// summed), plus sum_e |R_ec| a_e over the momentum rows (a_e = av) and the
+// energy row (aE)
 template <int N, int D, typename R>
-__device__ __forceinline__ void frame_mag_main(const Frame<N, D, R>& F, const R* ysp, const R* yr, R yE, R* Mm)
+__device__ __forceinline__ void frame_scale_main(const Frame<N, D, R>& F, R ay, R av, R aE, R* mg)
 {
-    R vt = R(0);   // sum over the tangential rows of |vh_j| |y_{N+j}|
+    R vt = R(0);   // sum of |vh_j| over the tangential rows
 #pragma unroll
-    for (int j = 1; j < D; j++) vt += fabs(F.vh[j]) * fabs(yr[j]);
-    const R aE = fabs(yE), a0 = fabs(yr[0]);
+    for (int j = 1; j < D; j++) vt += fabs(F.vh[j]);
     const R cv0 = F.c * F.vh[0];
     if constexpr (N == 1) {
-        const R ay = fabs(ysp[0]);
-        Mm[0] += F.sa * (ay + fabs(F.vh[0] - F.c) * a0 + vt + fabs(F.H - cv0) * aE);
-        Mm[1] += F.se * (ay + fabs(F.vh[0]) * a0 + vt + fabs(F.K) * aE);
-        Mm[2] += F.sa * (ay + fabs(F.vh[0] + F.c) * a0 + vt + fabs(F.H + cv0) * aE);
+        mg[0] = F.sa * (ay + (fabs(F.vh[0] - F.c) + vt) * av + fabs(F.H - cv0) * aE);
+        mg[1] = F.se * (ay + (fabs(F.vh[0]) + vt) * av + fabs(F.K) * aE);
+        mg[2] = F.sa * (ay + (fabs(F.vh[0] + F.c) + vt) * av + fabs(F.H + cv0) * aE);
     } else {
-        const R ay0 = fabs(ysp[0]), ay1 = fabs(ysp[1]);
-        const R vall = fabs(F.vh[0]) * a0 + vt;
-        Mm[0] += F.s2a * (fabs(F.Y[0]) * ay0 + fabs(F.Y[1]) * ay1 + fabs(F.vh[0] - F.c) * a0 + vt +
-                          fabs(F.H - cv0) * aE);
-        Mm[1] += fabs(F.d11) * ay0 + fabs(F.d21) * ay1 + fabs(F.d11 + F.d21) * vall +
-                 fabs(F.d11 * F.e2[0] + F.d21 * F.e2[1]) * aE;
-        Mm[2] += fabs(F.d12) * ay0 + fabs(F.d22) * ay1 + fabs(F.d12 + F.d22) * vall +
-                 fabs(F.d12 * F.e2[0] + F.d22 * F.e2[1]) * aE;
-        Mm[3] += F.s2a * (fabs(F.Y[0]) * ay0 + fabs(F.Y[1]) * ay1 + fabs(F.vh[0] + F.c) * a0 + vt +
-                          fabs(F.H + cv0) * aE);
+        const R ya = fmax(fabs(F.Y[0]), fabs(F.Y[1])) * ay;
+        const R va = (fabs(F.vh[0]) + vt) * av;
+        mg[0] = F.s2a * (ya + (fabs(F.vh[0] - F.c) + vt) * av + fabs(F.H - cv0) * aE);
+        mg[1] = fmax(fabs(F.d11), fabs(F.d21)) * ay + fabs(F.d11 + F.d21) * va +
+                fabs(F.d11 * F.e2[0] + F.d21 * F.e2[1]) * aE;
+        mg[2] = fmax(fabs(F.d12), fabs(F.d22)) * ay + fabs(F.d12 + F.d22) * va +
+                fabs(F.d12 * F.e2[0] + F.d22 * F.e2[1]) * aE;
+        mg[3] = F.s2a * (ya + (fabs(F.vh[0] + F.c) + vt) * av + fabs(F.H + cv0) * aE);
     }
 }
 

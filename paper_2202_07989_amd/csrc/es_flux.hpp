@@ -17,6 +17,8 @@ struct NodeTile {
     double v[D][NN];       // velocity
     double b[NN];          // beta = 1/T
     double lb[NN];         // log beta
+    float ay[NN];          // sum_l |y_l| (species entropy variables), and
+    float av[NN];          // beta |v|_1: row magnitudes for the sign test's zero tolerance
     double m[D + 1][NN];   // half the metrics of direction k: n_t/2, n_1/2..n_D/2 (an
                            // interface average is then one sum; halving is exact)
 };
@@ -178,21 +180,30 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
     R Z[NC];
     // MR-WENO on one scaled characteristic field, sign matrix Y: the WENO
     // jump and the jump agree in sign, and the jump is not zero to working
-    // precision, i.e. above zero_tol times mag, the size of the terms that
-    // make W_i and W_{i+1} (sum_e |R_ec| |(T V)_e| at both nodes).  Across a
-    // contact the acoustic jumps vanish up to rounding, in an isentropic flow
-    // the entropy field's do; those count as sign 0.
+    // precision, i.e. above zero_tol times mag, a bound on the size of the
+    // terms that make W_i and W_{i+1}: max_l |R_lc| sum_l |y_l| over the
+    // species rows, plus sum_e |R_ec| a_e with a_e = beta |v|_1 (>= every
+    // rotated |y_{N+j}|) for the momentum rows and beta for the energy row,
+    // all summed over nodes i and i+1.  Across a contact the acoustic jumps vanish up to rounding, in an
+    // isentropic flow the entropy field's do; those count as sign 0.
     auto weno_field = [&](const R (&w)[6], R mag) -> R {
         R jump;
         const R jw = mr5_jump<R, RC == 1>(w[0], w[1], w[2], w[3], w[4], w[5], Wc, jump);
         const bool y = (jw * jump > R(0)) && (fabs(jump) > Wc.zero_tol * mag);
         return y ? jw : R(0);
     };
+    // row magnitudes of nodes i and i+1, summed (the node part of the zero
+    // tolerance, kept per node in the tile): ay = sum_l |y_l|, av = beta
+    // |v|_1, aE = beta
+    auto node_scales = [&](R& ay, R& av, R& aE) {
+        ay = R(S.ay[iL]) + R(S.ay[iR]);
+        av = R(S.av[iL]) + R(S.av[iR]);
+        aE = R(fabs(S.b[iL]) + fabs(S.b[iR]));
+    };
+    asm volatile("" ::: "memory");
     {
-        R Wt[D - 1][6], Mt[D - 1];
+        R Wt[D - 1][6];
         const R sct = (N == 1) ? F.st : F.sq * F.c;   // scale of the tangential columns
-#pragma unroll
-        for (int j = 0; j < D - 1; j++) Mt[j] = R(0);
 #pragma unroll
         for (int t = 0; t < 6; t++) {
             const int q = st[t];
@@ -209,22 +220,10 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
 #pragma unroll
             for (int j = 0; j < D - 1; j++) Wt[j][t] = wt[j];
         }
-        // term sizes at nodes i and i+1, from values reloaded from LDS (the
-        // loop's values are not kept live for them)
-        asm volatile("" ::: "memory");
+        R ay, av, aE;
+        node_scales(ay, av, aE);
 #pragma unroll
-        for (int t = 2; t <= 3; t++) {
-            const int q = st[t];
-            const R bq = R(S.b[q]);
-            R vq[D], vr[D];
-#pragma unroll
-            for (int j = 0; j < D; j++) vq[j] = R(S.v[j][q]);
-            rot_apply<D, R>(T, vq, vr);
-#pragma unroll
-            for (int j = 0; j < D - 1; j++) Mt[j] += sct * (fabs(bq * vr[j + 1]) + fabs(F.vh[j + 1]) * fabs(bq));
-        }
-#pragma unroll
-        for (int j = 0; j < D - 1; j++) Z[N + 1 + j] = weno_field(Wt[j], Mt[j]);
+        for (int j = 0; j < D - 1; j++) Z[N + 1 + j] = weno_field(Wt[j], sct * (av + fabs(F.vh[j + 1]) * aE));
     }
     // the second group reloads its node values from LDS rather than keeping
     // the first group's loads live across the first group's WENO
@@ -232,36 +231,6 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
     {
         constexpr int NM = N + 2;          // fields 0..N and NC - 1
         R Wm[NM][6];
-        float Mm[NM];   // threshold scales only: single precision suffices
-        {
-        R Ma[NM];
-#pragma unroll
-        for (int c = 0; c < NM; c++) Ma[c] = R(0);
-#pragma unroll
-        for (int t = 2; t <= 3; t++) {
-            const int q = st[t];
-            const R bq = R(S.b[q]);
-            R vq[D], yr[D];
-            R v2 = R(0);
-#pragma unroll
-            for (int j = 0; j < D; j++) {
-                vq[j] = R(S.v[j][q]);
-                v2 += vq[j] * vq[j];
-            }
-            R ys[N];
-            const double lbq = S.lb[q];
-#pragma unroll
-            for (int l = 0; l < N; l++)
-                ys[l] = R(ph.cv[l] * lbq + ph.Rg[l] * S.lrho[l][q] + ph.cvgam[l]) - R(0.5) * bq * v2;
-            rot_apply<D, R>(T, vq, yr);
-#pragma unroll
-            for (int j = 0; j < D; j++) yr[j] *= bq;
-            frame_mag_main<N, D, R>(F, ys, yr, -bq, Ma);
-        }
-#pragma unroll
-        for (int c = 0; c < NM; c++) Mm[c] = float(Ma[c]);
-        }
-        asm volatile("" ::: "memory");
 #pragma unroll
         for (int t = 0; t < 6; t++) {
             const int q = st[t];
@@ -285,9 +254,14 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
 #pragma unroll
             for (int c = 0; c < NM; c++) Wm[c][t] = wm[c];
         }
+        {
+            R mg[NM], ay, av, aE;
+            node_scales(ay, av, aE);
+            frame_scale_main<N, D, R>(F, ay, av, aE, mg);
 #pragma unroll
-        for (int c = 0; c <= N; c++) Z[c] = weno_field(Wm[c], R(Mm[c]));
-        Z[NC - 1] = weno_field(Wm[N + 1], R(Mm[N + 1]));
+            for (int c = 0; c <= N; c++) Z[c] = weno_field(Wm[c], mg[c]);
+            Z[NC - 1] = weno_field(Wm[N + 1], mg[N + 1]);
+        }
     }
     R RZ[NC];
     frame_expand<N, D, R>(F, Z, RZ);
@@ -458,14 +432,27 @@ __device__ __forceinline__ unsigned node_state(const Phys& ph, NodeTile<N, D, NN
     const double e = U[NC - 1] - kin - ph.pinf_tot;
     const double beta = cvr * rcp(e);
     S.b[li] = beta;
-    S.lb[li] = ln_pos(beta);
+    const double lbeta = ln_pos(beta);
+    S.lb[li] = lbeta;
     bool ok = (beta > 0.0) && isfinite(beta) && isfinite(kin);
+    double v1 = 0.0, v2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        const double vj = S.v[j][li];
+        v1 += fabs(vj);
+        v2 += vj * vj;
+    }
+    double ysum = 0.0;
 #pragma unroll
     for (int sp = 0; sp < N; sp++) {
         S.rho[sp][li] = U[sp];
-        S.lrho[sp][li] = ln_pos(U[sp]);
+        const double lr = ln_pos(U[sp]);
+        S.lrho[sp][li] = lr;
+        ysum += fabs(ph.cv[sp] * lbeta + ph.Rg[sp] * lr + ph.cvgam[sp] - 0.5 * beta * v2);
         ok = ok && (U[sp] > 0.0);
     }
+    S.ay[li] = float(ysum);
+    S.av[li] = float(fabs(beta) * v1);
     if constexpr (N == 2) S.lrt[li] = ln_pos(rt);
     unsigned bad = ok ? 0u : 1u;
     if (!(Jq > 0.0)) bad |= 2u;
