@@ -35,7 +35,8 @@ class Grid(C.Structure):
         ("dxi", C.c_double * 3), ("len", C.c_double * 3), ("w", C.c_int),
         ("gamma", C.c_double * 2), ("cv", C.c_double * 2), ("pinf", C.c_double * 2),
         ("chi", C.c_double * 3), ("weno_eps", C.c_double), ("dissipation", C.c_int),
-        ("reconstruction", C.c_int),
+        ("reconstruction", C.c_int), ("bc", (C.c_int * 2) * 3), ("wall", (C.c_double * 2) * 3),
+        ("inflow", ((C.c_double * 6) * 2) * 3),
     ]
 
 
@@ -75,6 +76,8 @@ def lib():
             "orc_npoints": (C.c_long, [_G]),
             "orc_fill_ghosts": (None, [_G, _D, C.c_int]),
             "orc_fill_ghosts_x": (None, [_G, _D]),
+            "orc_fill_ghosts_kind": (None, [_G, _D, C.c_int, C.c_int]),
+            "orc_fill_ghosts_state": (None, [_G, _D, _D]),
             "orc_metrics": (C.c_int, [_G, _D, _D, C.c_double, C.c_double, _D, _D]),
             "orc_rhs": (C.c_int, [_G, _D, _D, _D, _D, _D, _D]),
             "orc_rhs_points": (C.c_int, [_G, _D, _D, _D, _D, C.c_int, C.POINTER(C.c_long), _D, _D]),
@@ -125,6 +128,15 @@ def grid(spec) -> Grid:
     g.weno_eps = spec.get("weno_eps", 1e-10)
     g.dissipation = spec.get("dissipation", 1)
     g.reconstruction = spec.get("reconstruction", 0)
+    for k, faces in enumerate(spec.get("bc", [])):
+        for side in range(2):
+            g.bc[k][side] = faces[side]
+    for k, faces in enumerate(spec.get("wall", [])):
+        for side in range(2):
+            g.wall[k][side] = faces[side]
+    for (k, side), U in spec.get("inflow", {}).items():
+        for c, u in enumerate(U):
+            g.inflow[k][side][c] = u
     return g
 
 
@@ -222,6 +234,13 @@ class Oracle:
 
     def fill_ghosts_x(self, x):
         self.L.orc_fill_ghosts_x(self.gp, _p(x))
+
+    def fill_ghosts_kind(self, a, ncomp, what):
+        """what: 0 plain, 1 mesh, 2 displacement, 3 jxi_x, 4 jxi_t."""
+        self.L.orc_fill_ghosts_kind(self.gp, _p(a), ncomp, what)
+
+    def fill_ghosts_state(self, JU, J):
+        self.L.orc_fill_ghosts_state(self.gp, _p(JU), _p(J))
 
     def metrics(self, x, disp=None, c_s=0.0, dt=0.0):
         d = self.g.dim

@@ -47,7 +47,14 @@ static int valid_grid(const orc_grid *g)
 {
     if (!g || (g->dim != 2 && g->dim != 3) || (g->nspec != 1 && g->nspec != 2)) return 0;
     if (g->ng < 3 || g->w < 1 || g->w > 3) return 0;
-    for (int k = 0; k < g->dim; k++) if (g->n[k] < 1 || !(g->dxi[k] > 0)) return 0;
+    for (int k = 0; k < g->dim; k++) {
+        if (g->n[k] < 1 || !(g->dxi[k] > 0)) return 0;
+        for (int s = 0; s < 2; s++)
+            if (g->bc[k][s] < 0 || g->bc[k][s] > 3) return 0;
+        /* a direction is periodic on both faces or on neither */
+        if ((g->bc[k][0] == 0) != (g->bc[k][1] == 0)) return 0;
+        if (g->bc[k][0] != 0 && !(g->wall[k][1] > g->wall[k][0])) return 0;
+    }
     if (g->dim == 2 && g->n[2] != 1) return 0;
     return 1;
 }
@@ -539,45 +546,123 @@ double orc_js5(const double *q, double eps)
 }
 
 /* ------------------------------------------------------------------------ */
-/* ghost layers (periodic)                                                  */
+/* ghost layers                                                             */
+/* Periodic directions wrap.  The paper names the boundary conditions of    */
+/* its examples (periodic; reflecting, inflow and outflow for the shock-    */
+/* bubble runs) without their discrete form.  Reading used here: nodes are  */
+/* cell-centred, so the face of a non-periodic direction lies halfway       */
+/* between the outermost interior node and the first ghost node, and the    */
+/* ghost node m layers outside the face images the interior node m - 1      */
+/* layers inside it (a mirror).  On such a face                             */
+/*   - the mesh is mirrored about the face's physical coordinate wall:      */
+/*     x_k -> 2 wall - x_k, the other coordinates kept (for every kind of   */
+/*     non-periodic face), so the Jacobi sweeps keep the face in place and  */
+/*     let the nodes next to it slide along it;                             */
+/*   - fields without a direction (J, monitor values) are mirrored copies;  */
+/*   - displacements are mirrored with component k negated, metrics         */
+/*     J dxi_a/dx_b mirrored and negated when exactly one of a, b is k,     */
+/*     J dxi_a/dt negated when a = k (what the mirrored mesh gives);        */
+/*   - the state: a reflecting wall mirrors U with the momentum component   */
+/*     k negated; outflow copies U of the outermost interior node; inflow   */
+/*     takes the face's prescribed state; JU = J (mirrored) times that U.   */
+/* Every out-of-range coordinate of a ghost node is mapped at once (edges   */
+/* and corners compose the rules of their directions; where an inflow face */
+/* is involved, the inflow state of the lowest such direction is taken).    */
 /* ------------------------------------------------------------------------ */
-static int wrap(const orc_grid *g, int k, int i, int *shift)
+enum { BC_PERIODIC = 0, BC_REFLECT = 1, BC_OUTFLOW = 2, BC_INFLOW = 3 };
+enum { GH_PLAIN = 0, GH_MESH = 1, GH_DISP = 2, GH_JXX = 3, GH_JXT = 4 };
+
+/* image of padded index i along direction k: *side = -1 below, +1 above,
+   0 inside; *kind = the face's condition (periodic or not) */
+static int image(const orc_grid *g, int k, int i, int *side, int *kind)
 {
-    /* map padded index i along k to its periodic image; shift = -1, 0, +1
-       counts how many periods the image was moved by (ghost - image) */
     int n = g->n[k], ng = g->ng, r = i - ng;
-    *shift = 0;
-    if (r < 0) { r += n; *shift = -1; }
-    else if (r >= n) { r -= n; *shift = 1; }
-    return r + ng;
+    *side = r < 0 ? -1 : (r >= n ? 1 : 0);
+    *kind = *side ? g->bc[k][*side > 0] : -1;
+    if (!*side) return i;
+    if (*kind == BC_PERIODIC) return (*side < 0 ? r + n : r - n) + ng;
+    return (*side < 0 ? -1 - r : 2 * n - 1 - r) + ng;
 }
 
-static void fill_ghosts_impl(const orc_grid *g, double *a, int ncomp, int is_x)
+static void fill_ghosts_impl(const orc_grid *g, double *a, int ncomp, int what)
 {
     long P = orc_npoints(g);
+    int d = g->dim;
     for (int i2 = 0; i2 < npad(g, 2); i2++)
         for (int i1 = 0; i1 < npad(g, 1); i1++)
             for (int i0 = 0; i0 < npad(g, 0); i0++) {
-                int idx[3] = {i0, i1, i2}, src[3] = {i0, i1, i2}, sh[3] = {0, 0, 0};
-                int ghost = 0;
-                for (int k = 0; k < g->dim; k++) {
-                    src[k] = wrap(g, k, idx[k], &sh[k]);
-                    if (sh[k]) ghost = 1;
+                int idx[3] = {i0, i1, i2}, src[3] = {i0, i1, i2}, side[3] = {0, 0, 0};
+                int kind[3] = {-1, -1, -1}, ghost = 0;
+                for (int k = 0; k < d; k++) {
+                    src[k] = image(g, k, idx[k], &side[k], &kind[k]);
+                    if (side[k]) ghost = 1;
                 }
                 if (!ghost) continue;
                 long dst = at(g, i0, i1, i2), from = at(g, src[0], src[1], src[2]);
                 for (int c = 0; c < ncomp; c++) {
                     double v = a[c * P + from];
-                    /* periodic rule for the mesh: component k of x carries
-                       +-L_k when wrapped along direction k */
-                    if (is_x && c < g->dim) v += sh[c] * g->len[c];
+                    for (int k = 0; k < d; k++) {
+                        if (!side[k]) continue;
+                        if (kind[k] == BC_PERIODIC) {
+                            /* component k of x carries +-L_k when wrapped along k */
+                            if (what == GH_MESH && c == k) v += side[k] * g->len[k];
+                            continue;
+                        }
+                        if (what == GH_MESH && c == k) v = 2.0 * g->wall[k][side[k] > 0] - v;
+                        if ((what == GH_DISP || what == GH_JXT) && c == k) v = -v;
+                        if (what == GH_JXX && ((c / d == k) != (c % d == k))) v = -v;
+                    }
                     a[c * P + dst] = v;
                 }
             }
 }
 
-void orc_fill_ghosts(const orc_grid *g, double *a, int ncomp) { fill_ghosts_impl(g, a, ncomp, 0); }
-void orc_fill_ghosts_x(const orc_grid *g, double *x) { fill_ghosts_impl(g, x, g->dim, 1); }
+void orc_fill_ghosts(const orc_grid *g, double *a, int ncomp) { fill_ghosts_impl(g, a, ncomp, GH_PLAIN); }
+void orc_fill_ghosts_x(const orc_grid *g, double *x) { fill_ghosts_impl(g, x, g->dim, GH_MESH); }
+void orc_fill_ghosts_kind(const orc_grid *g, double *a, int ncomp, int what)
+{
+    fill_ghosts_impl(g, a, ncomp, what);
+}
+
+/* the state (JU, J): J first (mirrored or wrapped), then JU by the rules
+   above */
+void orc_fill_ghosts_state(const orc_grid *g, double *JU, double *J)
+{
+    long P = orc_npoints(g);
+    int d = g->dim, N = g->nspec, nc = orc_ncomp(g);
+    orc_fill_ghosts(g, J, 1);
+    for (int i2 = 0; i2 < npad(g, 2); i2++)
+        for (int i1 = 0; i1 < npad(g, 1); i1++)
+            for (int i0 = 0; i0 < npad(g, 0); i0++) {
+                int idx[3] = {i0, i1, i2}, src[3] = {i0, i1, i2};
+                int ghost = 0, extrap = 0, flip[3] = {0, 0, 0};
+                const double *uin = NULL;
+                for (int k = 0; k < d; k++) {
+                    int side, kind;
+                    src[k] = image(g, k, idx[k], &side, &kind);
+                    if (!side) continue;
+                    ghost = 1;
+                    if (kind == BC_REFLECT) flip[k] = 1;
+                    if (kind == BC_OUTFLOW) {
+                        src[k] = side < 0 ? g->ng : g->ng + g->n[k] - 1;
+                        extrap = 1;
+                    }
+                    if (kind == BC_INFLOW && !uin) uin = g->inflow[k][side > 0];
+                }
+                if (!ghost) continue;
+                long dst = at(g, i0, i1, i2), from = at(g, src[0], src[1], src[2]);
+                double U[8];
+                for (int c = 0; c < nc; c++) {
+                    if (uin) U[c] = J[dst] * uin[c];
+                    else if (extrap) U[c] = J[dst] * (JU[c * P + from] / J[from]);
+                    else U[c] = JU[c * P + from];
+                }
+                if (!uin)
+                    for (int k = 0; k < d; k++)
+                        if (flip[k]) U[N + k] = -U[N + k];
+                for (int c = 0; c < nc; c++) JU[c * P + dst] = U[c];
+            }
+}
 
 /* ------------------------------------------------------------------------ */
 /* Section 3.2, discrete GCL metrics.                                       */
@@ -685,8 +770,8 @@ int orc_metrics(const orc_grid *g, const double *x_n, const double *disp,
                 }
             }
     free(xs);
-    orc_fill_ghosts(g, jxi_x, d * d);
-    if (jxi_t) orc_fill_ghosts(g, jxi_t, d);
+    orc_fill_ghosts_kind(g, jxi_x, d * d, GH_JXX);
+    if (jxi_t) orc_fill_ghosts_kind(g, jxi_t, d, GH_JXT);
     return ORC_OK;
 }
 
@@ -1144,7 +1229,7 @@ int orc_mesh_redistribute(const orc_grid *g, const orc_monitor *mo,
                 long i = at(g, i0, i1, i2);
                 for (int c = 0; c < d; c++) disp[c * P + i] = dt * (xa[c * P + i] - x_n[c * P + i]);
             }
-    orc_fill_ghosts(g, disp, d);
+    orc_fill_ghosts_kind(g, disp, d, GH_DISP);
     if (dtau) *dtau = dt;
     free(th); free(xa); free(xb);
     return rc;
@@ -1233,8 +1318,7 @@ int orc_step(const orc_grid *g, const orc_monitor *mo, double cfl, double dt_fix
     double *Jn = (double *)malloc((size_t)P * sizeof(double));
     double *JUo = (double *)calloc((size_t)nc * P, sizeof(double));
     double *Jo = (double *)calloc((size_t)P, sizeof(double));
-    orc_fill_ghosts(g, JU, nc);
-    orc_fill_ghosts(g, J, 1);
+    orc_fill_ghosts_state(g, JU, J);
     orc_fill_ghosts_x(g, x);
     double dtau = 0.0;
     if (move_mesh && mo) {
@@ -1255,8 +1339,7 @@ int orc_step(const orc_grid *g, const orc_monitor *mo, double cfl, double dt_fix
         orc_metrics(g, x, disp, c, dt, jx, jt);
         r = orc_rk_stage(g, s, dt, JUn, Jn, JU, J, jx, jt, JUo, Jo);
         if (r && !rc) rc = r;
-        orc_fill_ghosts(g, JUo, nc);
-        orc_fill_ghosts(g, Jo, 1);
+        orc_fill_ghosts_state(g, JUo, Jo);
         memcpy(JU, JUo, (size_t)nc * P * sizeof(double));
         memcpy(J, Jo, (size_t)P * sizeof(double));
     }

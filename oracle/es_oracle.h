@@ -54,6 +54,11 @@ typedef struct {
     int dissipation;   /* 0: EC scheme, 1: ES scheme                           */
     int reconstruction;/* 0: multi-resolution WENO (Appendix A), 1: classical  */
                        /*    fifth-order WENO of Jiang and Shu (MM-WENOJS)     */
+    int bc[3][2];      /* per face ([k][0] low, [k][1] high): 0 periodic,      */
+                       /*    1 reflecting wall, 2 outflow, 3 inflow; a         */
+                       /*    direction is periodic on both faces or neither    */
+    double wall[3][2]; /* physical coordinate x_k of each non-periodic face    */
+    double inflow[3][2][6]; /* prescribed conserved state U of inflow faces    */
 } orc_grid;
 
 typedef struct {
@@ -94,8 +99,13 @@ double orc_js5(const double *q, double eps);
 
 /* ---- whole-grid steps ----------------------------------------------------- */
 long   orc_npoints(const orc_grid *g);
+/* ghost layers: periodic wrap, or the mirror rules of non-periodic faces
+ * (plain fields, the mesh, and what = 2 displacements, 3 jxi_x, 4 jxi_t);
+ * the state (JU, J) by the reflecting / outflow / inflow rules */
 void   orc_fill_ghosts(const orc_grid *g, double *a, int ncomp);
 void   orc_fill_ghosts_x(const orc_grid *g, double *x);
+void   orc_fill_ghosts_kind(const orc_grid *g, double *a, int ncomp, int what);
+void   orc_fill_ghosts_state(const orc_grid *g, double *JU, double *J);
 int    orc_metrics(const orc_grid *g, const double *x_n, const double *disp,
                    double c_s, double dt, double *jxi_x, double *jxi_t);
 /* discrete Jacobian of a mesh from its metrics (for J at t = 0 on a mesh

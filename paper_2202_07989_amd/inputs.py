@@ -27,15 +27,29 @@ WATER_AIR = dict(gamma=(4.4, 1.4), cv=(1.0, 1.0), pinf=(6.0e8, 0.0))
 # --------------------------------------------------------------------------
 # workload specs
 # --------------------------------------------------------------------------
+BC_PERIODIC, BC_REFLECT, BC_OUTFLOW, BC_INFLOW = 0, 1, 2, 3
+
+
 def make_spec(dim, nspec, n, *, box=None, gamma=(1.4,), cv=(1.0,), pinf=(0.0,),
-              chi=CHI_DEFAULT, w=3, ng=3, dissipation=1, weno_eps=1e-10, reconstruction=0):
+              chi=CHI_DEFAULT, w=3, ng=3, dissipation=1, weno_eps=1e-10, reconstruction=0,
+              bc=None, wall=None, inflow=None):
+    """Workload spec.  Periodic in every direction unless bc gives per-face
+    conditions [(low, high), ...] (BC_*); wall then holds the physical
+    coordinates [(x_low, x_high), ...] of the faces (the computational box is
+    [0, x_high - x_low]) and inflow maps (direction, side) to the conserved
+    state U prescribed on an inflow face."""
     n = tuple(n) + (1,) * (3 - len(n))
     box = box or (1.0,) * dim
     box = tuple(box) + (1.0,) * (3 - len(box))
     dxi = tuple(box[k] / n[k] if k < dim else 1.0 for k in range(3))
-    return dict(dim=dim, nspec=nspec, n=n, ng=ng, dxi=dxi, len=box, w=w,
-                gamma=tuple(gamma), cv=tuple(cv), pinf=tuple(pinf), chi=tuple(chi),
-                weno_eps=weno_eps, dissipation=dissipation, reconstruction=reconstruction)
+    sp = dict(dim=dim, nspec=nspec, n=n, ng=ng, dxi=dxi, len=box, w=w,
+              gamma=tuple(gamma), cv=tuple(cv), pinf=tuple(pinf), chi=tuple(chi),
+              weno_eps=weno_eps, dissipation=dissipation, reconstruction=reconstruction)
+    if bc is not None:
+        sp["bc"] = [tuple(b) for b in bc]
+        sp["wall"] = [tuple(wl) for wl in (wall or [(0.0, box[k]) for k in range(dim)])]
+        sp["inflow"] = dict(inflow or {})
+    return sp
 
 
 def spec_c1(n=64):
@@ -293,6 +307,101 @@ def init_shock_bubble(spec, mach=1.5, shock_x=0.2, trace=1e-3, p0=1.0e5,
     v = [(1 - fb) * fs * u1] + [np.zeros_like(p) for _ in range(d - 1)]
     U = conserved(spec, rho, v, p)
     return assemble(spec, U, J, x)
+
+
+# --------------------------------------------------------------------------
+# the paper's two-species examples on walled domains (Examples 5.7 - 5.9).
+# Initial mesh uniform, x = wall_low + xi, J = 1.  Region boundaries are
+# spread over a tanh profile `width` cells wide: the scheme has no positivity
+# limiter, and with the examples' sharp data (partial densities down to
+# 1e-5 next to 1) a partial density turns negative in the first step.
+# --------------------------------------------------------------------------
+def _walled_mesh(spec):
+    xi = xi_nodes(spec)
+    return [xi[k] + spec["wall"][k][0] for k in range(spec["dim"])]
+
+
+def _step(phi, h, width):
+    """Smoothed indicator of phi > 0 (phi a signed distance)."""
+    return 0.5 * (1.0 + np.tanh(phi / (width * h))) if width > 0 else (phi > 0).astype(float)
+
+
+def _prims_at(spec, states, weights):
+    """Blend primitive states (rho_1, rho_2, v_1, v_2, p) with weights."""
+    N, d = spec["nspec"], spec["dim"]
+    rho = [sum(w * st[l] for st, w in zip(states, weights)) for l in range(N)]
+    v = [sum(w * st[N + j] for st, w in zip(states, weights)) for j in range(d)]
+    p = sum(w * st[N + d] for st, w in zip(states, weights))
+    return rho, v, p
+
+
+def spec_tripoint(n=(350, 150)):
+    """Example 5.7: [0, 7] x [0, 3], Gamma (1.5, 1.4), c_v 1, p_inf 0;
+    reflecting walls on all four faces (the paper does not name them)."""
+    return make_spec(2, 2, n, box=(7.0, 3.0), gamma=(1.5, 1.4), cv=(1.0, 1.0), pinf=(0.0, 0.0),
+                     chi=CHI_SHOCK, bc=[(BC_REFLECT, BC_REFLECT)] * 2, wall=[(0.0, 7.0), (0.0, 3.0)])
+
+
+def init_tripoint(spec, eps=1e-5, width=1.0):
+    """Three states: Omega_1 = [0,1]x[0,3] (1-eps, eps, 0, 0, 1), Omega_2 =
+    [1,7]x[1.5,3] (0.125-eps, eps, 0, 0, 0.1), Omega_3 = [1,7]x[0,1.5]
+    (eps, 1-eps, 0, 0, 0.1)."""
+    x = _walled_mesh(spec)
+    h = min(spec["dxi"][:2])
+    fl = _step(1.0 - x[0], h, width)
+    ft = _step(x[1] - 1.5, h, width)
+    z = np.zeros_like(x[0])
+    s1 = (1.0 - eps, eps, z, z, 1.0)
+    s2 = (0.125 - eps, eps, z, z, 0.1)
+    s3 = (eps, 1.0 - eps, z, z, 0.1)
+    rho, v, p = _prims_at(spec, [s1, s2, s3], [fl, (1 - fl) * ft, (1 - fl) * (1 - ft)])
+    return assemble(spec, conserved(spec, rho, v, p), np.ones_like(x[0]), x)
+
+
+# Example 5.8 (air / helium, ideal gases) and Example 5.9 (stiffened gas and
+# ideal gas): domain [0, 445] x [-44.5, 44.5], reflecting walls at the top
+# and bottom, outflow on the left, inflow of the post-shock state on the
+# right; a bubble of radius 25 at (225, 0); the shock at x_1 = 275 moving left.
+SB_CASES = {
+    "he": dict(gamma=(1.4, 1.647), Rg=(0.287, 1.578), pinf=(0.0, 0.0), eps=0.03,
+               bubble=lambda e, R: (e, 1.225 * (R[0] / R[1]) - e, 0.0, 0.0, 101325.0),
+               pre=lambda e: (1.225 - e, e, 0.0, 0.0, 101325.0),
+               post=lambda e: (1.6861 - e, e, -113.5243, 0.0, 159060.0)),
+    "stiff": dict(gamma=(3.0, 1.4), cv=(1.0, 1.0), pinf=(100.0, 0.0), eps=0.05,
+                  bubble=lambda e, R: (e, 5.0 - e, 0.0, 0.0, 100.0),
+                  pre=lambda e: (1.0 - e, e, 0.0, 0.0, 100.0),
+                  post=lambda e: (1.980198 - e, e, -121.2497, 0.0, 29800.0)),
+}
+
+
+def spec_shock_bubble2d(case="he", n=(800, 160)):
+    c = SB_CASES[case]
+    if "Rg" in c:
+        cv = tuple(R / (g - 1.0) for R, g in zip(c["Rg"], c["gamma"]))     # R_l = c_v,l (Gamma_l - 1)
+    else:
+        cv = c["cv"]
+    sp = make_spec(2, 2, n, box=(445.0, 89.0), gamma=c["gamma"], cv=cv, pinf=c["pinf"], chi=CHI_SHOCK,
+                   bc=[(BC_OUTFLOW, BC_INFLOW), (BC_REFLECT, BC_REFLECT)],
+                   wall=[(0.0, 445.0), (-44.5, 44.5)])
+    post = c["post"](c["eps"])
+    Uin = conserved(sp, [np.array(post[0]), np.array(post[1])], [np.array(post[2]), np.array(post[3])],
+                    np.array(post[4])).reshape(-1)
+    sp["inflow"] = {(0, 1): [float(u) for u in Uin]}
+    sp["example"] = case
+    return sp
+
+
+def init_shock_bubble2d(spec, width=1.0):
+    c = SB_CASES[spec["example"]]
+    e = c["eps"]
+    R = c.get("Rg", (1.0, 1.0))
+    x = _walled_mesh(spec)
+    h = min(spec["dxi"][:2])
+    fb = _step(25.0 - np.sqrt((x[0] - 225.0) ** 2 + x[1] ** 2), h, width)
+    fs = _step(x[0] - 275.0, h, width)
+    rho, v, p = _prims_at(spec, [c["bubble"](e, R), c["pre"](e), c["post"](e)],
+                          [fb * (1 - fs), (1 - fb) * (1 - fs), fs])
+    return assemble(spec, conserved(spec, rho, v, p), np.ones_like(x[0]), x)
 
 
 # --------------------------------------------------------------------------
