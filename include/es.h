@@ -15,8 +15,10 @@
  *     J dxi_k/dx_j; jxi_t: dim components, J dxi_k/dt.
  *   - Device scalars (dt, lambda, Delta_tau, entropy sums) are single FP64
  *     values in device memory so a step needs no host synchronisation.
- *   - The grid is periodic in every direction; ghost layers are filled by
- *     es_fill_ghosts / es_fill_ghosts_x.
+ *   - Each direction is periodic, or bounded by two faces each with a
+ *     reflecting wall, outflow or inflow condition (es_grid.bc); ghost
+ *     layers are filled by es_fill_ghosts / es_fill_ghosts_x /
+ *     es_fill_ghosts_state, and by the calls that produce a field.
  *
  * Streams: every call is asynchronous on the given hipStream_t (passed as
  * void*, NULL = default stream).  A context must not be used from two host
@@ -59,6 +61,22 @@ enum { ES_FP64 = 0, ES_MIXED = 1 };
  * with ES_MIXED, es_create and es_batch_create return ES_EUNSUPPORTED. */
 enum { ES_WENO_MR = 0, ES_WENO_JS = 1 };
 
+/* face conditions (es_grid.bc).  Section 5 runs its shock-bubble examples
+ * with reflecting walls on two faces and outflow / inflow on the others
+ * (Example 5.8) without giving their discrete form.  Here nodes stay
+ * cell-centred: a face lies halfway between the outermost interior node and
+ * the first ghost node, and the ghost node m layers outside images the
+ * interior node m - 1 layers inside (a mirror).  On every non-periodic face
+ * the mesh is mirrored about the face's coordinate wall (x_k -> 2 wall -
+ * x_k), so the mesh equations keep the face fixed and move the nodes along
+ * it; J and other plain fields are mirrored copies.  The state: ES_BC_REFLECT
+ * mirrors U with momentum component k negated; ES_BC_OUTFLOW copies U of
+ * the outermost interior node; ES_BC_INFLOW sets the face's prescribed
+ * conserved state es_grid.inflow; each times the mirrored J.  A direction
+ * is periodic on both faces or on neither.  Batches take periodic grids
+ * only (ES_EUNSUPPORTED). */
+enum { ES_BC_PERIODIC = 0, ES_BC_REFLECT = 1, ES_BC_OUTFLOW = 2, ES_BC_INFLOW = 3 };
+
 typedef struct {
     int dim;           /* d = 2 or 3                                            */
     int nspec;         /* N = 1 or 2                                            */
@@ -76,6 +94,12 @@ typedef struct {
     int precision;     /* ES_FP64, or ES_MIXED: FP32 flux/WENO arithmetic with  */
                        /* FP64 log means, metrics, mesh and entropy sums        */
     int reconstruction;/* ES_WENO_MR or ES_WENO_JS (else ES_EUNSUPPORTED)       */
+    int bc[3][2];      /* ES_BC_* of the low [k][0] and high [k][1] face of     */
+                       /* direction k; zero (all periodic) by default           */
+    double wall[3][2]; /* physical coordinate x_k of each non-periodic face     */
+                       /* (wall[k][1] > wall[k][0])                             */
+    double inflow[3][2][6]; /* conserved state U (rho_1..rho_N, rho v, E) of    */
+                       /* each ES_BC_INFLOW face (finite)                       */
 } es_grid;
 
 typedef struct {
@@ -104,18 +128,25 @@ typedef struct es_ctx es_ctx;
 int es_create(const es_grid *g, es_ctx **out);
 int es_destroy(es_ctx *c);
 
-/* Periodic ghost layers of an ncomp-component field (plain copies). */
+/* Ghost layers of an ncomp-component field without direction (J, monitor
+ * values): periodic copies, mirrored copies across non-periodic faces. */
 int es_fill_ghosts(es_ctx *c, double *a, int ncomp, void *stream);
 
-/* Periodic ghost layers of the mesh x: component k gains +-L_k when wrapped
- * along direction k (x(xi + L e_k) = x(xi) + L_k e_k). */
+/* Ghost layers of the mesh x: component k gains +-L_k when wrapped along a
+ * periodic direction k (x(xi + L e_k) = x(xi) + L_k e_k); mirrored about
+ * the face (x_k -> 2 wall - x_k) across a non-periodic one. */
 int es_fill_ghosts_x(es_ctx *c, double *x, void *stream);
+
+/* Ghost layers of the state: J (as es_fill_ghosts), then JU by the face
+ * conditions (ES_BC_*).  JU and J must differ (ES_EINVAL). */
+int es_fill_ghosts_state(es_ctx *c, double *JU, double *J, void *stream);
 
 /* Section 3.2, eq SCLCoeff / eq VCLCoeff: metrics of the stage mesh
  * x = x_n + c_s * disp (disp may be NULL: fixed mesh).  jxi_x gets the
  * 2w-th order conservative cross-derivative form at interior nodes; jxi_t =
  * -sum_j (disp_j / dt) jxi_x[k][j] when disp and dt_dev are given, else 0.
- * Ghost layers of the outputs are filled periodically.  x_n and disp need
+ * Ghost layers of the outputs are filled (wrapped, or as the mirrored mesh
+ * gives them across non-periodic faces).  x_n and disp need
  * valid ghost layers.  flags: 0, or ES_METRICS_VCL_ONLY to recompute only
  * jxi_t from an existing jxi_x. */
 enum { ES_METRICS_VCL_ONLY = 1 };
@@ -161,7 +192,8 @@ int max_wavespeed(es_ctx *c, const double *JU, const double *J,
 /* Section 4: monitor eq monitor from sigma = JU/J components, n_smooth
  * passes of the low-pass filter, n_sweeps Jacobi iterations of the mesh
  * equations, movement limiter Delta_tau and disp = Delta_tau (x^[mu] - x_n).
- * Inputs need valid ghost layers; disp gets periodic ghost layers.
+ * Inputs need valid ghost layers; disp gets its ghost layers (component k
+ * negated across a non-periodic face of direction k).
  * dtau_dev (1 value) and resid_dev (n_sweeps values: max |x^[nu+1] -
  * x^[nu]|) may be NULL. */
 int mesh_redistribute(es_ctx *c, const es_monitor *m, const double *JU,

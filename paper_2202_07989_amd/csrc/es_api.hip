@@ -15,6 +15,7 @@ struct es_ctx {
     es_grid grid;
     Phys ph;
     Geo geo;
+    InflowStates inflow;
     int device;
     unsigned* status = nullptr;   // device status word
     double* scal = nullptr;       // 16 device scalars: [0] lambda [1] dt [2..] scratch
@@ -71,8 +72,19 @@ int check_grid(const es_grid* g)
     if (g->precision != ES_FP64 && g->precision != ES_MIXED) return ES_EUNSUPPORTED;
     if (g->reconstruction != ES_WENO_MR && g->reconstruction != ES_WENO_JS) return ES_EUNSUPPORTED;
     if (g->reconstruction == ES_WENO_JS && g->precision != ES_FP64) return ES_EUNSUPPORTED;
-    for (int k = 0; k < g->dim; k++)
+    const int nc = g->nspec + g->dim + 1;
+    for (int k = 0; k < g->dim; k++) {
         if (g->n[k] < g->ng || !(g->dxi[k] > 0.0) || !(g->len[k] > 0.0)) return ES_EINVAL;
+        for (int s = 0; s < 2; s++)
+            if (g->bc[k][s] < ES_BC_PERIODIC || g->bc[k][s] > ES_BC_INFLOW) return ES_EINVAL;
+        // a direction is periodic on both faces or on neither
+        if ((g->bc[k][0] == ES_BC_PERIODIC) != (g->bc[k][1] == ES_BC_PERIODIC)) return ES_EINVAL;
+        if (g->bc[k][0] != ES_BC_PERIODIC && !(g->wall[k][1] > g->wall[k][0])) return ES_EINVAL;
+        for (int s = 0; s < 2; s++)
+            if (g->bc[k][s] == ES_BC_INFLOW)
+                for (int q = 0; q < nc; q++)
+                    if (!std::isfinite(g->inflow[k][s][q])) return ES_EINVAL;
+    }
     if (g->dim == 2 && g->n[2] != 1) return ES_EINVAL;
     for (int l = 0; l < g->nspec; l++)
         if (!(g->gamma[l] > 1.0) || !(g->cv[l] > 0.0) || !(g->pinf[l] >= 0.0)) return ES_EINVAL;
@@ -121,6 +133,10 @@ void build_params(const es_grid* g, Phys& ph, Geo& geo)
         geo.dxi[k] = act ? g->dxi[k] : 1.0;
         geo.idxi[k] = 1.0 / geo.dxi[k];
         geo.len[k] = act ? g->len[k] : 1.0;
+        for (int s = 0; s < 2; s++) {
+            geo.bc[k][s] = act ? g->bc[k][s] : BC_PERIODIC;
+            geo.wall[k][s] = act ? g->wall[k][s] : 0.0;
+        }
     }
     geo.P = (long)geo.np[0] * geo.np[1] * geo.np[2];
 }
@@ -214,6 +230,7 @@ int es_create(const es_grid* g, es_ctx** out)
     if (!c) return ES_EHIP;
     c->grid = *g;
     build_params(g, c->ph, c->geo);
+    std::memcpy(c->inflow.u, g->inflow, sizeof(c->inflow.u));
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return ES_EHIP; }
     rc = dalloc(&c->status, 4);
     if (!rc) rc = dalloc(&c->scal, 16);
@@ -246,13 +263,19 @@ long es_npoints(const es_ctx* c) { return c ? c->geo.P : 0; }
 int es_fill_ghosts(es_ctx* c, double* a, int ncomp, void* stream)
 {
     if (!c || !a || ncomp < 1 || ncomp > 16) return ES_EINVAL;
-    return hip_rc(fill_ghosts(c->geo, a, ncomp, 0, S(stream)));
+    return hip_rc(fill_ghosts(c->geo, a, ncomp, GH_PLAIN, S(stream)));
 }
 
 int es_fill_ghosts_x(es_ctx* c, double* x, void* stream)
 {
     if (!c || !x) return ES_EINVAL;
-    return hip_rc(fill_ghosts(c->geo, x, c->geo.dim, 1, S(stream)));
+    return hip_rc(fill_ghosts(c->geo, x, c->geo.dim, GH_MESH, S(stream)));
+}
+
+int es_fill_ghosts_state(es_ctx* c, double* JU, double* J, void* stream)
+{
+    if (!c || !JU || !J || JU == J) return ES_EINVAL;
+    return hip_rc(fill_state(c->geo, c->inflow, JU, J, c->ph.nc, c->ph.nspec, S(stream)));
 }
 
 int es_metrics(es_ctx* c, const double* x_n, const double* disp, double c_s, const double* dt_dev,
@@ -365,9 +388,8 @@ int es_step(es_ctx* c, const es_monitor* m, double cfl, double dt_fixed, int mov
         if ((expr) != hipSuccess) return ES_EHIP;     \
     } while (0)
 
-    ES_TRY(fill_ghosts(g, JU, nc, 0, s));
-    ES_TRY(fill_ghosts(g, J, 1, 0, s));
-    ES_TRY(fill_ghosts(g, x, d, 1, s));
+    ES_TRY(fill_state(g, c->inflow, JU, J, nc, ph.nspec, s));
+    ES_TRY(fill_ghosts(g, x, d, GH_MESH, s));
     const double* disp = nullptr;
     if (move_mesh) {
         MonitorP mo = monitor_params(m);
@@ -399,13 +421,12 @@ int es_step(es_ctx* c, const es_monitor* m, double cfl, double dt_fixed, int mov
         RkArgs rk{JU, J, dt, A[st], B[st], outs[st][0], outs[st][1], (disp && st == 0) ? dt : nullptr};
         ES_TRY(launch_rhs(ph, g, mixed, inU, inJ, c->jxx, disp ? c->jxt : nullptr, accs[st][0], accs[st][1],
                           &rk, c->status, s));
-        ES_TRY(fill_ghosts(g, outs[st][0], nc, 0, s));
-        ES_TRY(fill_ghosts(g, outs[st][1], 1, 0, s));
+        ES_TRY(fill_state(g, c->inflow, outs[st][0], outs[st][1], nc, ph.nspec, s));
         inU = outs[st][0];
         inJ = outs[st][1];
     }
     if (disp) ES_TRY(add_inplace(x, disp, d * P, s));
-    ES_TRY(fill_ghosts(g, x, d, 1, s));
+    ES_TRY(fill_ghosts(g, x, d, GH_MESH, s));
     if (dt_dev) ES_TRY(copy(dt, dt_dev, 1, s));
     if (dtau_dev) ES_TRY(copy(dtau, dtau_dev, 1, s));
 #undef ES_TRY
@@ -480,6 +501,8 @@ int es_batch_create(const es_grid* grids, int count, es_batch** out)
         const int rc = check_grid(&grids[i]);
         if (rc) return rc;
         if (grids[i].dim != 2) return ES_EUNSUPPORTED;
+        for (int k = 0; k < 2; k++)
+            if (grids[i].bc[k][0] != ES_BC_PERIODIC) return ES_EUNSUPPORTED;   // batches are periodic
         if (!same_scheme(grids[0], grids[i])) return ES_EINVAL;
     }
     es_batch* b = new (std::nothrow) es_batch();

@@ -29,7 +29,11 @@ struct Geo {
     int np[3];                // padded extents
     long P;                   // points per component
     double dxi[3], idxi[3], len[3];
+    int bc[3][2];             // face conditions (BC_*), [k][0] low face, [k][1] high face
+    double wall[3][2];        // physical coordinate x_k of the non-periodic faces
 };
+
+enum { BC_PERIODIC = 0, BC_REFLECT = 1, BC_OUTFLOW = 2, BC_INFLOW = 3 };
 
 __device__ __forceinline__ long node_index(const Geo& g, int i0, int i1, int i2)
 {

@@ -1,89 +1,167 @@
-// es_kernels.hip -- the HBM-bound steps of the path on gfx950: periodic
-// ghost layers, GCL metrics (Section 3.2), the CFL wave speed (Section 5),
+// es_kernels.hip -- the HBM-bound steps of the path on gfx950: ghost
+// layers, GCL metrics (Section 3.2), the CFL wave speed (Section 5),
 // mesh redistribution (Section 4) and the FP64 entropy sums.
 #include "es_kernels.hpp"
 
 namespace es {
 
 // ---------------------------------------------------------------------------
-// periodic ghost layers: one pass per direction k over the two ghost slabs of
-// k; pass k covers the full padded range of the directions already done
-// (so edges and corners come out right) and the interior of the others.
-// ---------------------------------------------------------------------------
-// Periodic ghost layers in one launch: every ghost node (the shell of the
+// Ghost layers in one launch per field: every ghost node (the shell of the
 // padded box: the z slabs, then the y slabs over interior z, then the x slabs
-// over interior y and z) copies the interior node it wraps to, with all
-// coordinates wrapped at once.  For the mesh (is_x) component k gains
-// -L_k / +L_k when the node lies below / above the interior along k, the
-// same single shift a direction-by-direction fill would apply.
-__global__ void k_fill_shell(Geo g, double* __restrict__ a, int ncomp, int is_x, long nzs, long nys, long nxs)
+// over interior y and z) takes the value of one interior node, with all of
+// its out-of-range coordinates mapped at once.
+//
+// Periodic faces wrap (the mesh gains -L_k / +L_k in component k below /
+// above the interior along k).  The boundary conditions of the paper's
+// walled examples (reflecting walls, outflow, inflow) are taken with
+// cell-centred nodes: the face lies halfway between the outermost node and
+// the first ghost node, and the ghost node m layers outside mirrors the
+// interior node m - 1 layers inside.  Across such a face the mesh is
+// mirrored about the face's coordinate (x_k -> 2 wall - x_k), displacements
+// and time metrics negate component k, and a metric J dxi_a/dx_b is negated
+// when exactly one of a, b is k: the values the mirrored mesh has.  The
+// state is filled by fill_state.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void shell_node(const Geo& g, long t, long nzs, long nys, int d[3])
 {
     const int ng = g.ng;
     const int np0 = g.np[0], np1 = g.np[1];
     const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
-    const int z0 = g.dim == 3 ? ng : 0, nz = g.dim == 3 ? n2 : 1;
-    (void)nz;
+    const int z0 = g.dim == 3 ? ng : 0;
+    if (t < nzs) {                                   // z ghost planes
+        const long pl = (long)np0 * np1;
+        const int k = (int)(t / pl);
+        const int r = (int)(t % pl);
+        d[2] = k < ng ? k : k + n2;
+        d[1] = r / np0;
+        d[0] = r % np0;
+    } else if (t < nzs + nys) {                      // y ghost rows over interior z
+        const long u = t - nzs;
+        const long per = 2L * ng * np0;
+        d[2] = z0 + (int)(u / per);
+        const int r = (int)(u % per);
+        const int k = r / np0;
+        d[1] = k < ng ? k : k + n1;
+        d[0] = r % np0;
+    } else {                                         // x ghost columns over interior y, z
+        const long u = t - nzs - nys;
+        const long row = u / (2 * ng);
+        const int k = (int)(u % (2 * ng));
+        d[0] = k < ng ? k : k + n0;
+        d[1] = ng + (int)(row % n1);
+        d[2] = z0 + (int)(row / n1);
+    }
+}
+
+// interior image of padded index i along k; side = -1 / +1 below / above
+// the interior, 0 inside
+__device__ __forceinline__ int ghost_image(const Geo& g, int k, int i, int& side)
+{
+    const int n = g.n[k], r = i - g.ng;
+    side = r < 0 ? -1 : (r >= n ? 1 : 0);
+    if (!side) return i;
+    if (g.bc[k][side > 0] == BC_PERIODIC) return (side < 0 ? r + n : r - n) + g.ng;
+    return (side < 0 ? -1 - r : 2 * n - 1 - r) + g.ng;
+}
+
+__global__ void k_fill_shell(Geo g, double* __restrict__ a, int ncomp, int what, long nzs, long nys, long nxs)
+{
     const long total = nzs + nys + nxs;
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
         int d[3];
-        if (t < nzs) {                                   // z ghost planes
-            const long pl = (long)np0 * np1;
-            const int k = (int)(t / pl);
-            const int r = (int)(t % pl);
-            d[2] = k < ng ? k : k + n2;
-            d[1] = r / np0;
-            d[0] = r % np0;
-        } else if (t < nzs + nys) {                      // y ghost rows over interior z
-            const long u = t - nzs;
-            const long per = 2L * ng * np0;
-            d[2] = z0 + (int)(u / per);
-            const int r = (int)(u % per);
-            const int k = r / np0;
-            d[1] = k < ng ? k : k + n1;
-            d[0] = r % np0;
-        } else {                                         // x ghost columns over interior y, z
-            const long u = t - nzs - nys;
-            const long row = u / (2 * ng);
-            const int k = (int)(u % (2 * ng));
-            d[0] = k < ng ? k : k + n0;
-            d[1] = ng + (int)(row % n1);
-            d[2] = z0 + (int)(row / n1);
-        }
-        int sidx[3];
-        double shift[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-            sidx[k] = d[k];
-            if (k < g.dim) {
-                if (d[k] < ng) {
-                    sidx[k] = d[k] + g.n[k];
-                    shift[k] = -g.len[k];
-                } else if (d[k] >= ng + g.n[k]) {
-                    sidx[k] = d[k] - g.n[k];
-                    shift[k] = g.len[k];
-                }
-            }
-        }
+        shell_node(g, t, nzs, nys, d);
+        int sidx[3] = {d[0], d[1], d[2]}, side[3] = {0, 0, 0};
+        for (int k = 0; k < g.dim; k++) sidx[k] = ghost_image(g, k, d[k], side[k]);
         const long di = node_index(g, d[0], d[1], d[2]);
         const long si = node_index(g, sidx[0], sidx[1], sidx[2]);
         for (int c = 0; c < ncomp; c++) {
             double v = a[c * g.P + si];
-            if (is_x && c < g.dim) v += shift[c];
+            for (int k = 0; k < g.dim; k++) {
+                if (!side[k]) continue;
+                if (g.bc[k][side[k] > 0] == BC_PERIODIC) {
+                    if (what == GH_MESH && c == k) v += side[k] * g.len[k];
+                    continue;
+                }
+                if (what == GH_MESH && c == k) v = 2.0 * g.wall[k][side[k] > 0] - v;
+                if ((what == GH_DISP || what == GH_JXT) && c == k) v = -v;
+                if (what == GH_JXX && ((c / g.dim == k) != (c % g.dim == k))) v = -v;
+            }
             a[c * g.P + di] = v;
         }
     }
 }
 
-hipError_t fill_ghosts(const Geo& g, double* a, int ncomp, int is_x, hipStream_t s)
+// the state's ghosts (J's are filled first): a reflecting wall mirrors U
+// with momentum component k negated, outflow copies U of the outermost
+// interior node, inflow takes the face's prescribed state (the lowest
+// direction's where several meet); JU = J (mirrored) times that U
+__global__ void k_fill_state(Geo g, InflowStates in, double* __restrict__ JU, const double* __restrict__ J,
+                             int nc, int nspec, long nzs, long nys, long nxs)
+{
+    const long total = nzs + nys + nxs;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+        int d[3];
+        shell_node(g, t, nzs, nys, d);
+        int src[3] = {d[0], d[1], d[2]};
+        int flip = 0, uk = -1, us = 0;
+        bool extrap = false;
+        for (int k = 0; k < g.dim; k++) {
+            int side;
+            src[k] = ghost_image(g, k, d[k], side);
+            if (!side) continue;
+            const int kind = g.bc[k][side > 0];
+            if (kind == BC_REFLECT) flip |= 1 << k;
+            if (kind == BC_OUTFLOW) {
+                src[k] = side < 0 ? g.ng : g.ng + g.n[k] - 1;
+                extrap = true;
+            }
+            if (kind == BC_INFLOW && uk < 0) {
+                uk = k;
+                us = side > 0;
+            }
+        }
+        const long di = node_index(g, d[0], d[1], d[2]);
+        const long si = node_index(g, src[0], src[1], src[2]);
+        for (int c = 0; c < nc; c++) {
+            double u;
+            if (uk >= 0) u = J[di] * in.u[uk][us][c];
+            else if (extrap) u = J[di] * (JU[c * g.P + si] / J[si]);
+            else u = JU[c * g.P + si];
+            if (uk < 0 && c >= nspec && c < nspec + g.dim && ((flip >> (c - nspec)) & 1)) u = -u;
+            JU[c * g.P + di] = u;
+        }
+    }
+}
+
+static void shell_sizes(const Geo& g, long& nzs, long& nys, long& nxs)
 {
     const long ng2 = 2L * g.ng;
     const long nz = g.dim == 3 ? g.n[2] : 1;
-    const long nzs = g.dim == 3 ? ng2 * g.np[0] * g.np[1] : 0;
-    const long nys = ng2 * g.np[0] * nz;
-    const long nxs = ng2 * g.n[1] * nz;
+    nzs = g.dim == 3 ? ng2 * g.np[0] * g.np[1] : 0;
+    nys = ng2 * g.np[0] * nz;
+    nxs = ng2 * g.n[1] * nz;
+}
+
+hipError_t fill_ghosts(const Geo& g, double* a, int ncomp, int what, hipStream_t s)
+{
+    long nzs, nys, nxs;
+    shell_sizes(g, nzs, nys, nxs);
     const long total = nzs + nys + nxs;
     const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_fill_shell, dim3(blocks), dim3(256), 0, s, g, a, ncomp, is_x, nzs, nys, nxs);
+    hipLaunchKernelGGL(k_fill_shell, dim3(blocks), dim3(256), 0, s, g, a, ncomp, what, nzs, nys, nxs);
+    return hipGetLastError();
+}
+
+hipError_t fill_state(const Geo& g, const InflowStates& in, double* JU, double* J, int nc, int nspec,
+                      hipStream_t s)
+{
+    hipError_t e = fill_ghosts(g, J, 1, GH_PLAIN, s);
+    if (e != hipSuccess) return e;
+    long nzs, nys, nxs;
+    shell_sizes(g, nzs, nys, nxs);
+    const long total = nzs + nys + nxs;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill_state, dim3(blocks), dim3(256), 0, s, g, in, JU, J, nc, nspec, nzs, nys, nxs);
     return hipGetLastError();
 }
 
@@ -433,7 +511,7 @@ hipError_t jacobian(const Phys& ph, const Geo& g, const double* x, const double*
     const long nint = (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1);
     hipLaunchKernelGGL(k_jacobian, dim3(grid_for(nint)), dim3(256), 0, s, g, ph, x, jxx, J);
     const hipError_t e = hipGetLastError();
-    return e != hipSuccess ? e : fill_ghosts(g, J, 1, 0, s);
+    return e != hipSuccess ? e : fill_ghosts(g, J, 1, GH_PLAIN, s);
 }
 
 hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double* disp, double cs,
@@ -464,10 +542,10 @@ hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double*
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (!vcl_only) {
-        e = fill_ghosts(g, jxx, g.dim * g.dim, 0, s);
+        e = fill_ghosts(g, jxx, g.dim * g.dim, GH_JXX, s);
         if (e != hipSuccess) return e;
     }
-    if (jxt) e = fill_ghosts(g, jxt, g.dim, 0, s);
+    if (jxt) e = fill_ghosts(g, jxt, g.dim, GH_JXT, s);
     return e;
 }
 
@@ -1120,7 +1198,7 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, c
         hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part + q * RED_BLOCKS,
                            march ? jblocks : nb, w.scal + q, 0, 0.0, status);
     hipLaunchKernelGGL(k_theta, dim3(gi), dim3(256), 0, s, g, mo, w.grad, w.scal, w.th0);
-    hipError_t e = fill_ghosts(g, w.th0, 1, 0, s);
+    hipError_t e = fill_ghosts(g, w.th0, 1, GH_PLAIN, s);
     if (e != hipSuccess) return e;
     double* th = w.th0;
     double* th2 = w.th1;
@@ -1129,7 +1207,7 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, c
             hipLaunchKernelGGL(k_filter3, jgrid, dim3(256), 0, s, g, th, th2, jchunk);
         else
             hipLaunchKernelGGL(k_filter, dim3(gi), dim3(256), 0, s, g, th, th2);
-        if ((e = fill_ghosts(g, th2, 1, 0, s)) != hipSuccess) return e;
+        if ((e = fill_ghosts(g, th2, 1, GH_PLAIN, s)) != hipSuccess) return e;
         std::swap(th, th2);
     }
     // Jacobi sweeps: the first reads x_n itself, then xa and xb alternate
@@ -1143,7 +1221,7 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, c
             hipLaunchKernelGGL(k_jacobi<2>, dim3(nb), dim3(256), 0, s, g, th, xcur, xa, w.part);
         else
             hipLaunchKernelGGL(k_jacobi<3>, dim3(nb), dim3(256), 0, s, g, th, xcur, xa, w.part);
-        if ((e = fill_ghosts(g, xa, g.dim, 1, s)) != hipSuccess) return e;
+        if ((e = fill_ghosts(g, xa, g.dim, GH_MESH, s)) != hipSuccess) return e;
         if (resid_out)
             hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part, march ? jblocks : nb,
                                resid_out + nu, 0, 0.0, status);
@@ -1158,7 +1236,7 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, c
     hipLaunchKernelGGL(k_finish<RED_MIN>, dim3(1), dim3(256), 0, s, w.part, nb, w.scal + 4, 2, 0.0, status);
     if ((e = fill_value(disp, g.dim * P, 0.0, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_disp, dim3(gi), dim3(256), 0, s, g, xcur, xn, w.scal + 4, disp);
-    if ((e = fill_ghosts(g, disp, g.dim, 0, s)) != hipSuccess) return e;
+    if ((e = fill_ghosts(g, disp, g.dim, GH_DISP, s)) != hipSuccess) return e;
     if (dtau_out && (e = copy(w.scal + 4, dtau_out, 1, s)) != hipSuccess) return e;
     return hipGetLastError();
 }

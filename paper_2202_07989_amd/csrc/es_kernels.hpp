@@ -31,7 +31,21 @@ struct MeshWork {
 
 struct RkArgs;
 
-hipError_t fill_ghosts(const Geo& g, double* a, int ncomp, int is_x, hipStream_t s);
+// what a ghost fill treats: plain fields, the mesh x, displacements, the
+// metrics J dxi_k/dx_j, the time metrics J dxi_k/dt (they differ only in
+// the signs and offsets a mirror across a non-periodic face gives them)
+enum { GH_PLAIN = 0, GH_MESH = 1, GH_DISP = 2, GH_JXX = 3, GH_JXT = 4 };
+
+// prescribed conserved states of the inflow faces
+struct InflowStates {
+    double u[3][2][6];
+};
+
+hipError_t fill_ghosts(const Geo& g, double* a, int ncomp, int what, hipStream_t s);
+// ghost layers of the state: J, then JU by the reflecting / outflow / inflow
+// rules (periodic faces wrap)
+hipError_t fill_state(const Geo& g, const InflowStates& in, double* JU, double* J, int nc, int nspec,
+                      hipStream_t s);
 hipError_t copy(const double* src, double* dst, long n, hipStream_t s);
 hipError_t fill_value(double* dst, long n, double v, hipStream_t s);
 hipError_t add_inplace(double* a, const double* b, long n, hipStream_t s);

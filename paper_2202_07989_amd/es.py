@@ -21,6 +21,7 @@ ES_FP64, ES_MIXED = 0, 1
 ES_WENO_MR, ES_WENO_JS = 0, 1
 ES_MONITOR_GRAD2, ES_MONITOR_GRAD_LAP = 0, 1
 ES_METRICS_VCL_ONLY = 1
+ES_BC_PERIODIC, ES_BC_REFLECT, ES_BC_OUTFLOW, ES_BC_INFLOW = 0, 1, 2, 3
 
 
 class EsError(RuntimeError):
@@ -35,7 +36,8 @@ class EsGrid(C.Structure):
         ("dxi", C.c_double * 3), ("len", C.c_double * 3), ("w", C.c_int),
         ("gamma", C.c_double * 2), ("cv", C.c_double * 2), ("pinf", C.c_double * 2),
         ("chi", C.c_double * 3), ("weno_eps", C.c_double), ("dissipation", C.c_int),
-        ("precision", C.c_int), ("reconstruction", C.c_int),
+        ("precision", C.c_int), ("reconstruction", C.c_int), ("bc", (C.c_int * 2) * 3),
+        ("wall", (C.c_double * 2) * 3), ("inflow", ((C.c_double * 6) * 2) * 3),
     ]
 
 
@@ -52,6 +54,7 @@ _SIGS = {
     "es_destroy": [_P],
     "es_fill_ghosts": [_P, _P, C.c_int, _P],
     "es_fill_ghosts_x": [_P, _P, _P],
+    "es_fill_ghosts_state": [_P, _P, _P, _P],
     "es_metrics": [_P, _P, _P, C.c_double, _P, _P, _P, C.c_int, _P],
     "es_rhs": [_P, _P, _P, _P, _P, _P, _P, _P],
     "es_rk_stage": [_P, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
@@ -128,6 +131,15 @@ def make_grid(spec, precision=ES_FP64) -> EsGrid:
     g.dissipation = spec.get("dissipation", 1)
     g.reconstruction = spec.get("reconstruction", ES_WENO_MR)
     g.precision = precision
+    for k, faces in enumerate(spec.get("bc", [])):
+        for side in range(2):
+            g.bc[k][side] = faces[side]
+    for k, faces in enumerate(spec.get("wall", [])):
+        for side in range(2):
+            g.wall[k][side] = faces[side]
+    for (k, side), U in spec.get("inflow", {}).items():
+        for c, u in enumerate(U):
+            g.inflow[k][side][c] = u
     return g
 
 
@@ -176,6 +188,9 @@ class Context:
 
     def es_fill_ghosts_x(self, x, stream=None):
         _check("es_fill_ghosts_x", lib.es_fill_ghosts_x(self.h, _ptr(x), _stream(stream)))
+
+    def es_fill_ghosts_state(self, JU, J, stream=None):
+        _check("es_fill_ghosts_state", lib.es_fill_ghosts_state(self.h, _ptr(JU), _ptr(J), _stream(stream)))
 
     def es_metrics(self, x_n, disp, c_s, dt_dev, jxi_x, jxi_t, flags=0, stream=None):
         _check("es_metrics", lib.es_metrics(self.h, _ptr(x_n), _ptr(disp), float(c_s), _ptr(dt_dev),

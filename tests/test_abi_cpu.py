@@ -78,3 +78,27 @@ def test_invalid_arguments_rejected_before_any_launch(lib):
     assert es.lib.es_step(null, null, 0.4, 0.0, 0, null, null, null, null, null, null) == es.ES_EINVAL
     assert es.lib.es_status(null, null, null, 0) == es.ES_EINVAL
     assert es.lib.es_destroy(null) == es.ES_EINVAL
+
+
+def test_face_conditions_checked_before_any_launch(lib):
+    """A direction is periodic on both faces or on neither; faces of a
+    non-periodic direction need wall[k][1] > wall[k][0]; kinds stay in
+    ES_BC_*; inflow states are finite; batches take periodic grids only."""
+    from paper_2202_07989_amd import es
+    from paper_2202_07989_amd import inputs as I
+    h = C.c_void_p()
+    sp = I.spec_shock_bubble2d("he", (16, 8))
+    for bad in ("half-periodic", "wall-order", "kind", "inflow-nan"):
+        g = es.make_grid(sp)
+        if bad == "half-periodic":
+            g.bc[1][0] = es.ES_BC_PERIODIC
+        elif bad == "wall-order":
+            g.wall[1][0], g.wall[1][1] = 1.0, -1.0
+        elif bad == "kind":
+            g.bc[0][1] = 7
+        elif bad == "inflow-nan":
+            g.inflow[0][1][2] = float("nan")
+        assert es.lib.es_create(C.byref(g), C.byref(h)) == es.ES_EINVAL, bad
+    grids = (es.EsGrid * 1)(es.make_grid(sp))
+    assert es.lib.es_batch_create(C.cast(grids, C.c_void_p), 1, C.byref(h)) == es.ES_EUNSUPPORTED
+    assert es.lib.es_fill_ghosts_state(None, None, None, None) == es.ES_EINVAL
