@@ -529,17 +529,28 @@ EXAMPLES = {
     "tripoint": dict(t_end=5.0, alpha=1200.0, n_smooth=10, paper_s={"moving": 201.0, "uniform": 49.0},
                      what="Example 5.7 tri-point, 350 x 150, t = 5"),
     "shock-bubble-he": dict(t_end=0.676, alpha=1000.0, paper_s={"moving": 3840.0, "uniform": 552.0},
+                            case="he", n=(800, 160),
                             what="Example 5.8 shock / helium bubble, 800 x 160, t = 0.676"),
     "shock-bubble-stiff": dict(t_end=0.8, alpha=1200.0, paper_s={"moving": 568.0, "uniform": 107.0},
+                               case="stiff", n=(800, 160),
                                what="Example 5.9 shock / bubble in stiffened gas, 800 x 160, t = 0.8"),
+    # 10 filter passes here too: with 3 the mesh gathers around the light
+    # bubble until the smallest J is 5e-4 (t = 0.07) and then tangles
+    "shock-bubble-he-3d": dict(t_end=0.72, alpha=1200.0, n_smooth=10,
+                               paper_s={"moving": 39960.0, "uniform": 9240.0},
+                               case="he", n=(400, 80, 80),
+                               what="Example 5.10 3D shock / helium bubble, 400 x 80 x 80, t = 0.72"),
+    "shock-bubble-stiff-3d": dict(t_end=0.64, sigma=(1, 3), alpha=(500.0, 500.0),
+                                  paper_s={"moving": 7740.0, "uniform": 2792.0}, case="stiff", n=(400, 80, 80),
+                                  what="Example 5.11 3D shock / bubble in stiffened gas, 400 x 80 x 80, t = 0.64"),
 }
 
 
 def example_run(args):
     """One of the paper's walled examples (reflecting walls; outflow and
     inflow for the shock-bubble runs) advanced to its final time at CFL 0.4
-    with 10 Jacobi sweeps and 3 filter passes per step (the paper's
-    settings; 10 passes for the tri-point), on the moving mesh or the uniform mesh (--mesh).  Reports the
+    (0.3 in 3D) with 10 Jacobi sweeps and 3 filter passes per step (the paper's
+    settings; 10 passes for the tri-point and Example 5.10), on the moving mesh or the uniform mesh (--mesh).  Reports the
     wall-clock time from the first step to the last (inputs resident on the
     GPU; the host reads each step's dt back to land on the final time), the
     cell-stage rate, the smallest partial density, and for walls on every
@@ -555,13 +566,15 @@ def example_run(args):
         sp = I.spec_tripoint()
         JU, J, x = I.init_tripoint(sp)
     else:
-        sp = I.spec_shock_bubble2d(args.example.split("-")[-1])
-        JU, J, x = I.init_shock_bubble2d(sp)
+        sp = I.spec_shock_bubble_walled(ex["case"], ex["n"])
+        JU, J, x = I.init_shock_bubble_walled(sp)
     if args.precision == "mixed":
         prec = es.ES_MIXED
     else:
         prec = es.ES_FP64
-    mon = I.monitor_spec(n_sweeps=10, n_smooth=ex.get("n_smooth", 3), sigma=(0,), alpha=(ex["alpha"],))
+    alpha = ex["alpha"] if isinstance(ex["alpha"], tuple) else (ex["alpha"],)
+    mon = I.monitor_spec(n_sweeps=10, n_smooth=ex.get("n_smooth", 3), sigma=ex.get("sigma", (0,)), alpha=alpha)
+    cfl = 0.4 if sp["dim"] == 2 else 0.3
     move = args.mesh == "moving"
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     ctx = es.Context(sp, precision=prec)
@@ -581,7 +594,7 @@ def example_run(args):
             fixed = rem
         elif dt_prev is not None and rem < 2.0 * dt_prev:
             fixed = 0.5 * rem
-        ctx.es_step(gU, gJ, gx, mon=mon, cfl=0.4, dt_fixed=fixed, move_mesh=move, dt_dev=dt_dev)
+        ctx.es_step(gU, gJ, gx, mon=mon, cfl=cfl, dt_fixed=fixed, move_mesh=move, dt_dev=dt_dev)
         dt = float(dt_dev.item())
         t += dt
         dt_prev = dt
@@ -597,7 +610,7 @@ def example_run(args):
     rc, flags = ctx.es_status()
     hU, hJ, hx = gU.cpu().numpy(), gJ.cpu().numpy(), gx.cpu().numpy()
     rho = hU[Iin][:2] / hJ[Iin]
-    cells = sp["n"][0] * sp["n"][1]
+    cells = int(np.prod(sp["n"][:sp["dim"]]))
     out = {"mode": "example", "example": ex["what"], "mesh": args.mesh, "precision": args.precision,
            "status": rc, "steps": steps, "t_end": t, "wall_s": wall, "ms_per_step": 1e3 * wall / steps,
            "cell_stage_updates_per_s": 3.0 * cells * steps / wall,

@@ -327,7 +327,7 @@ def _step(phi, h, width):
 
 
 def _prims_at(spec, states, weights):
-    """Blend primitive states (rho_1, rho_2, v_1, v_2, p) with weights."""
+    """Blend primitive states (rho_1, rho_2, v_1 .. v_d, p) with weights."""
     N, d = spec["nspec"], spec["dim"]
     rho = [sum(w * st[l] for st, w in zip(states, weights)) for l in range(N)]
     v = [sum(w * st[N + j] for st, w in zip(states, weights)) for j in range(d)]
@@ -358,49 +358,57 @@ def init_tripoint(spec, eps=1e-5, width=1.0):
     return assemble(spec, conserved(spec, rho, v, p), np.ones_like(x[0]), x)
 
 
-# Example 5.8 (air / helium, ideal gases) and Example 5.9 (stiffened gas and
-# ideal gas): domain [0, 445] x [-44.5, 44.5], reflecting walls at the top
-# and bottom, outflow on the left, inflow of the post-shock state on the
-# right; a bubble of radius 25 at (225, 0); the shock at x_1 = 275 moving left.
+# Examples 5.8 / 5.10 (air / helium, ideal gases) and 5.9 / 5.11 (stiffened
+# gas around an ideal-gas bubble), 2D or 3D: domain [0, 445] x [-44.5, 44.5]
+# (x [-44.5, 44.5] in 3D), reflecting walls on the lateral faces, outflow on
+# the left, inflow of the post-shock state on the right; a bubble of radius
+# 25 at (225, 0, 0); the shock at x_1 = 275 moving left.
 SB_CASES = {
     "he": dict(gamma=(1.4, 1.647), Rg=(0.287, 1.578), pinf=(0.0, 0.0), eps=0.03,
-               bubble=lambda e, R: (e, 1.225 * (R[0] / R[1]) - e, 0.0, 0.0, 101325.0),
-               pre=lambda e: (1.225 - e, e, 0.0, 0.0, 101325.0),
-               post=lambda e: (1.6861 - e, e, -113.5243, 0.0, 159060.0)),
+               bubble=lambda e, R: (e, 1.225 * (R[0] / R[1]) - e, 101325.0),
+               pre=lambda e: (1.225 - e, e, 101325.0),
+               post=lambda e: (1.6861 - e, e, -113.5243, 159060.0)),
     "stiff": dict(gamma=(3.0, 1.4), cv=(1.0, 1.0), pinf=(100.0, 0.0), eps=0.05,
-                  bubble=lambda e, R: (e, 5.0 - e, 0.0, 0.0, 100.0),
-                  pre=lambda e: (1.0 - e, e, 0.0, 0.0, 100.0),
-                  post=lambda e: (1.980198 - e, e, -121.2497, 0.0, 29800.0)),
+                  bubble=lambda e, R: (e, 5.0 - e, 100.0),
+                  pre=lambda e: (1.0 - e, e, 100.0),
+                  post=lambda e: (1.980198 - e, e, -121.2497, 29800.0)),
 }
 
 
-def spec_shock_bubble2d(case="he", n=(800, 160)):
+def spec_shock_bubble_walled(case="he", n=(800, 160)):
+    """Examples 5.8 / 5.9 (n of length 2) or 5.10 / 5.11 (length 3)."""
     c = SB_CASES[case]
+    d = len(n)
     if "Rg" in c:
         cv = tuple(R / (g - 1.0) for R, g in zip(c["Rg"], c["gamma"]))     # R_l = c_v,l (Gamma_l - 1)
     else:
         cv = c["cv"]
-    sp = make_spec(2, 2, n, box=(445.0, 89.0), gamma=c["gamma"], cv=cv, pinf=c["pinf"], chi=CHI_SHOCK,
-                   bc=[(BC_OUTFLOW, BC_INFLOW), (BC_REFLECT, BC_REFLECT)],
-                   wall=[(0.0, 445.0), (-44.5, 44.5)])
+    sp = make_spec(d, 2, n, box=(445.0,) + (89.0,) * (d - 1), gamma=c["gamma"], cv=cv, pinf=c["pinf"],
+                   chi=CHI_SHOCK, bc=[(BC_OUTFLOW, BC_INFLOW)] + [(BC_REFLECT, BC_REFLECT)] * (d - 1),
+                   wall=[(0.0, 445.0)] + [(-44.5, 44.5)] * (d - 1))
     post = c["post"](c["eps"])
-    Uin = conserved(sp, [np.array(post[0]), np.array(post[1])], [np.array(post[2]), np.array(post[3])],
-                    np.array(post[4])).reshape(-1)
+    v = [np.array(post[2])] + [np.array(0.0)] * (d - 1)
+    Uin = conserved(sp, [np.array(post[0]), np.array(post[1])], v, np.array(post[3])).reshape(-1)
     sp["inflow"] = {(0, 1): [float(u) for u in Uin]}
     sp["example"] = case
     return sp
 
 
-def init_shock_bubble2d(spec, width=1.0):
+def init_shock_bubble_walled(spec, width=1.0):
     c = SB_CASES[spec["example"]]
     e = c["eps"]
     R = c.get("Rg", (1.0, 1.0))
+    d = spec["dim"]
     x = _walled_mesh(spec)
-    h = min(spec["dxi"][:2])
-    fb = _step(25.0 - np.sqrt((x[0] - 225.0) ** 2 + x[1] ** 2), h, width)
+    h = min(spec["dxi"][:d])
+    r = np.sqrt((x[0] - 225.0) ** 2 + sum(x[k] ** 2 for k in range(1, d)))
+    fb = _step(25.0 - r, h, width)
     fs = _step(x[0] - 275.0, h, width)
-    rho, v, p = _prims_at(spec, [c["bubble"](e, R), c["pre"](e), c["post"](e)],
-                          [fb * (1 - fs), (1 - fb) * (1 - fs), fs])
+    z = np.zeros_like(x[0])
+    b, a, q = c["bubble"](e, R), c["pre"](e), c["post"](e)
+    states = [(b[0], b[1]) + (z,) * d + (b[2],), (a[0], a[1]) + (z,) * d + (a[2],),
+              (q[0], q[1], q[2] + z) + (z,) * (d - 1) + (q[3],)]
+    rho, v, p = _prims_at(spec, states, [fb * (1 - fs), (1 - fb) * (1 - fs), fs])
     return assemble(spec, conserved(spec, rho, v, p), np.ones_like(x[0]), x)
 
 

@@ -87,7 +87,7 @@ def test_face_conditions_checked_before_any_launch(lib):
     from paper_2202_07989_amd import es
     from paper_2202_07989_amd import inputs as I
     h = C.c_void_p()
-    sp = I.spec_shock_bubble2d("he", (16, 8))
+    sp = I.spec_shock_bubble_walled("he", (16, 8))
     for bad in ("half-periodic", "wall-order", "kind", "inflow-nan"):
         g = es.make_grid(sp)
         if bad == "half-periodic":

@@ -8,7 +8,8 @@ mixed path to 2e-5.  Cases: the shock-bubble of Example 5.8 (outflow /
 inflow along x, walls along y), the tri-point of Example 5.7 (walls
 everywhere), a one-species curvilinear case with walls on all faces, and a
 3D case mixing a wall pair, an outflow / inflow pair and a periodic
-direction.  At the examples' own sizes (800 x 160, 350 x 150) whole steps
+direction, and the 3D stiffened shock-bubble of Example 5.11 on a coarse
+grid.  At the examples' own sizes (800 x 160, 350 x 150) whole steps
 are compared at every node, and on the tri-point with walls everywhere the
 GPU conserves species mass and energy over many moving-mesh steps."""
 import numpy as np
@@ -40,8 +41,8 @@ R, O, IN = I.BC_REFLECT, I.BC_OUTFLOW, I.BC_INFLOW
 
 def bc_case(name):
     if name == "2d-shock-bubble":
-        sp = I.spec_shock_bubble2d("he", (61, 14))
-        JU, J, x = I.init_shock_bubble2d(sp)
+        sp = I.spec_shock_bubble_walled("he", (61, 14))
+        JU, J, x = I.init_shock_bubble_walled(sp)
         mon = I.monitor_spec(n_sweeps=5, n_smooth=3, sigma=(0,), alpha=(1000.0,))
         return sp, JU, J, x, mon
     if name == "2d-tripoint":
@@ -54,6 +55,10 @@ def bc_case(name):
         U, J0 = state(sp, 41)
         JU, J, x = I.assemble(sp, U, J0, inside_mesh(sp, 42))
         return sp, JU, J, x, I.monitor_spec(n_sweeps=6, n_smooth=2, sigma=(0, 3), alpha=(50.0, 20.0))
+    if name == "3d-shock-bubble":
+        sp = I.spec_shock_bubble_walled("stiff", (41, 9, 8))
+        JU, J, x = I.init_shock_bubble_walled(sp)
+        return sp, JU, J, x, I.monitor_spec(n_sweeps=5, n_smooth=3, sigma=(1, 3), alpha=(500.0, 500.0))
     if name == "3d-mixed":
         sp = walled(3, 2, (17, 14, 11), [(R, R), (O, IN), (0, 0)], chi=I.CHI_SHOCK, gamma=(1.4, 1.67),
                     cv=(1.0, 2.5), pinf=(0.0, 0.0))
@@ -66,7 +71,7 @@ def bc_case(name):
     raise KeyError(name)
 
 
-NAMES = ["2d-shock-bubble", "2d-tripoint", "2d-n1-walls", "3d-mixed"]
+NAMES = ["2d-shock-bubble", "2d-tripoint", "2d-n1-walls", "3d-mixed", "3d-shock-bubble"]
 
 
 def oracle_ghosts(o, JU, J, x):
@@ -128,7 +133,7 @@ def test_bc_rhs_parity(name, prec):
     hU, hJ = host(gU), host(gJ)
     Iin = I.interior(sp)
     sU, sJ = rhs_scale(JU, J, lam, Iin, sp)
-    tol = TOL_FP64 if prec == es.ES_FP64 else (TOL_MIXED_PHYS if name == "2d-shock-bubble" else TOL_MIXED)
+    tol = TOL_FP64 if prec == es.ES_FP64 else (TOL_MIXED_PHYS if "shock-bubble" in name else TOL_MIXED)
     worst = 0.0
     for c in range(o.nc):
         e = parity(hU[c][Iin[1:]], dU[c][Iin[1:]], sU[c])
@@ -158,7 +163,7 @@ def test_bc_mesh_redistribute_parity(name):
 
 
 @pytest.mark.parametrize("name,nsteps", [("2d-shock-bubble", 3), ("2d-tripoint", 3), ("2d-n1-walls", 3),
-                                         ("3d-mixed", 2)])
+                                         ("3d-mixed", 2), ("3d-shock-bubble", 2)])
 def test_bc_step_parity(name, nsteps):
     say(f"[bc steps] {name} steps={nsteps}")
     sp, JU, J, x, mon = bc_case(name)
@@ -192,8 +197,8 @@ def test_bc_examples_full_size_steps(example):
         JU, J, x = I.init_tripoint(sp)
         mon = I.monitor_spec(n_sweeps=5, n_smooth=3, sigma=(0,), alpha=(1200.0,))
     else:
-        sp = I.spec_shock_bubble2d(example.split("-")[-1])
-        JU, J, x = I.init_shock_bubble2d(sp)
+        sp = I.spec_shock_bubble_walled(example.split("-")[-1])
+        JU, J, x = I.init_shock_bubble_walled(sp)
         mon = I.monitor_spec(n_sweeps=5, n_smooth=3, sigma=(0,), alpha=(1000.0,))
     o = oracle.Oracle(sp)
     ctx = es.Context(sp)
