@@ -42,8 +42,9 @@ class Grid(C.Structure):
 
 class Monitor(C.Structure):
     _fields_ = [
-        ("nsig", C.c_int), ("sigma", C.c_int * 4), ("alpha", C.c_double * 4),
-        ("n_smooth", C.c_int), ("n_sweeps", C.c_int), ("form", C.c_int), ("beta", C.c_double * 4),
+        ("nsig", C.c_int), ("sigma", C.c_int * 6), ("alpha", C.c_double * 6),
+        ("n_smooth", C.c_int), ("n_sweeps", C.c_int), ("form", C.c_int), ("beta", C.c_double * 6),
+        ("psi", C.c_double * 2),
     ]
 
 
@@ -85,6 +86,7 @@ def lib():
             "orc_rk_stage": (C.c_int, [_G, C.c_int, C.c_double, _D, _D, _D, _D, _D, _D, _D, _D]),
             "orc_max_wavespeed": (C.c_int, [_G, _D, _D, _D, C.c_double, _D, _D]),
             "orc_monitor_fn": (C.c_int, [_G, C.POINTER(Monitor), _D, _D, _D]),
+            "orc_schlieren": (C.c_int, [_G, C.POINTER(Monitor), _D, _D, _D]),
             "orc_mesh_redistribute": (C.c_int, [_G, C.POINTER(Monitor), _D, _D, _D, _D, _D, _D]),
             "orc_total_entropy": (C.c_double, [_G, _D, _D]),
             "orc_entropy_rate": (C.c_double, [_G, _D, _D, _D, _D]),
@@ -153,6 +155,8 @@ def monitor(spec) -> Monitor:
     m.form = spec.get("form", 0)
     for t, b in enumerate(spec.get("beta", [])):
         m.beta[t] = b
+    for t, q in enumerate(spec.get("psi", [])):
+        m.psi[t] = q
     return m
 
 
@@ -291,6 +295,13 @@ class Oracle:
         th = np.zeros_like(J)
         rc = self.L.orc_monitor_fn(self.gp, C.byref(m), _p(JU), _p(J), _p(th))
         return rc, th
+
+    def schlieren(self, mon, JU, J):
+        m = monitor(mon)
+        phi = np.zeros_like(J)
+        rc = self.L.orc_schlieren(self.gp, C.byref(m), _p(JU), _p(J), _p(phi))
+        assert rc == 0, rc
+        return phi
 
     def mesh_redistribute(self, mon, JU, J, x):
         m = monitor(mon)

@@ -1075,18 +1075,77 @@ int orc_max_wavespeed(const orc_grid *g, const double *JU, const double *J,
 /*   x_k,i-e_k)/(2 dx_k) if dx_k < 0, (x_k,i+e_k - x_k,i)/(2 dx_k) if > 0.   */
 /* disp = Delta_tau (x^{[mu]} - x^n); resid[nu] = max |x^{[nu+1]}-x^{[nu]}|. */
 /* ------------------------------------------------------------------------ */
-static double sigma_at(const orc_grid *g, const double *JU, const double *J, long i, int sig)
+/* Monitor variables: 0 rho, 1 rho_1, 2 rho_2, 3 p, 4 |v| (the "u" of the   */
+/*   multi-variable monitor of Example 5.9, read as the speed), 5 the        */
+/*   schlieren function Phi = exp(-Psi |grad rho| / max |grad rho|) of eq    */
+/*   schlieren with Psi = (psi_1 rho_1 + psi_2 rho_2) / rho (psi_1 alone for */
+/*   one species), |grad rho| by the same central differences as the        */
+/*   monitor, its max over the interior; Phi = 1 where that max is 0.  Phi  */
+/*   is formed at the interior nodes and carried into the ghost layers like */
+/*   any plain field.                                                        */
+static double sigma_at(const orc_grid *g, const double *JU, const double *J, const double *phi,
+                       long i, int sig)
 {
     long P = orc_npoints(g);
     int nc = orc_ncomp(g);
     double U[MAXC];
+    if (sig == 5) return phi[i];
     for (int c = 0; c < nc; c++) U[c] = JU[c * P + i] / J[i];
     if (sig == 0) { double r = 0.0; for (int l = 0; l < g->nspec; l++) r += U[l]; return r; }
     if (sig == 1) return U[0];
     if (sig == 2) return g->nspec > 1 ? U[1] : U[0];
     prim_t q;
     prim_of(g, U, &q);
+    if (sig == 4) {
+        double v2 = 0.0;
+        for (int j = 0; j < g->dim; j++) v2 += q.v[j] * q.v[j];
+        return sqrt(v2);
+    }
     return q.p;
+}
+
+/* Phi at every interior node, ghost layers filled */
+static void schlieren(const orc_grid *g, const orc_monitor *mo, const double *JU, const double *J,
+                      double *phi);
+int orc_schlieren(const orc_grid *g, const orc_monitor *mo, const double *JU, const double *J,
+                  double *phi)
+{
+    if (!valid_grid(g) || !mo || !JU || !J || !phi) return ORC_EINVAL;
+    schlieren(g, mo, JU, J, phi);
+    return ORC_OK;
+}
+
+static void schlieren(const orc_grid *g, const orc_monitor *mo, const double *JU, const double *J,
+                      double *phi)
+{
+    long P = orc_npoints(g);
+    int d = g->dim;
+    double *gr = (double *)calloc((size_t)P, sizeof(double));
+    double gmax = 0.0;
+    for (int i2 = lo_(g, 2); i2 < hi_(g, 2); i2++)
+        for (int i1 = lo_(g, 1); i1 < hi_(g, 1); i1++)
+            for (int i0 = lo_(g, 0); i0 < hi_(g, 0); i0++) {
+                long i = at(g, i0, i1, i2);
+                double g2 = 0.0;
+                for (int k = 0; k < d; k++) {
+                    long st = stride_(g, k);
+                    double dk = (sigma_at(g, JU, J, NULL, i + st, 0) - sigma_at(g, JU, J, NULL, i - st, 0))
+                                / (2.0 * g->dxi[k]);
+                    g2 += dk * dk;
+                }
+                gr[i] = sqrt(g2);
+                if (gr[i] > gmax) gmax = gr[i];
+            }
+    for (int i2 = lo_(g, 2); i2 < hi_(g, 2); i2++)
+        for (int i1 = lo_(g, 1); i1 < hi_(g, 1); i1++)
+            for (int i0 = lo_(g, 0); i0 < hi_(g, 0); i0++) {
+                long i = at(g, i0, i1, i2);
+                double r1 = sigma_at(g, JU, J, NULL, i, 1), rho = sigma_at(g, JU, J, NULL, i, 0);
+                double psi = g->nspec > 1 ? (mo->psi[0] * r1 + mo->psi[1] * (rho - r1)) / rho : mo->psi[0];
+                phi[i] = gmax > 0.0 ? exp(-psi * gr[i] / gmax) : 1.0;
+            }
+    free(gr);
+    orc_fill_ghosts(g, phi, 1);
 }
 
 static void filter_pass(const orc_grid *g, const double *in, double *out)
@@ -1111,13 +1170,22 @@ static void filter_pass(const orc_grid *g, const double *in, double *out)
 int orc_monitor_fn(const orc_grid *g, const orc_monitor *mo, const double *JU,
                    const double *J, double *theta)
 {
-    if (!valid_grid(g) || !mo || mo->nsig < 1 || mo->nsig > 4) return ORC_EINVAL;
+    if (!valid_grid(g) || !mo || mo->nsig < 1 || mo->nsig > 6) return ORC_EINVAL;
     if (mo->form != 0 && (mo->form != 1 || mo->nsig > 2)) return ORC_EINVAL;
     long P = orc_npoints(g);
-    int d = g->dim;
+    int d = g->dim, use_phi = 0;
+    for (int s = 0; s < mo->nsig; s++) {
+        if (mo->sigma[s] < 0 || mo->sigma[s] > 5) return ORC_EINVAL;
+        if (mo->sigma[s] == 5) use_phi = 1;
+    }
+    double *phi = NULL;
+    if (use_phi) {
+        phi = (double *)calloc((size_t)P, sizeof(double));
+        schlieren(g, mo, JU, J, phi);
+    }
     double *grad = (double *)calloc((size_t)mo->nsig * P, sizeof(double));
     double *lap = (double *)calloc((size_t)mo->nsig * P, sizeof(double));
-    double gmax[4] = {0, 0, 0, 0}, lmax[4] = {0, 0, 0, 0};
+    double gmax[6] = {0, 0, 0, 0, 0, 0}, lmax[6] = {0, 0, 0, 0, 0, 0};
     for (int s = 0; s < mo->nsig; s++)
         for (int i2 = lo_(g, 2); i2 < hi_(g, 2); i2++)
             for (int i1 = lo_(g, 1); i1 < hi_(g, 1); i1++)
@@ -1126,18 +1194,18 @@ int orc_monitor_fn(const orc_grid *g, const orc_monitor *mo, const double *JU,
                     double g2 = 0.0;
                     for (int k = 0; k < d; k++) {
                         long st = stride_(g, k);
-                        double dsk = (sigma_at(g, JU, J, i + st, mo->sigma[s])
-                                      - sigma_at(g, JU, J, i - st, mo->sigma[s])) / (2.0 * g->dxi[k]);
+                        double dsk = (sigma_at(g, JU, J, phi, i + st, mo->sigma[s])
+                                      - sigma_at(g, JU, J, phi, i - st, mo->sigma[s])) / (2.0 * g->dxi[k]);
                         g2 += dsk * dsk;
                     }
                     grad[s * P + i] = sqrt(g2);
                     if (grad[s * P + i] > gmax[s]) gmax[s] = grad[s * P + i];
                     if (mo->form == 1) {
-                        double sc = sigma_at(g, JU, J, i, mo->sigma[s]), l = 0.0;
+                        double sc = sigma_at(g, JU, J, phi, i, mo->sigma[s]), l = 0.0;
                         for (int k = 0; k < d; k++) {
                             long st = stride_(g, k);
-                            l += (sigma_at(g, JU, J, i + st, mo->sigma[s]) - 2.0 * sc
-                                  + sigma_at(g, JU, J, i - st, mo->sigma[s])) / (g->dxi[k] * g->dxi[k]);
+                            l += (sigma_at(g, JU, J, phi, i + st, mo->sigma[s]) - 2.0 * sc
+                                  + sigma_at(g, JU, J, phi, i - st, mo->sigma[s])) / (g->dxi[k] * g->dxi[k]);
                         }
                         lap[s * P + i] = fabs(l);
                         if (lap[s * P + i] > lmax[s]) lmax[s] = lap[s * P + i];
@@ -1159,6 +1227,7 @@ int orc_monitor_fn(const orc_grid *g, const orc_monitor *mo, const double *JU,
             }
     free(grad);
     free(lap);
+    free(phi);
     orc_fill_ghosts(g, theta, 1);
     double *tmp = (double *)calloc(P, sizeof(double));
     for (int s = 0; s < mo->n_smooth; s++) {

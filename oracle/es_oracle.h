@@ -62,14 +62,16 @@ typedef struct {
 } orc_grid;
 
 typedef struct {
-    int nsig;          /* number of monitor variables kappa (1..4)             */
-    int sigma[4];      /* 0: rho, 1: rho_1, 2: rho_2, 3: p                     */
-    double alpha[4];   /* alpha_k                                              */
+    int nsig;          /* number of monitor variables kappa (1..6)             */
+    int sigma[6];      /* 0: rho, 1: rho_1, 2: rho_2, 3: p, 4: |v|, 5: the     */
+                       /*    schlieren function Phi (eq schlieren)             */
+    double alpha[6];   /* alpha_k                                              */
     int n_smooth;      /* low-pass filter passes                               */
     int n_sweeps;      /* Jacobi iterations mu                                 */
     int form;          /* 0: eq monitor; 1: the isentropic-vortex form with a  */
                        /*    Laplacian term (Section 5), at most two variables */
-    double beta[4];    /* Laplacian weights of form 1                          */
+    double beta[6];    /* Laplacian weights of form 1                          */
+    double psi[2];     /* Psi = (psi_1 rho_1 + psi_2 rho_2) / rho of Phi       */
 } orc_monitor;
 
 /* ---- pointwise pieces (exposed for the pins) ---------------------------- */
@@ -126,6 +128,10 @@ int    orc_max_wavespeed(const orc_grid *g, const double *JU, const double *J,
                          const double *jxi_x, double cfl, double *lambda,
                          double *dt);
 /* monitor Theta after the n_smooth filter passes (the Theta the Jacobi sweeps use) */
+/* the schlieren function Phi (monitor variable 5) at the interior nodes,
+ * ghost layers filled */
+int    orc_schlieren(const orc_grid *g, const orc_monitor *mo, const double *JU,
+                     const double *J, double *phi);
 int    orc_monitor_fn(const orc_grid *g, const orc_monitor *m, const double *JU,
                       const double *J, double *theta);
 int    orc_mesh_redistribute(const orc_grid *g, const orc_monitor *m,
