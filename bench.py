@@ -531,7 +531,9 @@ EXAMPLES = {
     "shock-bubble-he": dict(t_end=0.676, alpha=1000.0, paper_s={"moving": 3840.0, "uniform": 552.0},
                             case="he", n=(800, 160),
                             what="Example 5.8 shock / helium bubble, 800 x 160, t = 0.676"),
-    "shock-bubble-stiff": dict(t_end=0.8, alpha=1200.0, paper_s={"moving": 568.0, "uniform": 107.0},
+    # Example 5.9's own monitor: schlieren function, speed, partial
+    # densities and pressure
+    "shock-bubble-stiff": dict(t_end=0.8, monitor="m7", paper_s={"moving": 568.0, "uniform": 107.0},
                                case="stiff", n=(800, 160),
                                what="Example 5.9 shock / bubble in stiffened gas, 800 x 160, t = 0.8"),
     # 10 filter passes here too: with 3 the mesh gathers around the light
@@ -572,8 +574,12 @@ def example_run(args):
         prec = es.ES_MIXED
     else:
         prec = es.ES_FP64
-    alpha = ex["alpha"] if isinstance(ex["alpha"], tuple) else (ex["alpha"],)
-    mon = I.monitor_spec(n_sweeps=10, n_smooth=ex.get("n_smooth", 3), sigma=ex.get("sigma", (0,)), alpha=alpha)
+    if ex.get("monitor") == "m7":
+        mon = I.monitor_m7(n_sweeps=10, n_smooth=ex.get("n_smooth", 3))
+    else:
+        alpha = ex["alpha"] if isinstance(ex["alpha"], tuple) else (ex["alpha"],)
+        mon = I.monitor_spec(n_sweeps=10, n_smooth=ex.get("n_smooth", 3), sigma=ex.get("sigma", (0,)),
+                             alpha=alpha)
     cfl = 0.4 if sp["dim"] == 2 else 0.3
     move = args.mesh == "moving"
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()

@@ -103,14 +103,24 @@ typedef struct {
 } es_grid;
 
 typedef struct {
-    int nsig;          /* number of monitor variables kappa, 1..4               */
-    int sigma[4];      /* 0: rho, 1: rho_1, 2: rho_2, 3: p                      */
-    double alpha[4];   /* alpha_k >= 0                                          */
+    int nsig;          /* number of monitor variables kappa, 1..6               */
+    int sigma[6];      /* 0: rho, 1: rho_1, 2: rho_2, 3: p, 4: the speed |v|,   */
+                       /* 5: the schlieren function Phi (below)                 */
+    double alpha[6];   /* alpha_k >= 0                                          */
     int n_smooth;      /* low-pass filter passes                                */
     int n_sweeps;      /* Jacobi iterations mu (1..4096)                        */
     int form;          /* ES_MONITOR_GRAD2 or ES_MONITOR_GRAD_LAP (below)       */
-    double beta[4];    /* Laplacian weights of ES_MONITOR_GRAD_LAP, >= 0        */
+    double beta[6];    /* Laplacian weights of ES_MONITOR_GRAD_LAP, >= 0        */
+    double psi[2];     /* weights of Phi's Psi (finite)                         */
 } es_monitor;
+
+/* The monitor of Example 5.9 combines (Phi, u, rho_1, rho_2, p); u is taken
+ * as the speed |v|.  Phi is the schlieren function of eq schlieren, Phi =
+ * exp(-Psi |grad rho| / max |grad rho|), Psi = (psi[0] rho_1 + psi[1]
+ * rho_2) / rho (psi[0] for one species), |grad rho| by the monitor's
+ * central differences in xi, its maximum over the interior nodes (Phi = 1
+ * where that maximum is 0); Phi is formed at the interior nodes and carried
+ * into the ghost layers like a plain field. */
 
 /* monitor forms: ES_MONITOR_GRAD2 is eq monitor, Theta = (1 + sum_k alpha_k
  * (|grad sigma_k| / max|grad sigma_k|)^2)^(1/2); ES_MONITOR_GRAD_LAP is the

@@ -158,19 +158,20 @@ int ensure_mesh_ws(es_ctx* c, int nsig)
 {
     const size_t P = c->geo.P, d = c->geo.dim;
     if (c->mesh_ready && nsig <= c->mesh_nsig) return ES_OK;
-    int rc = dalloc(&c->mesh.grad, 4 * P);
+    int rc = dalloc(&c->mesh.grad, MON_CH * P);
     if (!rc) rc = dalloc(&c->mesh.th0, P);
     if (!rc) rc = dalloc(&c->mesh.th1, P);
     if (!rc) rc = dalloc(&c->mesh.xa, d * P);
     if (!rc) rc = dalloc(&c->mesh.xb, d * P);
-    if (!rc) rc = dalloc(&c->mesh.part, 4 * 2048);
+    if (!rc) rc = dalloc(&c->mesh.phi, P);
+    if (!rc) rc = dalloc(&c->mesh.part, 8 * 2048);
     if (!rc) rc = dalloc(&c->mesh.scal, 8);
     if (rc) return rc;
     // theta ghosts are read by the filter before the first fill
     if (fill_value(c->mesh.th0, P, 1.0, 0) != hipSuccess) return ES_EHIP;
     if (fill_value(c->mesh.th1, P, 1.0, 0) != hipSuccess) return ES_EHIP;
     c->mesh_ready = true;
-    c->mesh_nsig = 4;
+    c->mesh_nsig = MON_CH;
     return hipDeviceSynchronize() == hipSuccess ? ES_OK : ES_EHIP;
 }
 
@@ -198,18 +199,22 @@ MonitorP monitor_params(const es_monitor* m)
     mo.n_sweeps = m->n_sweeps;
     mo.form = m->form;
     for (int s = 0; s < m->nsig; s++) mo.beta[s] = m->form == ES_MONITOR_GRAD_LAP ? m->beta[s] : 0.0;
+    mo.psi[0] = m->psi[0];
+    mo.psi[1] = m->psi[1];
+    mo.phi = nullptr;
     return mo;
 }
 
 int check_monitor(const es_monitor* m)
 {
-    if (!m || m->nsig < 1 || m->nsig > 4 || m->n_smooth < 0 || m->n_sweeps < 0 || m->n_sweeps > 4096)
+    if (!m || m->nsig < 1 || m->nsig > MON_CH || m->n_smooth < 0 || m->n_sweeps < 0 || m->n_sweeps > 4096)
         return ES_EINVAL;
     for (int s = 0; s < m->nsig; s++)
-        if (m->sigma[s] < 0 || m->sigma[s] > 3 || !(m->alpha[s] >= 0.0)) return ES_EINVAL;
+        if (m->sigma[s] < 0 || m->sigma[s] > 5 || !(m->alpha[s] >= 0.0)) return ES_EINVAL;
+    if (!std::isfinite(m->psi[0]) || !std::isfinite(m->psi[1])) return ES_EINVAL;
     if (m->form != ES_MONITOR_GRAD2 && m->form != ES_MONITOR_GRAD_LAP) return ES_EINVAL;
     if (m->form == ES_MONITOR_GRAD_LAP) {
-        if (m->nsig > 2) return ES_EINVAL;   // gradient and Laplacian maxima share four channels
+        if (m->nsig > 2) return ES_EINVAL;   // gradient and Laplacian maxima share the channels
         for (int s = 0; s < m->nsig; s++)
             if (!(m->beta[s] >= 0.0)) return ES_EINVAL;
     }
@@ -250,7 +255,7 @@ int es_destroy(es_ctx* c)
 {
     if (!c) return ES_EINVAL;
     void* bufs[] = {c->status, c->scal, c->part, c->G, c->mesh.grad, c->mesh.th0, c->mesh.th1,
-                    c->mesh.xa, c->mesh.xb, c->mesh.part, c->mesh.scal, c->bufA,
+                    c->mesh.xa, c->mesh.xb, c->mesh.phi, c->mesh.part, c->mesh.scal, c->bufA,
                     c->bufB, c->jxx, c->jxt, c->disp};
     for (void* p : bufs)
         if (p) (void)hipFree(p);

@@ -832,12 +832,26 @@ hipError_t entropy_sum(const Phys& ph, const Geo& g, const double* JU, const dou
 // |grad_xi sigma| by second-order central differences, for each monitor
 // variable; per-block maxima into part[s * RED_BLOCKS + block].  The form
 // with a Laplacian term also writes |lap_xi sigma| (second-order central
-// differences) as channel nsig + s.
+// differences) as channel nsig + s.  Variables: 0 rho, 1 rho_1, 2 rho_2,
+// 3 p, 4 the speed |v| (the u of Example 5.9's monitor), 5 the schlieren
+// function of eq schlieren, read from its array (with ghost layers).
 template <int N, int D>
 __device__ __forceinline__ double sigma_of(const Phys& ph, const double* JU, const double* Jv, long P,
-                                           long i, int sig)
+                                           long i, int sig, const double* phi)
 {
+    if (sig == 5) return phi[i];
     const double Jq = Jv[i];
+    if (sig == 4) {
+        double r = 0.0, m2 = 0.0;
+#pragma unroll
+        for (int l = 0; l < N; l++) r += JU[l * P + i] / Jq;
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            const double vj = (JU[(N + j) * P + i] / Jq) / r;
+            m2 += vj * vj;
+        }
+        return sqrt(m2);
+    }
     if (sig == 0) {
         double r = 0.0;
 #pragma unroll
@@ -858,18 +872,18 @@ __global__ void k_monitor_grad(Phys ph, Geo g, MonitorP mo, const double* __rest
 {
     const long P = g.P;
     const long nint = n_interior(g);
-    double gm[4] = {0.0, 0.0, 0.0, 0.0};
+    double gm[MON_CH] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
         int i0, i1, i2;
         const long i = interior_node(g, q, i0, i1, i2);
         for (int s = 0; s < mo.nsig; s++) {
             double g2 = 0.0, lap = 0.0;
-            const double sc = mo.form ? sigma_of<N, D>(ph, JU, Jv, P, i, mo.sigma[s]) : 0.0;
+            const double sc = mo.form ? sigma_of<N, D>(ph, JU, Jv, P, i, mo.sigma[s], mo.phi) : 0.0;
 #pragma unroll
             for (int k = 0; k < D; k++) {
                 const long st = dir_stride(g, k);
-                const double sp = sigma_of<N, D>(ph, JU, Jv, P, i + st, mo.sigma[s]);
-                const double sm = sigma_of<N, D>(ph, JU, Jv, P, i - st, mo.sigma[s]);
+                const double sp = sigma_of<N, D>(ph, JU, Jv, P, i + st, mo.sigma[s], mo.phi);
+                const double sm = sigma_of<N, D>(ph, JU, Jv, P, i - st, mo.sigma[s], mo.phi);
                 const double dk = (sp - sm) / (2.0 * g.dxi[k]);
                 g2 += dk * dk;
                 lap += (sp - 2.0 * sc + sm) / (g.dxi[k] * g.dxi[k]);
@@ -884,9 +898,10 @@ __global__ void k_monitor_grad(Phys ph, Geo g, MonitorP mo, const double* __rest
         }
     }
     const int nch = mo.form ? 2 * mo.nsig : mo.nsig;
-    for (int s = 0; s < 4; s++) {
+    for (int s = 0; s < MON_CH; s++) {
+        if (s >= nch) break;   // uniform across the block
         const double r = block_reduce<RED_MAX>(gm[s]);
-        if (threadIdx.x == 0 && s < nch) part[s * RED_BLOCKS + blockIdx.x] = r;
+        if (threadIdx.x == 0) part[s * RED_BLOCKS + blockIdx.x] = r;
     }
 }
 
@@ -911,19 +926,19 @@ k_monitor_grad3(Phys ph, Geo g, MonitorP mo, const double* __restrict__ JU, cons
     double ih[3];
 #pragma unroll
     for (int k = 0; k < 3; k++) ih[k] = 1.0 / (2.0 * g.dxi[k]);
-    double gm[4] = {0.0, 0.0, 0.0, 0.0};
+    double gm[MON_CH] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (in && zc0 < zc1) {
         for (int s = 0; s < mo.nsig; s++) {
             const int sg = mo.sigma[s];
             long i = ((long)zc0 * np1 + y) * np0 + x;
-            double sm = sigma_of<N, D>(ph, JU, Jv, P, i - sz, sg);
-            double s0 = sigma_of<N, D>(ph, JU, Jv, P, i, sg);
+            double sm = sigma_of<N, D>(ph, JU, Jv, P, i - sz, sg, mo.phi);
+            double s0 = sigma_of<N, D>(ph, JU, Jv, P, i, sg, mo.phi);
             for (int z = zc0; z < zc1; z++, i += sz) {
-                const double sp = sigma_of<N, D>(ph, JU, Jv, P, i + sz, sg);
-                const double xp = sigma_of<N, D>(ph, JU, Jv, P, i + 1, sg);
-                const double xm = sigma_of<N, D>(ph, JU, Jv, P, i - 1, sg);
-                const double yp = sigma_of<N, D>(ph, JU, Jv, P, i + sy, sg);
-                const double ym = sigma_of<N, D>(ph, JU, Jv, P, i - sy, sg);
+                const double sp = sigma_of<N, D>(ph, JU, Jv, P, i + sz, sg, mo.phi);
+                const double xp = sigma_of<N, D>(ph, JU, Jv, P, i + 1, sg, mo.phi);
+                const double xm = sigma_of<N, D>(ph, JU, Jv, P, i - 1, sg, mo.phi);
+                const double yp = sigma_of<N, D>(ph, JU, Jv, P, i + sy, sg, mo.phi);
+                const double ym = sigma_of<N, D>(ph, JU, Jv, P, i - sy, sg, mo.phi);
                 const double d0 = (xp - xm) * ih[0];
                 const double d1 = (yp - ym) * ih[1];
                 const double d2 = (sp - sm) * ih[2];
@@ -944,9 +959,10 @@ k_monitor_grad3(Phys ph, Geo g, MonitorP mo, const double* __restrict__ JU, cons
     }
     const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     const int nch = mo.form ? 2 * mo.nsig : mo.nsig;
-    for (int s = 0; s < 4; s++) {
+    for (int s = 0; s < MON_CH; s++) {
+        if (s >= nch) break;   // uniform across the block
         const double r = block_reduce<RED_MAX>(gm[s]);
-        if (threadIdx.x == 0 && s < nch) part[s * RED_BLOCKS + blk] = r;
+        if (threadIdx.x == 0) part[s * RED_BLOCKS + blk] = r;
     }
 }
 
@@ -977,6 +993,67 @@ k_filter3(Geo g, const double* __restrict__ in, double* __restrict__ out, int zc
         qm = q0;
         q0 = qp;
     }
+}
+
+// the schlieren function of eq schlieren, Phi = exp(-Psi |grad rho| /
+// max |grad rho|), Psi = (psi_1 rho_1 + psi_2 rho_2) / rho: first
+// |grad_xi rho| (the monitor's central differences) with per-block maxima,
+// then Phi from the global maximum (1 where it is 0)
+template <int N, int D>
+__global__ void k_rho_grad(Phys ph, Geo g, const double* __restrict__ JU, const double* __restrict__ Jv,
+                           double* __restrict__ gr, double* __restrict__ part)
+{
+    const long P = g.P;
+    const long nint = n_interior(g);
+    double gm = 0.0;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+        double g2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            const long st = dir_stride(g, k);
+            const double sp = sigma_of<N, D>(ph, JU, Jv, P, i + st, 0, nullptr);
+            const double sm = sigma_of<N, D>(ph, JU, Jv, P, i - st, 0, nullptr);
+            const double dk = (sp - sm) / (2.0 * g.dxi[k]);
+            g2 += dk * dk;
+        }
+        gr[i] = sqrt(g2);
+        gm = fmax(gm, gr[i]);
+    }
+    const double r = block_reduce<RED_MAX>(gm);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+template <int N, int D>
+__global__ void k_schlieren(Phys ph, Geo g, MonitorP mo, const double* __restrict__ JU,
+                            const double* __restrict__ Jv, const double* __restrict__ gr,
+                            const double* __restrict__ gmax, double* __restrict__ phi)
+{
+    const long P = g.P;
+    const long nint = n_interior(g);
+    const double G = *gmax;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        const long i = interior_node(g, q, i0, i1, i2);
+        double psi = mo.psi[0];
+        if (N == 2) {
+            const double r1 = sigma_of<N, D>(ph, JU, Jv, P, i, 1, nullptr);
+            const double r = sigma_of<N, D>(ph, JU, Jv, P, i, 0, nullptr);
+            psi = (mo.psi[0] * r1 + mo.psi[1] * (r - r1)) / r;
+        }
+        phi[i] = G > 0.0 ? exp(-psi * gr[i] / G) : 1.0;
+    }
+}
+
+template <int N, int D>
+static void launch_schlieren(const Phys& ph, const Geo& g, const MonitorP& mo, const double* JU,
+                             const double* J, double* gr, double* part, double* gmax, double* phi, int nb,
+                             int gi, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_rho_grad<N, D>), dim3(nb), dim3(256), 0, s, ph, g, JU, J, gr, part);
+    hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, part, nb, gmax, 0, 0.0, nullptr);
+    hipLaunchKernelGGL((k_schlieren<N, D>), dim3(gi), dim3(256), 0, s, ph, g, mo, JU, J, gr, gmax, phi);
 }
 
 __global__ void k_theta(Geo g, MonitorP mo, const double* __restrict__ grad, const double* __restrict__ gmax,
@@ -1171,10 +1248,12 @@ static void launch_monitor(const Phys& ph, const Geo& g, const MonitorP& mo, con
     hipLaunchKernelGGL((k_monitor_grad<N, D>), dim3(nb), dim3(256), 0, s, ph, g, mo, JU, J, grad, part);
 }
 
-hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, const double* JU,
+hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo_in, const double* JU,
                              const double* J, const double* xn, double* disp, MeshWork& w,
                              double* dtau_out, double* resid_out, unsigned* status, hipStream_t s)
 {
+    MonitorP mo = mo_in;
+    mo.phi = w.phi;
     const long P = g.P;
     const long nint = (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1);
     const int nb = red_grid(nint);
@@ -1187,6 +1266,16 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, c
     const dim3 jgrid(jx, jy, (g.n[2] + jchunk - 1) / jchunk);
     const int jblocks = jx * jy * (int)jgrid.z;
     const bool march = g.dim == 3 && jblocks <= RED_BLOCKS;
+    // the schlieren function first when the monitor uses it (th1 holds
+    // |grad rho| until the filter overwrites it)
+    bool use_phi = false;
+    for (int q = 0; q < mo.nsig; q++) use_phi = use_phi || mo.sigma[q] == 5;
+    if (use_phi) {
+        ES_DISPATCH_ND(ph, g, launch_schlieren, ph, g, mo, JU, J, w.th1, w.part + 6 * RED_BLOCKS, w.scal + 7,
+                       w.phi, nb, gi, s);
+        const hipError_t e0 = fill_ghosts(g, w.phi, 1, GH_PLAIN, s);
+        if (e0 != hipSuccess) return e0;
+    }
     // monitor and its global maxima
     if (march && ph.nspec == 1)
         hipLaunchKernelGGL(k_monitor_grad3<1>, jgrid, dim3(256), 0, s, ph, g, mo, JU, J, w.grad, w.part, jchunk);
@@ -1233,11 +1322,11 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, c
         hipLaunchKernelGGL(k_limiter<2>, dim3(nb), dim3(256), 0, s, g, xcur, xn, w.part);
     else
         hipLaunchKernelGGL(k_limiter<3>, dim3(nb), dim3(256), 0, s, g, xcur, xn, w.part);
-    hipLaunchKernelGGL(k_finish<RED_MIN>, dim3(1), dim3(256), 0, s, w.part, nb, w.scal + 4, 2, 0.0, status);
+    hipLaunchKernelGGL(k_finish<RED_MIN>, dim3(1), dim3(256), 0, s, w.part, nb, w.scal + 6, 2, 0.0, status);
     if ((e = fill_value(disp, g.dim * P, 0.0, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_disp, dim3(gi), dim3(256), 0, s, g, xcur, xn, w.scal + 4, disp);
+    hipLaunchKernelGGL(k_disp, dim3(gi), dim3(256), 0, s, g, xcur, xn, w.scal + 6, disp);
     if ((e = fill_ghosts(g, disp, g.dim, GH_DISP, s)) != hipSuccess) return e;
-    if (dtau_out && (e = copy(w.scal + 4, dtau_out, 1, s)) != hipSuccess) return e;
+    if (dtau_out && (e = copy(w.scal + 6, dtau_out, 1, s)) != hipSuccess) return e;
     return hipGetLastError();
 }
 

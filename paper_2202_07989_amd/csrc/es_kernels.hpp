@@ -10,23 +10,28 @@
 
 namespace es {
 
+constexpr int MON_CH = 6;   // monitor channels (variables, or gradient + Laplacian pairs)
+
 struct MonitorP {
     int nsig;
-    int sigma[4];
-    double alpha[4];
+    int sigma[MON_CH];     // 0 rho, 1 rho_1, 2 rho_2, 3 p, 4 |v|, 5 the schlieren function
+    double alpha[MON_CH];
     int n_smooth, n_sweeps;
     int form;          // 0: eq monitor; 1: gradient + Laplacian (channels nsig..2 nsig - 1)
-    double beta[4];
+    double beta[MON_CH];
+    double psi[2];     // Psi = (psi_1 rho_1 + psi_2 rho_2) / rho of the schlieren function
+    const double* phi; // the schlieren function with ghost layers (when a variable is 5)
 };
 
 struct MeshWork {
-    double* grad;   // nsig * P
+    double* grad;   // MON_CH * P
     double* th0;    // P
     double* th1;    // P
     double* xa;     // dim * P
     double* xb;     // dim * P
-    double* part;   // 4 * 2048 partials
-    double* scal;   // 8 scalars: monitor maxima [0..3], Delta_tau [4]
+    double* phi;    // P: the schlieren function
+    double* part;   // 8 * 2048 partials
+    double* scal;   // 8 scalars: monitor maxima [0..5], Delta_tau [6], max |grad rho| [7]
 };
 
 struct RkArgs;

@@ -43,8 +43,9 @@ class EsGrid(C.Structure):
 
 class EsMonitor(C.Structure):
     _fields_ = [
-        ("nsig", C.c_int), ("sigma", C.c_int * 4), ("alpha", C.c_double * 4),
-        ("n_smooth", C.c_int), ("n_sweeps", C.c_int), ("form", C.c_int), ("beta", C.c_double * 4),
+        ("nsig", C.c_int), ("sigma", C.c_int * 6), ("alpha", C.c_double * 6),
+        ("n_smooth", C.c_int), ("n_sweeps", C.c_int), ("form", C.c_int), ("beta", C.c_double * 6),
+        ("psi", C.c_double * 2),
     ]
 
 
@@ -153,6 +154,8 @@ def make_monitor(mon) -> EsMonitor:
     m.form = mon.get("form", ES_MONITOR_GRAD2)
     for t, b in enumerate(mon.get("beta", [])):
         m.beta[t] = b
+    for t, q in enumerate(mon.get("psi", [])):
+        m.psi[t] = q
     return m
 
 

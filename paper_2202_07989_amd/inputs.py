@@ -71,6 +71,18 @@ def monitor_spec(n_sweeps=10, n_smooth=3, sigma=(0,), alpha=(1200.0,)):
     return dict(sigma=list(sigma), alpha=list(alpha), n_smooth=n_smooth, n_sweeps=n_sweeps)
 
 
+MON_RHO, MON_RHO1, MON_RHO2, MON_P, MON_SPEED, MON_SCHLIEREN = 0, 1, 2, 3, 4, 5
+
+
+def monitor_m7(n_sweeps=10, n_smooth=3):
+    """Example 5.9's monitor: (Phi, u, rho_1, rho_2, p) with alpha (600, 500,
+    1200, 1200, 1200) and the schlieren weights Psi = (120 rho_1 + 20 rho_2)
+    / rho."""
+    return dict(sigma=[MON_SCHLIEREN, MON_SPEED, MON_RHO1, MON_RHO2, MON_P],
+                alpha=[600.0, 500.0, 1200.0, 1200.0, 1200.0], psi=[120.0, 20.0],
+                n_smooth=n_smooth, n_sweeps=n_sweeps)
+
+
 # --------------------------------------------------------------------------
 # layout helpers
 # --------------------------------------------------------------------------

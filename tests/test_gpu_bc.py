@@ -59,6 +59,10 @@ def bc_case(name):
         sp = I.spec_shock_bubble_walled("stiff", (41, 9, 8))
         JU, J, x = I.init_shock_bubble_walled(sp)
         return sp, JU, J, x, I.monitor_spec(n_sweeps=5, n_smooth=3, sigma=(1, 3), alpha=(500.0, 500.0))
+    if name == "2d-stiff-m7":
+        sp = I.spec_shock_bubble_walled("stiff", (63, 15))
+        JU, J, x = I.init_shock_bubble_walled(sp)
+        return sp, JU, J, x, I.monitor_m7()
     if name == "3d-mixed":
         sp = walled(3, 2, (17, 14, 11), [(R, R), (O, IN), (0, 0)], chi=I.CHI_SHOCK, gamma=(1.4, 1.67),
                     cv=(1.0, 2.5), pinf=(0.0, 0.0))
@@ -144,7 +148,7 @@ def test_bc_rhs_parity(name, prec):
     say(f"    worst component parity {worst:.2e}")
 
 
-@pytest.mark.parametrize("name", NAMES)
+@pytest.mark.parametrize("name", NAMES + ["2d-stiff-m7"])
 def test_bc_mesh_redistribute_parity(name):
     say(f"[bc mesh] {name}")
     sp, JU, J, x, mon = bc_case(name)
@@ -163,7 +167,7 @@ def test_bc_mesh_redistribute_parity(name):
 
 
 @pytest.mark.parametrize("name,nsteps", [("2d-shock-bubble", 3), ("2d-tripoint", 3), ("2d-n1-walls", 3),
-                                         ("3d-mixed", 2), ("3d-shock-bubble", 2)])
+                                         ("3d-mixed", 2), ("3d-shock-bubble", 2), ("2d-stiff-m7", 3)])
 def test_bc_step_parity(name, nsteps):
     say(f"[bc steps] {name} steps={nsteps}")
     sp, JU, J, x, mon = bc_case(name)

@@ -113,7 +113,17 @@ def test_wavespeed_parity(name):
                                       ("2d-n2-bubble", dict(sigma=[0], alpha=[20.0], beta=[10.0], form=1,
                                                             n_smooth=3, n_sweeps=10)),
                                       ("3d-n2-random", dict(sigma=[1, 3], alpha=[20.0, 5.0], beta=[10.0, 2.0],
-                                                            form=1, n_smooth=2, n_sweeps=6))])
+                                                            form=1, n_smooth=2, n_sweeps=6)),
+                                      # the five-variable monitor of Example 5.9: schlieren function,
+                                      # speed, partial densities, pressure
+                                      ("2d-n2-bubble", dict(sigma=[5, 4, 1, 2, 3],
+                                                            alpha=[600.0, 500.0, 1200.0, 1200.0, 1200.0],
+                                                            psi=[120.0, 20.0], n_smooth=3, n_sweeps=10)),
+                                      ("3d-n2-random", dict(sigma=[5, 4, 0, 3, 1, 2],
+                                                            alpha=[300.0, 200.0, 50.0, 50.0, 20.0, 20.0],
+                                                            psi=[20.0, 5.0], n_smooth=2, n_sweeps=5)),
+                                      ("2d-n1", dict(sigma=[4, 5], alpha=[100.0, 100.0], psi=[30.0],
+                                                     n_smooth=1, n_sweeps=4))])
 def test_mesh_redistribute_parity(name, mon):
     say(f"[mesh parity] {name} {mon}")
     sp, o, JU, J, x, disp, jx, jt = prepared(name)
