@@ -157,6 +157,9 @@ hipError_t fill_state(const Geo& g, const InflowStates& in, double* JU, double* 
 {
     hipError_t e = fill_ghosts(g, J, 1, GH_PLAIN, s);
     if (e != hipSuccess) return e;
+    bool periodic = true;
+    for (int k = 0; k < g.dim; k++) periodic = periodic && g.bc[k][0] == BC_PERIODIC;
+    if (periodic) return fill_ghosts(g, JU, nc, GH_PLAIN, s);   // plain wrapped copies
     long nzs, nys, nxs;
     shell_sizes(g, nzs, nys, nxs);
     const long total = nzs + nys + nxs;
@@ -835,13 +838,13 @@ hipError_t entropy_sum(const Phys& ph, const Geo& g, const double* JU, const dou
 // differences) as channel nsig + s.  Variables: 0 rho, 1 rho_1, 2 rho_2,
 // 3 p, 4 the speed |v| (the u of Example 5.9's monitor), 5 the schlieren
 // function of eq schlieren, read from its array (with ghost layers).
-template <int N, int D>
+template <int N, int D, bool EXT = true>
 __device__ __forceinline__ double sigma_of(const Phys& ph, const double* JU, const double* Jv, long P,
                                            long i, int sig, const double* phi)
 {
-    if (sig == 5) return phi[i];
+    if (EXT && sig == 5) return phi[i];
     const double Jq = Jv[i];
-    if (sig == 4) {
+    if (EXT && sig == 4) {
         double r = 0.0, m2 = 0.0;
 #pragma unroll
         for (int l = 0; l < N; l++) r += JU[l * P + i] / Jq;
@@ -865,7 +868,9 @@ __device__ __forceinline__ double sigma_of(const Phys& ph, const double* JU, con
     return s.p;
 }
 
-template <int N, int D>
+// EXT: the monitor uses the speed or the schlieren function (without them
+// the kernels need fewer registers)
+template <int N, int D, bool EXT>
 __global__ void k_monitor_grad(Phys ph, Geo g, MonitorP mo, const double* __restrict__ JU,
                                const double* __restrict__ Jv, double* __restrict__ grad,
                                double* __restrict__ part)
@@ -878,12 +883,12 @@ __global__ void k_monitor_grad(Phys ph, Geo g, MonitorP mo, const double* __rest
         const long i = interior_node(g, q, i0, i1, i2);
         for (int s = 0; s < mo.nsig; s++) {
             double g2 = 0.0, lap = 0.0;
-            const double sc = mo.form ? sigma_of<N, D>(ph, JU, Jv, P, i, mo.sigma[s], mo.phi) : 0.0;
+            const double sc = mo.form ? sigma_of<N, D, EXT>(ph, JU, Jv, P, i, mo.sigma[s], mo.phi) : 0.0;
 #pragma unroll
             for (int k = 0; k < D; k++) {
                 const long st = dir_stride(g, k);
-                const double sp = sigma_of<N, D>(ph, JU, Jv, P, i + st, mo.sigma[s], mo.phi);
-                const double sm = sigma_of<N, D>(ph, JU, Jv, P, i - st, mo.sigma[s], mo.phi);
+                const double sp = sigma_of<N, D, EXT>(ph, JU, Jv, P, i + st, mo.sigma[s], mo.phi);
+                const double sm = sigma_of<N, D, EXT>(ph, JU, Jv, P, i - st, mo.sigma[s], mo.phi);
                 const double dk = (sp - sm) / (2.0 * g.dxi[k]);
                 g2 += dk * dk;
                 lap += (sp - 2.0 * sc + sm) / (g.dxi[k] * g.dxi[k]);
@@ -910,7 +915,7 @@ __global__ void k_monitor_grad(Phys ph, Geo g, MonitorP mo, const double* __rest
 // planes; sigma at z-1, z, z+1 of the own column comes from a 3-plane ring,
 // the four in-plane neighbours are evaluated from the state directly.
 // Per-block maxima go to part[s * RED_BLOCKS + block] in block order.
-template <int N>
+template <int N, bool EXT>
 __global__ void __launch_bounds__(256)
 k_monitor_grad3(Phys ph, Geo g, MonitorP mo, const double* __restrict__ JU, const double* __restrict__ Jv,
                 double* __restrict__ grad, double* __restrict__ part, int zchunk)
@@ -931,38 +936,44 @@ k_monitor_grad3(Phys ph, Geo g, MonitorP mo, const double* __restrict__ JU, cons
         for (int s = 0; s < mo.nsig; s++) {
             const int sg = mo.sigma[s];
             long i = ((long)zc0 * np1 + y) * np0 + x;
-            double sm = sigma_of<N, D>(ph, JU, Jv, P, i - sz, sg, mo.phi);
-            double s0 = sigma_of<N, D>(ph, JU, Jv, P, i, sg, mo.phi);
+            double sm = sigma_of<N, D, EXT>(ph, JU, Jv, P, i - sz, sg, mo.phi);
+            double s0 = sigma_of<N, D, EXT>(ph, JU, Jv, P, i, sg, mo.phi);
+            double mg = 0.0, ml = 0.0;     // this channel's maxima over the column
             for (int z = zc0; z < zc1; z++, i += sz) {
-                const double sp = sigma_of<N, D>(ph, JU, Jv, P, i + sz, sg, mo.phi);
-                const double xp = sigma_of<N, D>(ph, JU, Jv, P, i + 1, sg, mo.phi);
-                const double xm = sigma_of<N, D>(ph, JU, Jv, P, i - 1, sg, mo.phi);
-                const double yp = sigma_of<N, D>(ph, JU, Jv, P, i + sy, sg, mo.phi);
-                const double ym = sigma_of<N, D>(ph, JU, Jv, P, i - sy, sg, mo.phi);
+                const double sp = sigma_of<N, D, EXT>(ph, JU, Jv, P, i + sz, sg, mo.phi);
+                const double xp = sigma_of<N, D, EXT>(ph, JU, Jv, P, i + 1, sg, mo.phi);
+                const double xm = sigma_of<N, D, EXT>(ph, JU, Jv, P, i - 1, sg, mo.phi);
+                const double yp = sigma_of<N, D, EXT>(ph, JU, Jv, P, i + sy, sg, mo.phi);
+                const double ym = sigma_of<N, D, EXT>(ph, JU, Jv, P, i - sy, sg, mo.phi);
                 const double d0 = (xp - xm) * ih[0];
                 const double d1 = (yp - ym) * ih[1];
                 const double d2 = (sp - sm) * ih[2];
                 const double gv = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
                 grad[s * P + i] = gv;
-                gm[s] = fmax(gm[s], gv);
+                mg = fmax(mg, gv);
                 if (mo.form) {   // the same sum as k_monitor_grad: directions 0, 1, 2 in order
                     double lap = (xp - 2.0 * s0 + xm) / (g.dxi[0] * g.dxi[0]);
                     lap += (yp - 2.0 * s0 + ym) / (g.dxi[1] * g.dxi[1]);
                     lap += (sp - 2.0 * s0 + sm) / (g.dxi[2] * g.dxi[2]);
                     grad[(mo.nsig + s) * P + i] = fabs(lap);
-                    gm[mo.nsig + s] = fmax(gm[mo.nsig + s], fabs(lap));
+                    ml = fmax(ml, fabs(lap));
                 }
                 sm = s0;
                 s0 = sp;
+            }
+#pragma unroll
+            for (int c = 0; c < MON_CH; c++) {
+                if (c == s) gm[c] = mg;
+                if (mo.form && c == mo.nsig + s) gm[c] = ml;
             }
         }
     }
     const long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     const int nch = mo.form ? 2 * mo.nsig : mo.nsig;
+#pragma unroll
     for (int s = 0; s < MON_CH; s++) {
-        if (s >= nch) break;   // uniform across the block
         const double r = block_reduce<RED_MAX>(gm[s]);
-        if (threadIdx.x == 0) part[s * RED_BLOCKS + blk] = r;
+        if (threadIdx.x == 0 && s < nch) part[s * RED_BLOCKS + blk] = r;
     }
 }
 
@@ -1242,10 +1253,14 @@ __global__ void k_disp(Geo g, const double* __restrict__ xmu, const double* __re
 }
 
 template <int N, int D>
-static void launch_monitor(const Phys& ph, const Geo& g, const MonitorP& mo, const double* JU,
+static void launch_monitor(const Phys& ph, const Geo& g, const MonitorP& mo, bool ext, const double* JU,
                            const double* J, double* grad, double* part, int nb, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_monitor_grad<N, D>), dim3(nb), dim3(256), 0, s, ph, g, mo, JU, J, grad, part);
+    if (ext)
+        hipLaunchKernelGGL((k_monitor_grad<N, D, true>), dim3(nb), dim3(256), 0, s, ph, g, mo, JU, J, grad, part);
+    else
+        hipLaunchKernelGGL((k_monitor_grad<N, D, false>), dim3(nb), dim3(256), 0, s, ph, g, mo, JU, J, grad,
+                           part);
 }
 
 hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo_in, const double* JU,
@@ -1268,8 +1283,11 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo_in
     const bool march = g.dim == 3 && jblocks <= RED_BLOCKS;
     // the schlieren function first when the monitor uses it (th1 holds
     // |grad rho| until the filter overwrites it)
-    bool use_phi = false;
-    for (int q = 0; q < mo.nsig; q++) use_phi = use_phi || mo.sigma[q] == 5;
+    bool use_phi = false, ext = false;
+    for (int q = 0; q < mo.nsig; q++) {
+        use_phi = use_phi || mo.sigma[q] == 5;
+        ext = ext || mo.sigma[q] >= 4;
+    }
     if (use_phi) {
         ES_DISPATCH_ND(ph, g, launch_schlieren, ph, g, mo, JU, J, w.th1, w.part + 6 * RED_BLOCKS, w.scal + 7,
                        w.phi, nb, gi, s);
@@ -1277,12 +1295,13 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo_in
         if (e0 != hipSuccess) return e0;
     }
     // monitor and its global maxima
-    if (march && ph.nspec == 1)
-        hipLaunchKernelGGL(k_monitor_grad3<1>, jgrid, dim3(256), 0, s, ph, g, mo, JU, J, w.grad, w.part, jchunk);
-    else if (march)
-        hipLaunchKernelGGL(k_monitor_grad3<2>, jgrid, dim3(256), 0, s, ph, g, mo, JU, J, w.grad, w.part, jchunk);
-    else
-        ES_DISPATCH_ND(ph, g, launch_monitor, ph, g, mo, JU, J, w.grad, w.part, nb, s);
+    if (march) {
+        auto* kern = ph.nspec == 1 ? (ext ? k_monitor_grad3<1, true> : k_monitor_grad3<1, false>)
+                                   : (ext ? k_monitor_grad3<2, true> : k_monitor_grad3<2, false>);
+        hipLaunchKernelGGL(kern, jgrid, dim3(256), 0, s, ph, g, mo, JU, J, w.grad, w.part, jchunk);
+    } else {
+        ES_DISPATCH_ND(ph, g, launch_monitor, ph, g, mo, ext, JU, J, w.grad, w.part, nb, s);
+    }
     for (int q = 0; q < (mo.form ? 2 * mo.nsig : mo.nsig); q++)
         hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part + q * RED_BLOCKS,
                            march ? jblocks : nb, w.scal + q, 0, 0.0, status);
