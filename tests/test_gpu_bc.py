@@ -251,3 +251,36 @@ def test_batch_rejects_walled_grids():
     with pytest.raises(es.EsError) as e:
         es.Batch([sp])
     assert e.value.code == es.ES_EUNSUPPORTED
+
+
+def test_step_graph_replays_equal_eager_steps():
+    """Two moving-mesh steps of the walled shock-bubble captured in one HIP
+    graph: every replay, with eager steps and synchronisations between
+    replays, leaves the state, the mesh and the two dt bitwise equal to the
+    same steps run eagerly."""
+    say("[bc graph] 2d-shock-bubble, 2 steps per replay, 3 replays")
+    sp, JU, J, x, mon = bc_case("2d-shock-bubble")
+    ctx = es.Context(sp)
+    rU, rJ, rx = dev(JU), dev(J), dev(x)
+    gU, gJ, gx = dev(JU), dev(J), dev(x)
+    d_ref = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dts = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ctx.es_step(rU, rJ, rx, mon=mon, cfl=0.4, move_mesh=True)      # workspaces exist before capture
+    ctx.es_step(gU, gJ, gx, mon=mon, cfl=0.4, move_mesh=True)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for k in range(2):
+            ctx.es_step(gU, gJ, gx, mon=mon, cfl=0.4, move_mesh=True, dt_dev=dts[k:k + 1])
+    for r in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in range(2):
+            ctx.es_step(rU, rJ, rx, mon=mon, cfl=0.4, move_mesh=True, dt_dev=d_ref)
+            torch.cuda.synchronize()
+            if k == 1:
+                assert host(dts)[1] == host(d_ref)[0], r
+        np.testing.assert_array_equal(host(gU), host(rU))
+        np.testing.assert_array_equal(host(gJ), host(rJ))
+        np.testing.assert_array_equal(host(gx), host(rx))
+    assert ctx.es_status()[0] == es.ES_OK
