@@ -7,7 +7,7 @@ limiter) + GCL metrics + CFL step + three fused SSP-RK3 stages (ES flux:
 2w = 6 EC flux + MR-WENO dissipation) + ghost layers + the FP64 total
 entropy.  value = 256^3 * 3 / (seconds per step).
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -688,7 +688,7 @@ def main():
     if args.reconstruction == "js" and args.precision != "fp64":
         ap.error("--reconstruction js runs in FP64 only (add --precision fp64)")
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
