@@ -192,25 +192,36 @@ def test_bc_step_parity(name, nsteps):
         assert parity(hx[c], x[c], np.abs(x[c]).max()) <= TOL_FP64, c
 
 
-@pytest.mark.parametrize("example", ["shock-bubble-he", "shock-bubble-stiff", "tripoint"])
+@pytest.mark.parametrize("example", ["shock-bubble-he", "shock-bubble-stiff", "tripoint", "shock-bubble-he-3d"])
 def test_bc_examples_full_size_steps(example):
-    """Two moving-mesh steps at the examples' own sizes, every node."""
+    """Moving-mesh steps at the examples' own sizes, every node: two in 2D
+    (800 x 160, 350 x 150), one of Example 5.10 at 400 x 80 x 80."""
     say(f"[bc full size] {example}")
+    nsteps, cfl = 2, 0.4
     if example == "tripoint":
         sp = I.spec_tripoint()
         JU, J, x = I.init_tripoint(sp)
         mon = I.monitor_spec(n_sweeps=5, n_smooth=3, sigma=(0,), alpha=(1200.0,))
+    elif example == "shock-bubble-he-3d":
+        sp = I.spec_shock_bubble_walled("he", (400, 80, 80))
+        JU, J, x = I.init_shock_bubble_walled(sp)
+        mon = I.monitor_spec(n_sweeps=10, n_smooth=10, sigma=(0,), alpha=(1200.0,))
+        nsteps, cfl = 1, 0.3
+    elif example == "shock-bubble-stiff":
+        sp = I.spec_shock_bubble_walled("stiff")
+        JU, J, x = I.init_shock_bubble_walled(sp)
+        mon = I.monitor_m7()
     else:
-        sp = I.spec_shock_bubble_walled(example.split("-")[-1])
+        sp = I.spec_shock_bubble_walled("he")
         JU, J, x = I.init_shock_bubble_walled(sp)
         mon = I.monitor_spec(n_sweeps=5, n_smooth=3, sigma=(0,), alpha=(1000.0,))
     o = oracle.Oracle(sp)
     ctx = es.Context(sp)
     gU, gJ, gx = dev(JU), dev(J), dev(x)
-    for _ in range(2):
-        rc, dt, _ = o.step(JU, J, x, mon=mon, cfl=0.4, move_mesh=True)
+    for _ in range(nsteps):
+        rc, dt, _ = o.step(JU, J, x, mon=mon, cfl=cfl, move_mesh=True)
         assert rc == 0
-        ctx.es_step(gU, gJ, gx, mon=mon, cfl=0.4, move_mesh=True)
+        ctx.es_step(gU, gJ, gx, mon=mon, cfl=cfl, move_mesh=True)
     assert ctx.es_status()[0] == es.ES_OK
     Iin = I.interior(sp)
     _, lam, _ = o.max_wavespeed(JU, J, o.metrics(x)[0], 1.0)
@@ -218,7 +229,7 @@ def test_bc_examples_full_size_steps(example):
     hU, hx = host(gU), host(gx)
     for c in range(o.nc):
         assert parity(hU[c][Iin[1:]], JU[c][Iin[1:]], sc[c]) <= TOL_FP64, c
-    for c in range(2):
+    for c in range(sp["dim"]):
         assert parity(hx[c], x[c], np.abs(x[c]).max()) <= TOL_FP64, c
 
 
