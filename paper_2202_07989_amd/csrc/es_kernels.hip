@@ -64,7 +64,25 @@ __device__ __forceinline__ int ghost_image(const Geo& g, int k, int i, int& side
     return (side < 0 ? -1 - r : 2 * n - 1 - r) + g.ng;
 }
 
-__global__ void k_fill_shell(Geo g, double* __restrict__ a, int ncomp, int what, long nzs, long nys, long nxs)
+// ghost value of component c of a field of kind `what` from its image value v
+__device__ __forceinline__ double ghost_value(const Geo& g, int what, int c, const int side[3], double v)
+{
+    for (int k = 0; k < g.dim; k++) {
+        if (!side[k]) continue;
+        if (g.bc[k][side[k] > 0] == BC_PERIODIC) {
+            if (what == GH_MESH && c == k) v += side[k] * g.len[k];
+            continue;
+        }
+        if (what == GH_MESH && c == k) v = 2.0 * g.wall[k][side[k] > 0] - v;
+        if ((what == GH_DISP || what == GH_JXT) && c == k) v = -v;
+        if (what == GH_JXX && ((c / g.dim == k) != (c % g.dim == k))) v = -v;
+    }
+    return v;
+}
+
+// one or two fields (a2 may be null) of their own kinds per launch
+__global__ void k_fill_shell(Geo g, double* __restrict__ a, int ncomp, int what, double* __restrict__ a2,
+                             int ncomp2, int what2, long nzs, long nys, long nxs)
 {
     const long total = nzs + nys + nxs;
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
@@ -74,40 +92,31 @@ __global__ void k_fill_shell(Geo g, double* __restrict__ a, int ncomp, int what,
         for (int k = 0; k < g.dim; k++) sidx[k] = ghost_image(g, k, d[k], side[k]);
         const long di = node_index(g, d[0], d[1], d[2]);
         const long si = node_index(g, sidx[0], sidx[1], sidx[2]);
-        for (int c = 0; c < ncomp; c++) {
-            double v = a[c * g.P + si];
-            for (int k = 0; k < g.dim; k++) {
-                if (!side[k]) continue;
-                if (g.bc[k][side[k] > 0] == BC_PERIODIC) {
-                    if (what == GH_MESH && c == k) v += side[k] * g.len[k];
-                    continue;
-                }
-                if (what == GH_MESH && c == k) v = 2.0 * g.wall[k][side[k] > 0] - v;
-                if ((what == GH_DISP || what == GH_JXT) && c == k) v = -v;
-                if (what == GH_JXX && ((c / g.dim == k) != (c % g.dim == k))) v = -v;
-            }
-            a[c * g.P + di] = v;
-        }
+        for (int c = 0; c < ncomp; c++) a[c * g.P + di] = ghost_value(g, what, c, side, a[c * g.P + si]);
+        if (a2)
+            for (int c = 0; c < ncomp2; c++) a2[c * g.P + di] = ghost_value(g, what2, c, side, a2[c * g.P + si]);
     }
 }
 
-// the state's ghosts (J's are filled first): a reflecting wall mirrors U
-// with momentum component k negated, outflow copies U of the outermost
-// interior node, inflow takes the face's prescribed state (the lowest
-// direction's where several meet); JU = J (mirrored) times that U
-__global__ void k_fill_state(Geo g, InflowStates in, double* __restrict__ JU, const double* __restrict__ J,
+// the state's ghosts: J is a plain field (wrapped or mirrored); a
+// reflecting wall mirrors U with momentum component k negated, outflow
+// copies U of the outermost interior node, inflow takes the face's
+// prescribed state (the lowest direction's where several meet); JU = J
+// (mirrored) times that U
+__global__ void k_fill_state(Geo g, InflowStates in, double* __restrict__ JU, double* __restrict__ J,
                              int nc, int nspec, long nzs, long nys, long nxs)
 {
     const long total = nzs + nys + nxs;
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
         int d[3];
         shell_node(g, t, nzs, nys, d);
-        int src[3] = {d[0], d[1], d[2]};
+        int src[3] = {d[0], d[1], d[2]}, img[3] = {d[0], d[1], d[2]};
         int flip = 0, uk = -1, us = 0;
         bool extrap = false;
         for (int k = 0; k < g.dim; k++) {
             int side;
             src[k] = ghost_image(g, k, d[k], side);
+            img[k] = src[k];
             if (!side) continue;
             const int kind = g.bc[k][side > 0];
             if (kind == BC_REFLECT) flip |= 1 << k;
@@ -122,10 +131,12 @@ __global__ void k_fill_state(Geo g, InflowStates in, double* __restrict__ JU, co
         }
         const long di = node_index(g, d[0], d[1], d[2]);
         const long si = node_index(g, src[0], src[1], src[2]);
+        const double Jd = J[node_index(g, img[0], img[1], img[2])];
+        J[di] = Jd;
         for (int c = 0; c < nc; c++) {
             double u;
-            if (uk >= 0) u = J[di] * in.u[uk][us][c];
-            else if (extrap) u = J[di] * (JU[c * g.P + si] / J[si]);
+            if (uk >= 0) u = Jd * in.u[uk][us][c];
+            else if (extrap) u = Jd * (JU[c * g.P + si] / J[si]);
             else u = JU[c * g.P + si];
             if (uk < 0 && c >= nspec && c < nspec + g.dim && ((flip >> (c - nspec)) & 1)) u = -u;
             JU[c * g.P + di] = u;
@@ -142,24 +153,29 @@ static void shell_sizes(const Geo& g, long& nzs, long& nys, long& nxs)
     nxs = ng2 * g.n[1] * nz;
 }
 
-hipError_t fill_ghosts(const Geo& g, double* a, int ncomp, int what, hipStream_t s)
+hipError_t fill_ghosts2(const Geo& g, double* a, int ncomp, int what, double* a2, int ncomp2, int what2,
+                       hipStream_t s)
 {
     long nzs, nys, nxs;
     shell_sizes(g, nzs, nys, nxs);
     const long total = nzs + nys + nxs;
     const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_fill_shell, dim3(blocks), dim3(256), 0, s, g, a, ncomp, what, nzs, nys, nxs);
+    hipLaunchKernelGGL(k_fill_shell, dim3(blocks), dim3(256), 0, s, g, a, ncomp, what, a2, ncomp2, what2, nzs,
+                       nys, nxs);
     return hipGetLastError();
+}
+
+hipError_t fill_ghosts(const Geo& g, double* a, int ncomp, int what, hipStream_t s)
+{
+    return fill_ghosts2(g, a, ncomp, what, nullptr, 0, GH_PLAIN, s);
 }
 
 hipError_t fill_state(const Geo& g, const InflowStates& in, double* JU, double* J, int nc, int nspec,
                       hipStream_t s)
 {
-    hipError_t e = fill_ghosts(g, J, 1, GH_PLAIN, s);
-    if (e != hipSuccess) return e;
     bool periodic = true;
     for (int k = 0; k < g.dim; k++) periodic = periodic && g.bc[k][0] == BC_PERIODIC;
-    if (periodic) return fill_ghosts(g, JU, nc, GH_PLAIN, s);   // plain wrapped copies
+    if (periodic) return fill_ghosts2(g, JU, nc, GH_PLAIN, J, 1, GH_PLAIN, s);   // plain wrapped copies
     long nzs, nys, nxs;
     shell_sizes(g, nzs, nys, nxs);
     const long total = nzs + nys + nxs;
@@ -544,10 +560,7 @@ hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double*
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (!vcl_only) {
-        e = fill_ghosts(g, jxx, g.dim * g.dim, GH_JXX, s);
-        if (e != hipSuccess) return e;
-    }
+    if (!vcl_only) return fill_ghosts2(g, jxx, g.dim * g.dim, GH_JXX, jxt, g.dim, GH_JXT, s);
     if (jxt) e = fill_ghosts(g, jxt, g.dim, GH_JXT, s);
     return e;
 }
@@ -1109,10 +1122,39 @@ __global__ void k_filter(Geo g, const double* __restrict__ in, double* __restric
     }
 }
 
-// one Jacobi sweep of the mesh equations; per-block max |x_new - x_old|
+// one Jacobi update of interior node i
+template <int D>
+__device__ __forceinline__ void jacobi_node(const Geo& g, const double* th, const double* xa, long i, double* xn)
+{
+    const long P = g.P;
+    double tp[D], tm[D], ih2[D];
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        const long st = dir_stride(g, k);
+        tp[k] = 0.5 * (th[i] + th[i + st]);
+        tm[k] = 0.5 * (th[i] + th[i - st]);
+        ih2[k] = g.dxi[k] * g.dxi[k];
+    }
+#pragma unroll
+    for (int c = 0; c < D; c++) {
+        double num = 0.0, den = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            const long st = dir_stride(g, k);
+            num += (tp[k] * xa[c * P + i + st] + tm[k] * xa[c * P + i - st]) / ih2[k];
+            den += (tp[k] + tm[k]) / ih2[k];
+        }
+        xn[c] = num / den;
+    }
+}
+
+// one Jacobi sweep of the mesh equations, per-block max |x_new - x_old|,
+// with the ghost layers of its output in the same launch: a
+// ghost node takes the update of the interior node it wraps or mirrors to
+// (computed again, with the same arithmetic) under the mesh's ghost rule
 template <int D>
 __global__ void k_jacobi(Geo g, const double* __restrict__ th, const double* __restrict__ xa,
-                         double* __restrict__ xb, double* __restrict__ part)
+                         double* __restrict__ xb, double* __restrict__ part, long nzs, long nys, long nxs)
 {
     const long P = g.P;
     const long nint = n_interior(g);
@@ -1120,29 +1162,25 @@ __global__ void k_jacobi(Geo g, const double* __restrict__ th, const double* __r
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
         int i0, i1, i2;
         const long i = interior_node(g, q, i0, i1, i2);
-        double tp[D], tm[D], ih2[D];
-        double den = 0.0;
-#pragma unroll
-        for (int k = 0; k < D; k++) {
-            const long st = dir_stride(g, k);
-            tp[k] = 0.5 * (th[i] + th[i + st]);
-            tm[k] = 0.5 * (th[i] + th[i - st]);
-            ih2[k] = g.dxi[k] * g.dxi[k];
-        }
+        double xn[D];
+        jacobi_node<D>(g, th, xa, i, xn);
 #pragma unroll
         for (int c = 0; c < D; c++) {
-            double num = 0.0;
-            den = 0.0;
-#pragma unroll
-            for (int k = 0; k < D; k++) {
-                const long st = dir_stride(g, k);
-                num += (tp[k] * xa[c * P + i + st] + tm[k] * xa[c * P + i - st]) / ih2[k];
-                den += (tp[k] + tm[k]) / ih2[k];
-            }
-            const double xn = num / den;
-            xb[c * P + i] = xn;
-            r = fmax(r, fabs(xn - xa[c * P + i]));
+            xb[c * P + i] = xn[c];
+            r = fmax(r, fabs(xn[c] - xa[c * P + i]));
         }
+    }
+    const long total = nzs + nys + nxs;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+        int d[3];
+        shell_node(g, t, nzs, nys, d);
+        int sidx[3] = {d[0], d[1], d[2]}, side[3] = {0, 0, 0};
+        for (int k = 0; k < D; k++) sidx[k] = ghost_image(g, k, d[k], side[k]);
+        double xn[D];
+        jacobi_node<D>(g, th, xa, node_index(g, sidx[0], sidx[1], sidx[2]), xn);
+        const long di = node_index(g, d[0], d[1], d[2]);
+#pragma unroll
+        for (int c = 0; c < D; c++) xb[c * P + di] = ghost_value(g, GH_MESH, c, side, xn[c]);
     }
     r = block_reduce<RED_MAX>(r);
     if (threadIdx.x == 0) part[blockIdx.x] = r;
@@ -1318,7 +1356,10 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo_in
         if ((e = fill_ghosts(g, th2, 1, GH_PLAIN, s)) != hipSuccess) return e;
         std::swap(th, th2);
     }
-    // Jacobi sweeps: the first reads x_n itself, then xa and xb alternate
+    // Jacobi sweeps: the first reads x_n itself, then xa and xb alternate;
+    // the sweeps that are not z-marching write their own ghost layers
+    long nzs, nys, nxs;
+    shell_sizes(g, nzs, nys, nxs);
     const double* xcur = xn;
     double* xa = w.xa;
     double* xb = w.xb;
@@ -1326,10 +1367,10 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo_in
         if (march)
             hipLaunchKernelGGL(k_jacobi3, jgrid, dim3(256), 0, s, g, th, xcur, xa, w.part, jchunk);
         else if (g.dim == 2)
-            hipLaunchKernelGGL(k_jacobi<2>, dim3(nb), dim3(256), 0, s, g, th, xcur, xa, w.part);
+            hipLaunchKernelGGL(k_jacobi<2>, dim3(nb), dim3(256), 0, s, g, th, xcur, xa, w.part, nzs, nys, nxs);
         else
-            hipLaunchKernelGGL(k_jacobi<3>, dim3(nb), dim3(256), 0, s, g, th, xcur, xa, w.part);
-        if ((e = fill_ghosts(g, xa, g.dim, GH_MESH, s)) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_jacobi<3>, dim3(nb), dim3(256), 0, s, g, th, xcur, xa, w.part, nzs, nys, nxs);
+        if (march && (e = fill_ghosts(g, xa, g.dim, GH_MESH, s)) != hipSuccess) return e;
         if (resid_out)
             hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part, march ? jblocks : nb,
                                resid_out + nu, 0, 0.0, status);
