@@ -80,6 +80,22 @@ __device__ __forceinline__ double ghost_value(const Geo& g, int what, int c, con
     return v;
 }
 
+// The grid-stride kernels of this file that produce a field also write its ghost
+// layers when given the shell sizes (nzs + nys + nxs > 0): a ghost node
+// takes the value of the interior node it wraps or mirrors to, computed again
+// with the same arithmetic, under the field's ghost rule.  That saves the
+// separate fill launch.
+__device__ __forceinline__ long shell_image(const Geo& g, long t, long nzs, long nys, int side[3], long& di)
+{
+    int d[3];
+    shell_node(g, t, nzs, nys, d);
+    int sidx[3] = {d[0], d[1], d[2]};
+    side[0] = side[1] = side[2] = 0;
+    for (int k = 0; k < g.dim; k++) sidx[k] = ghost_image(g, k, d[k], side[k]);
+    di = node_index(g, d[0], d[1], d[2]);
+    return node_index(g, sidx[0], sidx[1], sidx[2]);
+}
+
 // one or two fields (a2 may be null) of their own kinds per launch
 __global__ void k_fill_shell(Geo g, double* __restrict__ a, int ncomp, int what, double* __restrict__ a2,
                              int ncomp2, int what2, long nzs, long nys, long nxs)
@@ -433,49 +449,70 @@ k_metric3(Geo g, Phys ph, const double* __restrict__ disp, const double* __restr
 }
 
 // 2D: J dxi_1/dx = (delta_2 x_2, -delta_2 x_1)/dxi_2, J dxi_2/dx = (-delta_1 x_2, delta_1 x_1)/dxi_1
+__device__ __forceinline__ void metric2_node(const Geo& g, const Phys& ph, const double* xn, const double* disp,
+                                             double cs, double dt, long i, double M[2][2], double nt[2])
+{
+    const long P = g.P;
+    const long s0 = 1, s1 = g.np[0];
+    double d[2][2];   // d[a][p] = delta_a[x_p]
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+        const long st = a == 0 ? s0 : s1;
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
+            double s = 0.0;
+            for (int m = 1; m <= ph.w; m++)
+                s += ph.alpha[m - 1] * (xs_at(xn, disp, cs, P, p, i + m * st) - xs_at(xn, disp, cs, P, p, i - m * st));
+            d[a][p] = 0.5 * s;
+        }
+    }
+    M[0][0] = d[1][1] / g.dxi[1];
+    M[0][1] = -d[1][0] / g.dxi[1];
+    M[1][0] = -d[0][1] / g.dxi[0];
+    M[1][1] = d[0][0] / g.dxi[0];
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        nt[k] = 0.0;
+        if (disp && dt > 0.0)
+#pragma unroll
+            for (int j = 0; j < 2; j++) nt[k] -= (disp[j * P + i] / dt) * M[k][j];
+    }
+}
+
 __global__ void k_metric2(Geo g, Phys ph, const double* __restrict__ xn,
                           const double* __restrict__ disp, double cs, const double* __restrict__ dt_dev,
-                          double* __restrict__ jxx, double* __restrict__ jxt)
+                          double* __restrict__ jxx, double* __restrict__ jxt, long nzs, long nys, long nxs)
 {
     const long P = g.P;
     const long nint = n_interior(g);
     const double dt = dt_dev ? *dt_dev : 0.0;
-    const long s0 = 1, s1 = g.np[0];
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
         int i0, i1, i2;
         const long i = interior_node(g, q, i0, i1, i2);
-        double d[2][2];   // d[a][p] = delta_a[x_p]
-#pragma unroll
-        for (int a = 0; a < 2; a++) {
-            const long st = a == 0 ? s0 : s1;
-#pragma unroll
-            for (int p = 0; p < 2; p++) {
-                double s = 0.0;
-                for (int m = 1; m <= ph.w; m++)
-                    s += ph.alpha[m - 1] * (xs_at(xn, disp, cs, P, p, i + m * st) -
-                                            xs_at(xn, disp, cs, P, p, i - m * st));
-                d[a][p] = 0.5 * s;
-            }
-        }
-        double M[2][2];
-        M[0][0] = d[1][1] / g.dxi[1];
-        M[0][1] = -d[1][0] / g.dxi[1];
-        M[1][0] = -d[0][1] / g.dxi[0];
-        M[1][1] = d[0][0] / g.dxi[0];
+        double M[2][2], nt[2];
+        metric2_node(g, ph, xn, disp, cs, dt, i, M, nt);
 #pragma unroll
         for (int k = 0; k < 2; k++)
 #pragma unroll
             for (int j = 0; j < 2; j++) jxx[(k * 2 + j) * P + i] = M[k][j];
-        if (jxt) {
+        if (jxt)
 #pragma unroll
-            for (int k = 0; k < 2; k++) {
-                double nt = 0.0;
-                if (disp && dt > 0.0)
+            for (int k = 0; k < 2; k++) jxt[k * P + i] = nt[k];
+    }
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < nzs + nys + nxs;
+         t += (long)gridDim.x * blockDim.x) {
+        int side[3];
+        long di;
+        const long si = shell_image(g, t, nzs, nys, side, di);
+        double M[2][2], nt[2];
+        metric2_node(g, ph, xn, disp, cs, dt, si, M, nt);
 #pragma unroll
-                    for (int j = 0; j < 2; j++) nt -= (disp[j * P + i] / dt) * M[k][j];
-                jxt[k * P + i] = nt;
-            }
-        }
+        for (int k = 0; k < 2; k++)
+#pragma unroll
+            for (int j = 0; j < 2; j++) jxx[(k * 2 + j) * P + di] = ghost_value(g, GH_JXX, k * 2 + j, side, M[k][j]);
+        if (jxt)
+#pragma unroll
+            for (int k = 0; k < 2; k++) jxt[k * P + di] = ghost_value(g, GH_JXT, k, side, nt[k]);
     }
 }
 
@@ -541,9 +578,12 @@ hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double*
     if (vcl_only) {
         if (!jxt) return hipSuccess;
         hipLaunchKernelGGL(k_vcl, dim3(grid_for(nint)), dim3(256), 0, s, g, disp, dt_dev, jxx, jxt);
-    } else if (g.dim == 2) {
+    } else if (g.dim == 2) {   // with its ghost layers
+        long nzs, nys, nxs;
+        shell_sizes(g, nzs, nys, nxs);
         hipLaunchKernelGGL(k_metric2, dim3(grid_for(nint)), dim3(256), 0, s, g, ph, xn, disp, cs, dt_dev,
-                           jxx, jxt);
+                           jxx, jxt, nzs, nys, nxs);
+        return hipGetLastError();
     } else {
         // z chunks: enough blocks to fill the chip, chunks long against the
         // 6-plane ring start-up
@@ -1080,45 +1120,71 @@ static void launch_schlieren(const Phys& ph, const Geo& g, const MonitorP& mo, c
     hipLaunchKernelGGL((k_schlieren<N, D>), dim3(gi), dim3(256), 0, s, ph, g, mo, JU, J, gr, gmax, phi);
 }
 
+__device__ __forceinline__ double theta_node(const MonitorP& mo, const double* grad, const double* gmax, long P,
+                                             long i)
+{
+    double th = 1.0;
+    for (int s = 0; s < mo.nsig; s++) {
+        const double G = gmax[s];
+        if (G > 0.0) {
+            const double r = grad[s * P + i] / G;
+            th += mo.form ? mo.alpha[s] * r : mo.alpha[s] * r * r;
+        }
+        if (mo.form && gmax[mo.nsig + s] > 0.0)
+            th += mo.beta[s] * (grad[(mo.nsig + s) * P + i] / gmax[mo.nsig + s]);
+    }
+    return sqrt(th);
+}
+
 __global__ void k_theta(Geo g, MonitorP mo, const double* __restrict__ grad, const double* __restrict__ gmax,
-                        double* __restrict__ theta)
+                        double* __restrict__ theta, long nzs, long nys, long nxs)
 {
     const long P = g.P;
     const long nint = n_interior(g);
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
         int i0, i1, i2;
         const long i = interior_node(g, q, i0, i1, i2);
-        double th = 1.0;
-        for (int s = 0; s < mo.nsig; s++) {
-            const double G = gmax[s];
-            if (G > 0.0) {
-                const double r = grad[s * P + i] / G;
-                th += mo.form ? mo.alpha[s] * r : mo.alpha[s] * r * r;
-            }
-            if (mo.form && gmax[mo.nsig + s] > 0.0)
-                th += mo.beta[s] * (grad[(mo.nsig + s) * P + i] / gmax[mo.nsig + s]);
-        }
-        theta[i] = sqrt(th);
+        theta[i] = theta_node(mo, grad, gmax, P, i);
+    }
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < nzs + nys + nxs;
+         t += (long)gridDim.x * blockDim.x) {
+        int side[3];
+        long di;
+        const long si = shell_image(g, t, nzs, nys, side, di);
+        theta[di] = theta_node(mo, grad, gmax, P, si);
     }
 }
 
 // low-pass filter: sum over j in {0,+-1}^d of (1/2)^(|j|_1 + d) Theta_{i+j}
-__global__ void k_filter(Geo g, const double* __restrict__ in, double* __restrict__ out)
+__device__ __forceinline__ double filter_node(const Geo& g, const double* in, long i)
 {
-    const long nint = n_interior(g);
     const long s0 = 1, s1 = g.np[0], s2 = (long)g.np[0] * g.np[1];
     const int r2 = g.dim == 3 ? 1 : 0;
+    double s = 0.0;
+    for (int j2 = -r2; j2 <= r2; j2++)
+        for (int j1 = -1; j1 <= 1; j1++)
+            for (int j0 = -1; j0 <= 1; j0++) {
+                const int e = abs(j0) + abs(j1) + abs(j2) + g.dim;
+                s += ldexp(1.0, -e) * in[i + j0 * s0 + j1 * s1 + j2 * s2];
+            }
+    return s;
+}
+
+__global__ void k_filter(Geo g, const double* __restrict__ in, double* __restrict__ out, long nzs, long nys,
+                         long nxs)
+{
+    const long nint = n_interior(g);
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
         int i0, i1, i2;
         const long i = interior_node(g, q, i0, i1, i2);
-        double s = 0.0;
-        for (int j2 = -r2; j2 <= r2; j2++)
-            for (int j1 = -1; j1 <= 1; j1++)
-                for (int j0 = -1; j0 <= 1; j0++) {
-                    const int e = abs(j0) + abs(j1) + abs(j2) + g.dim;
-                    s += ldexp(1.0, -e) * in[i + j0 * s0 + j1 * s1 + j2 * s2];
-                }
-        out[i] = s;
+        out[i] = filter_node(g, in, i);
+    }
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < nzs + nys + nxs;
+         t += (long)gridDim.x * blockDim.x) {
+        int side[3];
+        long di;
+        const long si = shell_image(g, t, nzs, nys, side, di);
+        out[di] = filter_node(g, in, si);
     }
 }
 
@@ -1278,7 +1344,7 @@ __global__ void k_limiter(Geo g, const double* __restrict__ xmu, const double* _
 }
 
 __global__ void k_disp(Geo g, const double* __restrict__ xmu, const double* __restrict__ xn,
-                       const double* __restrict__ dtau, double* __restrict__ disp)
+                       const double* __restrict__ dtau, double* __restrict__ disp, long nzs, long nys, long nxs)
 {
     const long P = g.P;
     const long nint = n_interior(g);
@@ -1287,6 +1353,14 @@ __global__ void k_disp(Geo g, const double* __restrict__ xmu, const double* __re
         int i0, i1, i2;
         const long i = interior_node(g, q, i0, i1, i2);
         for (int c = 0; c < g.dim; c++) disp[c * P + i] = d * (xmu[c * P + i] - xn[c * P + i]);
+    }
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < nzs + nys + nxs;
+         t += (long)gridDim.x * blockDim.x) {
+        int side[3];
+        long di;
+        const long si = shell_image(g, t, nzs, nys, side, di);
+        for (int c = 0; c < g.dim; c++)
+            disp[c * P + di] = ghost_value(g, GH_DISP, c, side, d * (xmu[c * P + si] - xn[c * P + si]));
     }
 }
 
@@ -1343,23 +1417,24 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo_in
     for (int q = 0; q < (mo.form ? 2 * mo.nsig : mo.nsig); q++)
         hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part + q * RED_BLOCKS,
                            march ? jblocks : nb, w.scal + q, 0, 0.0, status);
-    hipLaunchKernelGGL(k_theta, dim3(gi), dim3(256), 0, s, g, mo, w.grad, w.scal, w.th0);
-    hipError_t e = fill_ghosts(g, w.th0, 1, GH_PLAIN, s);
-    if (e != hipSuccess) return e;
+    // theta, the filter passes that are not z-marching, the Jacobi sweeps
+    // that are not and the displacement write their own ghost layers
+    long nzs, nys, nxs;
+    shell_sizes(g, nzs, nys, nxs);
+    hipError_t e = hipSuccess;
+    hipLaunchKernelGGL(k_theta, dim3(gi), dim3(256), 0, s, g, mo, w.grad, w.scal, w.th0, nzs, nys, nxs);
     double* th = w.th0;
     double* th2 = w.th1;
     for (int q = 0; q < mo.n_smooth; q++) {
-        if (march)
+        if (march) {
             hipLaunchKernelGGL(k_filter3, jgrid, dim3(256), 0, s, g, th, th2, jchunk);
-        else
-            hipLaunchKernelGGL(k_filter, dim3(gi), dim3(256), 0, s, g, th, th2);
-        if ((e = fill_ghosts(g, th2, 1, GH_PLAIN, s)) != hipSuccess) return e;
+            if ((e = fill_ghosts(g, th2, 1, GH_PLAIN, s)) != hipSuccess) return e;
+        } else {
+            hipLaunchKernelGGL(k_filter, dim3(gi), dim3(256), 0, s, g, th, th2, nzs, nys, nxs);
+        }
         std::swap(th, th2);
     }
-    // Jacobi sweeps: the first reads x_n itself, then xa and xb alternate;
-    // the sweeps that are not z-marching write their own ghost layers
-    long nzs, nys, nxs;
-    shell_sizes(g, nzs, nys, nxs);
+    // Jacobi sweeps: the first reads x_n itself, then xa and xb alternate
     const double* xcur = xn;
     double* xa = w.xa;
     double* xb = w.xb;
@@ -1383,9 +1458,7 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo_in
     else
         hipLaunchKernelGGL(k_limiter<3>, dim3(nb), dim3(256), 0, s, g, xcur, xn, w.part);
     hipLaunchKernelGGL(k_finish<RED_MIN>, dim3(1), dim3(256), 0, s, w.part, nb, w.scal + 6, 2, 0.0, status);
-    if ((e = fill_value(disp, g.dim * P, 0.0, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_disp, dim3(gi), dim3(256), 0, s, g, xcur, xn, w.scal + 6, disp);
-    if ((e = fill_ghosts(g, disp, g.dim, GH_DISP, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_disp, dim3(gi), dim3(256), 0, s, g, xcur, xn, w.scal + 6, disp, nzs, nys, nxs);
     if (dtau_out && (e = copy(w.scal + 6, dtau_out, 1, s)) != hipSuccess) return e;
     return hipGetLastError();
 }
