@@ -222,8 +222,23 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
         }
         R ay, av, aE;
         node_scales(ay, av, aE);
+        R mt[D - 1];
+        bool need = false;
 #pragma unroll
-        for (int j = 0; j < D - 1; j++) Z[N + 1 + j] = weno_field(Wt[j], sct * (av + fabs(F.vh[j + 1]) * aE));
+        for (int j = 0; j < D - 1; j++) {
+            mt[j] = sct * (av + fabs(F.vh[j + 1]) * aE);
+            need = need || fabs(Wt[j][3] - Wt[j][2]) > Wc.zero_tol * mt[j];
+        }
+        // where no lane of the wave has a jump above the tolerance, every
+        // field of the group has Y = 0 and its WENO jump is not needed (the
+        // same for the second group)
+        if (__any(need)) {
+#pragma unroll
+            for (int j = 0; j < D - 1; j++) Z[N + 1 + j] = weno_field(Wt[j], mt[j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < D - 1; j++) Z[N + 1 + j] = R(0);
+        }
     }
     // the second group reloads its node values from LDS rather than keeping
     // the first group's loads live across the first group's WENO
@@ -258,9 +273,18 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
             R mg[NM], ay, av, aE;
             node_scales(ay, av, aE);
             frame_scale_main<N, D, R>(F, ay, av, aE, mg);
+            bool need = false;
 #pragma unroll
-            for (int c = 0; c <= N; c++) Z[c] = weno_field(Wm[c], mg[c]);
-            Z[NC - 1] = weno_field(Wm[N + 1], mg[N + 1]);
+            for (int c = 0; c < NM; c++) need = need || fabs(Wm[c][3] - Wm[c][2]) > Wc.zero_tol * mg[c];
+            if (__any(need)) {
+#pragma unroll
+                for (int c = 0; c <= N; c++) Z[c] = weno_field(Wm[c], mg[c]);
+                Z[NC - 1] = weno_field(Wm[N + 1], mg[N + 1]);
+            } else {
+#pragma unroll
+                for (int c = 0; c <= N; c++) Z[c] = R(0);
+                Z[NC - 1] = R(0);
+            }
         }
     }
     R RZ[NC];
