@@ -240,50 +240,64 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
             for (int j = 0; j < D - 1; j++) Z[N + 1 + j] = R(0);
         }
     }
-    // the second group reloads its node values from LDS rather than keeping
-    // the first group's loads live across the first group's WENO
-    asm volatile("" ::: "memory");
+    // the acoustic and species (entropy) fields: in FP64 as two groups (the
+    // acoustic fields, then the species fields), each reloading its node
+    // values from LDS rather than keeping the previous group's loads live
+    // across its WENO, which keeps the sweep within 128 registers (four
+    // waves per SIMD); in FP32 as one group
     {
-        constexpr int NM = N + 2;          // fields 0..N and NC - 1
-        R Wm[NM][6];
-#pragma unroll
-        for (int t = 0; t < 6; t++) {
-            const int q = st[t];
-            const R bq = R(S.b[q]);
-            R vq[D], vr[D];
-            R v2 = R(0), vbv = R(0);
-#pragma unroll
-            for (int j = 0; j < D; j++) {
-                vq[j] = R(S.v[j][q]);
-                v2 += vq[j] * vq[j];
-                vbv += vbar[j] * vq[j];
-            }
-            R ys[N];
-            const double lbq = S.lb[q];
-#pragma unroll
-            for (int l = 0; l < N; l++)
-                ys[l] = R(ph.cv[l] * lbq + ph.Rg[l] * S.lrho[l][q] + ph.cvgam[l]) - R(0.5) * bq * v2;
-            rot_apply<D, R>(T, vq, vr);
-            R wm[NM];
-            frame_project_main<N, D, R>(F, ys, bq * vr[0], bq * vbv, -bq, wm);
-#pragma unroll
-            for (int c = 0; c < NM; c++) Wm[c][t] = wm[c];
-        }
+        constexpr int NM = N + 2;                  // main fields 0..N and NC - 1
+        constexpr int NGRP = sizeof(R) == 8 ? 2 : 1;
+        R mg[NM];
         {
-            R mg[NM], ay, av, aE;
+            R ay, av, aE;
             node_scales(ay, av, aE);
             frame_scale_main<N, D, R>(F, ay, av, aE, mg);
+        }
+#pragma unroll
+        for (int grp = 0; grp < NGRP; grp++) {
+            asm volatile("" ::: "memory");
+            // main field of the c-th member of this group, and its slot in Z
+            const int nf = NGRP == 1 ? NM : (grp == 0 ? 2 : NM - 2);
+            auto mfield = [&](int c) { return NGRP == 1 ? c : (grp == 0 ? (c == 0 ? 0 : NM - 1) : 1 + c); };
+            auto zslot = [&](int m) { return m <= N ? m : NC - 1; };
+            R Wg[NM][6];
+#pragma unroll
+            for (int t = 0; t < 6; t++) {
+                const int q = st[t];
+                const R bq = R(S.b[q]);
+                R vq[D], vr[D];
+                R v2 = R(0), vbv = R(0);
+#pragma unroll
+                for (int j = 0; j < D; j++) {
+                    vq[j] = R(S.v[j][q]);
+                    v2 += vq[j] * vq[j];
+                    vbv += vbar[j] * vq[j];
+                }
+                R ys[N];
+                const double lbq = S.lb[q];
+#pragma unroll
+                for (int l = 0; l < N; l++)
+                    ys[l] = R(ph.cv[l] * lbq + ph.Rg[l] * S.lrho[l][q] + ph.cvgam[l]) - R(0.5) * bq * v2;
+                rot_apply<D, R>(T, vq, vr);
+                R wm[NM];
+                frame_project_main<N, D, R>(F, ys, bq * vr[0], bq * vbv, -bq, wm);
+#pragma unroll
+                for (int c = 0; c < NM; c++)
+                    if (c < nf) Wg[c][t] = wm[mfield(c)];
+            }
             bool need = false;
 #pragma unroll
-            for (int c = 0; c < NM; c++) need = need || fabs(Wm[c][3] - Wm[c][2]) > Wc.zero_tol * mg[c];
+            for (int c = 0; c < NM; c++)
+                if (c < nf) need = need || fabs(Wg[c][3] - Wg[c][2]) > Wc.zero_tol * mg[mfield(c)];
             if (__any(need)) {
 #pragma unroll
-                for (int c = 0; c <= N; c++) Z[c] = weno_field(Wm[c], mg[c]);
-                Z[NC - 1] = weno_field(Wm[N + 1], mg[N + 1]);
+                for (int c = 0; c < NM; c++)
+                    if (c < nf) Z[zslot(mfield(c))] = weno_field(Wg[c], mg[mfield(c)]);
             } else {
 #pragma unroll
-                for (int c = 0; c <= N; c++) Z[c] = R(0);
-                Z[NC - 1] = R(0);
+                for (int c = 0; c < NM; c++)
+                    if (c < nf) Z[zslot(mfield(c))] = R(0);
             }
         }
     }

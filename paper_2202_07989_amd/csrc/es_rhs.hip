@@ -20,11 +20,11 @@
 
 namespace es {
 
-// three waves per SIMD: with the branches that skip the WENO of flat
-// regions the FP64 two-species sweep needs ~160 registers; capped at 128
-// (four waves) it spills 140 bytes per thread and is slower
+// waves per SIMD: four for FP64 (the dissipation's acoustic and species
+// fields in two groups keep it within 128 registers), three for FP32 (one
+// group; splitting it costs more than the fourth wave gains)
 template <int N, int D, int K, int TL, int TC, int MODE, typename R, int RC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 3, 8)))
 k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restrict__ Jv,
           const double* __restrict__ jxx, const double* __restrict__ jxt,
           double* __restrict__ accU, double* __restrict__ accJ, RkArgs rk,
