@@ -89,8 +89,9 @@ __device__ __forceinline__ void ec_pair(const Phys& ph, const NodeTile<N, D, NN>
 
 // ES dissipation 1/2 s T^T R Y [[W]]^WENO at the interface between tile
 // nodes iL (= i) and iR (= i+1); st[t] are the tile indices of nodes
-// i-2..i+3.  Interface metrics, averages and R follow Section 3.4.
-template <int N, int D, int NN, int RC, typename R>
+// i-2..i+3.  Interface metrics, averages and R follow Section 3.4.  MG: the
+// acoustic and species fields in one group or two.
+template <int N, int D, int NN, int RC, typename R, int MG>
 __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D, NN>& S,
                                             const int st[6], const Weno<R>& Wc, R* Dout)
 {
@@ -240,14 +241,13 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
             for (int j = 0; j < D - 1; j++) Z[N + 1 + j] = R(0);
         }
     }
-    // the acoustic and species (entropy) fields: in FP64 as two groups (the
-    // acoustic fields, then the species fields), each reloading its node
-    // values from LDS rather than keeping the previous group's loads live
-    // across its WENO, which keeps the sweep within 128 registers (four
-    // waves per SIMD); in FP32 as one group
+    // the acoustic and species (entropy) fields, as one group or (MG = 2)
+    // two, the acoustic fields and then the species fields, each reloading
+    // its node values from LDS rather than keeping the previous group's loads
+    // live across its WENO: fewer registers for more loads
     {
         constexpr int NM = N + 2;                  // main fields 0..N and NC - 1
-        constexpr int NGRP = sizeof(R) == 8 ? 2 : 1;
+        constexpr int NGRP = MG;
         R mg[NM];
         {
             R ay, av, aE;
@@ -335,8 +335,10 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
 // every flux is then formed in registers first and X is written only after
 // a barrier that ends all node reads.  Every thread of the block must call
 // this (it holds barriers).
-template <int N, int D, int NN, int TL, int TC, bool XALIAS, int RC, typename R, typename LI, typename XI,
-          typename LOK>
+// (MG: the dissipation's acoustic and species fields in one group or two;
+// two in FP64, where they keep the sweeps within fewer registers)
+template <int N, int D, int NN, int TL, int TC, bool XALIAS, int RC, typename R,
+          int MG = (sizeof(R) == 8 ? 2 : 1), typename LI, typename XI, typename LOK>
 __device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<N, D, NN>& S,
                                                  R (*X)[(TL + 4) * TC], LI lidx, XI xidx,
                                                  LOK line_ok, int fi, int fc, bool f_ok, int hid)
@@ -355,7 +357,7 @@ __device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<
             int st[6];
 #pragma unroll
             for (int q = 0; q < 6; q++) st[q] = lidx(fl - 2 + q, fc);
-            dissipation<N, D, NN, RC, R>(ph, S, st, Wc, G);
+            dissipation<N, D, NN, RC, R, MG>(ph, S, st, Wc, G);
         } else {
 #pragma unroll
             for (int cc = 0; cc < NC; cc++) G[cc] = R(0);

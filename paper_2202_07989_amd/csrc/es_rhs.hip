@@ -20,11 +20,13 @@
 
 namespace es {
 
-// waves per SIMD: four for FP64 (the dissipation's acoustic and species
-// fields in two groups keep it within 128 registers), three for FP32 (one
-// group; splitting it costs more than the fourth wave gains)
+// waves per SIMD: four for the FP64 x and y sweeps, whose dissipation takes
+// the acoustic and species fields in two groups to stay within 128
+// registers; three for the FP64 z sweep (its strided loads gain less from a
+// fourth wave than its spills cost) and for FP32 (one group: splitting it
+// costs more than a fourth wave gains)
 template <int N, int D, int K, int TL, int TC, int MODE, typename R, int RC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 4 : 3, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(R) == 8 && K != 2) ? 4 : 3, 8)))
 k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restrict__ Jv,
           const double* __restrict__ jxx, const double* __restrict__ jxt,
           double* __restrict__ accU, double* __restrict__ accJ, RkArgs rk,
