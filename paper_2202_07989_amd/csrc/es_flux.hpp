@@ -174,8 +174,9 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
 
     // scaled entropy variables W_j = R^T T V(U_j) of the stencil nodes
     // j = i-2..i+3, one group of characteristic fields at a time (the
-    // tangential fields, then the acoustic and species fields), each group's
-    // MR-WENO jumps taken as soon as its stencil values exist.  The acoustic
+    // tangential fields, then the acoustic and species fields, these two in
+    // separate groups when MG = 2), each group's MR-WENO jumps taken as soon
+    // as its stencil values exist.  The acoustic
     // and species fields see the rotated momentum variables only through
     // (T vbar).(T b v) = b vbar.v and the normal row of T v.
     R Z[NC];
