@@ -225,7 +225,12 @@ int es_entropy_rate(es_ctx *c, const double *JU, const double *J,
  * RK stages on the stage meshes x_n + c_s disp (c = 0, 1, 1/2), and
  * x_{n+1} = x_n + disp.  JU, J, x are updated in place; dt and Delta_tau
  * are written to dt_dev / dtau_dev when given.  m may be NULL when
- * move_mesh = 0. */
+ * move_mesh = 0.  The context keeps the metrics of x_{n+1} (the c = 1 stage
+ * mesh, whose ghost layers the face rules give) with a copy of that mesh,
+ * and the next call reuses them when its x_n equals the copy value for value
+ * (compared on the device), so x may be changed between calls; the first
+ * call allocates this copy (d P doubles) and a second metric buffer (d^2 P).
+ * Calls on one context must not overlap. */
 int es_step(es_ctx *c, const es_monitor *m, double cfl, double dt_fixed,
             int move_mesh, double *JU, double *J, double *x, double *dt_dev,
             double *dtau_dev, void *stream);

@@ -4,6 +4,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <limits>
 #include <vector>
 
 #include "../../include/es.h"
@@ -27,6 +28,11 @@ struct es_ctx {
     int mesh_nsig = 0;
     double *bufA = nullptr, *bufB = nullptr;
     double *jxx = nullptr, *jxt = nullptr, *disp = nullptr;
+    // es_step: the metrics in jxx are those of the mesh mx (ghost layers
+    // included; NaN until a step has written it), so the next step reuses
+    // them when its x^n equals mx; jxx2 holds the c = 1/2 stage's metrics
+    double *mx = nullptr, *jxx2 = nullptr;
+    int* reuse = nullptr;         // device flag: jxx holds the metrics of this step's x^n
 };
 
 // a batch of independent 2D instances advanced together
@@ -183,7 +189,14 @@ int ensure_step_ws(es_ctx* c)
     if (!rc) rc = dalloc(&c->jxx, d * d * P);
     if (!rc) rc = dalloc(&c->jxt, d * P);
     if (!rc) rc = dalloc(&c->disp, d * P);
+    if (!rc) rc = dalloc(&c->jxx2, d * d * P);
+    if (!rc) rc = dalloc(&c->reuse, 1);
     if (!rc) rc = ensure_metric_ws(c);
+    if (!rc && !c->mx) {
+        rc = dalloc(&c->mx, d * P);
+        if (!rc && fill_value(c->mx, d * P, std::numeric_limits<double>::quiet_NaN(), 0) != hipSuccess) rc = ES_EHIP;
+        if (!rc && hipDeviceSynchronize() != hipSuccess) rc = ES_EHIP;
+    }
     return rc;
 }
 
@@ -256,7 +269,7 @@ int es_destroy(es_ctx* c)
     if (!c) return ES_EINVAL;
     void* bufs[] = {c->status, c->scal, c->part, c->G, c->mesh.grad, c->mesh.th0, c->mesh.th1,
                     c->mesh.xa, c->mesh.xb, c->mesh.phi, c->mesh.part, c->mesh.scal, c->bufA,
-                    c->bufB, c->jxx, c->jxt, c->disp};
+                    c->bufB, c->jxx, c->jxt, c->disp, c->mx, c->jxx2, c->reuse};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     delete c;
@@ -403,11 +416,18 @@ int es_step(es_ctx* c, const es_monitor* m, double cfl, double dt_fixed, int mov
     } else {
         ES_TRY(set_scalar(dtau, 0.0, s));
     }
-    // metrics of x^n and the CFL step (zero mesh velocity).  With a moving
-    // mesh the same pass leaves -sum_j disp_j J dxi_k/dx_j in jxt (divided by
-    // the device scalar 1); stage 0's sweeps divide it by dt once dt exists
+    // metrics of x^n and the CFL step (zero mesh velocity).  x^n is as a
+    // rule the previous step's c = 1 stage mesh, whose metrics that step left
+    // in jxx beside a copy mx of the mesh: a device-side comparison of x^n
+    // with mx decides whether they are reused or formed afresh, so a caller
+    // may change x between steps.  With a moving mesh the same pass leaves
+    // -sum_j disp_j J dxi_k/dx_j in jxt (divided by the device scalar 1);
+    // stage 0's sweeps divide it by dt once dt exists
+    ES_TRY(same_values(x, c->mx, d * P, c->reuse, s));
     ES_TRY(metrics(ph, g, x, disp, 0.0, disp ? c->scal + 5 : nullptr, c->jxx, disp ? c->jxt : nullptr, 0,
-                   c->G, s));
+                   c->G, s, c->reuse));
+    // a fixed mesh keeps these metrics for the steps that follow
+    if (!disp) ES_TRY(copy_unless(x, c->mx, d * P, c->reuse, s));
     if (dt_fixed > 0.0) ES_TRY(set_scalar(dt, dt_fixed, s));
     else ES_TRY(wavespeed(ph, g, JU, J, c->jxx, cfl, c->part, c->scal, c->status, s));
     static const double A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
@@ -420,18 +440,28 @@ int es_step(es_ctx* c, const es_monitor* m, double cfl, double dt_fixed, int mov
     const double* inJ = J;
     double* accs[3][2] = {{c->bufA, c->bufA + nc * P}, {c->bufB, c->bufB + nc * P}, {c->bufA, c->bufA + nc * P}};
     double* outs[3][2] = {{c->bufA, c->bufA + nc * P}, {c->bufB, c->bufB + nc * P}, {JU, J}};
+    double* jxs[3] = {c->jxx, c->jxx, disp ? c->jxx2 : c->jxx};
     for (int st = 0; st < 3; st++) {
-        // stage mesh x^n + c_s disp (stage 0 has it from the pass above)
-        if (disp && st > 0) ES_TRY(metrics(ph, g, x, disp, Cs[st], dt, c->jxx, c->jxt, 0, c->G, s));
+        // stage mesh x^n + c_s disp (stage 0 has it from the pass above).
+        // The c = 1 stage mesh is x^{n+1} = x^n + disp: it is formed once, in
+        // mx, with its ghost layers by the face rules, and its metrics stay in
+        // jxx for the next step; the c = 1/2 stage's go to jxx2
+        if (disp && st == 1) {
+            ES_TRY(add(x, disp, c->mx, d * P, s));
+            ES_TRY(fill_ghosts(g, c->mx, d, GH_MESH, s));
+            ES_TRY(metrics(ph, g, c->mx, disp, 0.0, dt, c->jxx, c->jxt, 0, c->G, s));
+        } else if (disp && st == 2) {
+            ES_TRY(metrics(ph, g, x, disp, Cs[st], dt, c->jxx2, c->jxt, 0, c->G, s));
+        }
         RkArgs rk{JU, J, dt, A[st], B[st], outs[st][0], outs[st][1], (disp && st == 0) ? dt : nullptr};
-        ES_TRY(launch_rhs(ph, g, mixed, inU, inJ, c->jxx, disp ? c->jxt : nullptr, accs[st][0], accs[st][1],
+        ES_TRY(launch_rhs(ph, g, mixed, inU, inJ, jxs[st], disp ? c->jxt : nullptr, accs[st][0], accs[st][1],
                           &rk, c->status, s));
         ES_TRY(fill_state(g, c->inflow, outs[st][0], outs[st][1], nc, ph.nspec, s));
         inU = outs[st][0];
         inJ = outs[st][1];
     }
-    if (disp) ES_TRY(add_inplace(x, disp, d * P, s));
-    ES_TRY(fill_ghosts(g, x, d, GH_MESH, s));
+    // x^{n+1} with its ghost layers
+    if (disp) ES_TRY(copy(c->mx, x, d * P, s));
     if (dt_dev) ES_TRY(copy(dt, dt_dev, 1, s));
     if (dtau_dev) ES_TRY(copy(dtau, dtau_dev, 1, s));
 #undef ES_TRY

@@ -227,14 +227,33 @@ __global__ void k_fill_value(double* __restrict__ dst, long n, double v)
         dst[t] = v;
 }
 
-// a += b over n values
-__global__ void k_axpy1(double* __restrict__ a, const double* __restrict__ b, long n)
+// c = a + b over n values
+__global__ void k_add(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ c, long n)
 {
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
-        a[t] += b[t];
+        c[t] = a[t] + b[t];
 }
 
 __global__ void k_set_scalar(double* dst, double v) { if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v; }
+__global__ void k_set_int(int* dst, int v) { if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v; }
+
+// clears *flag unless a and b hold the same n values (a NaN never matches)
+__global__ void k_same(const double* __restrict__ a, const double* __restrict__ b, long n, int* __restrict__ flag)
+{
+    bool differ = false;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+        differ |= !(a[t] == b[t]);
+    if (differ) *flag = 0;
+}
+
+// dst = src over n values when *flag is zero
+__global__ void k_copy_unless(const double* __restrict__ src, double* __restrict__ dst, long n,
+                              const int* __restrict__ flag)
+{
+    if (*flag) return;
+    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+        dst[t] = src[t];
+}
 
 static int grid_for(long n) { return (int)std::max<long>(1, std::min<long>((n + 255) / 256, 16384)); }
 
@@ -248,9 +267,20 @@ hipError_t fill_value(double* dst, long n, double v, hipStream_t s)
     hipLaunchKernelGGL(k_fill_value, dim3(grid_for(n)), dim3(256), 0, s, dst, n, v);
     return hipGetLastError();
 }
-hipError_t add_inplace(double* a, const double* b, long n, hipStream_t s)
+hipError_t add(const double* a, const double* b, double* c, long n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_axpy1, dim3(grid_for(n)), dim3(256), 0, s, a, b, n);
+    hipLaunchKernelGGL(k_add, dim3(grid_for(n)), dim3(256), 0, s, a, b, c, n);
+    return hipGetLastError();
+}
+hipError_t same_values(const double* a, const double* b, long n, int* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, flag, 1);
+    hipLaunchKernelGGL(k_same, dim3(grid_for(n)), dim3(256), 0, s, a, b, n, flag);
+    return hipGetLastError();
+}
+hipError_t copy_unless(const double* src, double* dst, long n, const int* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy_unless, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n, flag);
     return hipGetLastError();
 }
 hipError_t set_scalar(double* dst, double v, hipStream_t s)
@@ -266,7 +296,7 @@ __device__ __forceinline__ double xs_at(const double* xn, const double* disp, do
                                         long i)
 {
     double v = xn[p * P + i];
-    if (disp) v += cs * disp[p * P + i];
+    if (disp && cs != 0.0) v += cs * disp[p * P + i];
     return v;
 }
 
@@ -301,8 +331,9 @@ __device__ __forceinline__ double cdiff(const double* al, double p1, double m1, 
 
 __global__ void __launch_bounds__(MT * MT)
 k_metric_prod3(Geo g, Phys ph, const double* __restrict__ xn, const double* __restrict__ disp,
-               double cs, double* __restrict__ Pr, int zchunk)
+               double cs, double* __restrict__ Pr, int zchunk, const int* __restrict__ reuse)
 {
+    if (reuse && *reuse) return;
     __shared__ double T[3][MH][MH];
     const long P = g.P;
     const int np0 = g.np[0], np1 = g.np[1], np2 = g.np[2];
@@ -380,8 +411,9 @@ k_metric_prod3(Geo g, Phys ph, const double* __restrict__ xn, const double* __re
 __global__ void __launch_bounds__(MX * MY)
 k_metric3(Geo g, Phys ph, const double* __restrict__ disp, const double* __restrict__ Pr,
           const double* __restrict__ dt_dev, double* __restrict__ jxx, double* __restrict__ jxt,
-          int zchunk)
+          int zchunk, const int* __restrict__ reuse)
 {
+    if (reuse && *reuse) return;
     const long P = g.P;
     const int np0 = g.np[0], np1 = g.np[1];
     const int x = g.ng + blockIdx.x * MX + threadIdx.x, y = g.ng + blockIdx.y * MY + threadIdx.y;
@@ -481,8 +513,10 @@ __device__ __forceinline__ void metric2_node(const Geo& g, const Phys& ph, const
 
 __global__ void k_metric2(Geo g, Phys ph, const double* __restrict__ xn,
                           const double* __restrict__ disp, double cs, const double* __restrict__ dt_dev,
-                          double* __restrict__ jxx, double* __restrict__ jxt, long nzs, long nys, long nxs)
+                          double* __restrict__ jxx, double* __restrict__ jxt, long nzs, long nys, long nxs,
+                          const int* __restrict__ reuse)
 {
+    if (reuse && *reuse) return;
     const long P = g.P;
     const long nint = n_interior(g);
     const double dt = dt_dev ? *dt_dev : 0.0;
@@ -516,10 +550,11 @@ __global__ void k_metric2(Geo g, Phys ph, const double* __restrict__ xn,
     }
 }
 
-// jxi_t only, from an existing jxi_x
+// jxi_t only, from an existing jxi_x (only when *only_if is set, if given)
 __global__ void k_vcl(Geo g, const double* __restrict__ disp, const double* __restrict__ dt_dev,
-                      const double* __restrict__ jxx, double* __restrict__ jxt)
+                      const double* __restrict__ jxx, double* __restrict__ jxt, const int* __restrict__ only_if)
 {
+    if (only_if && !*only_if) return;
     const long P = g.P;
     const int D = g.dim;
     const long nint = n_interior(g);
@@ -572,18 +607,27 @@ hipError_t jacobian(const Phys& ph, const Geo& g, const double* x, const double*
 
 hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double* disp, double cs,
                    const double* dt_dev, double* jxx, double* jxt, int vcl_only, double* G,
-                   hipStream_t s)
+                   hipStream_t s, const int* reuse)
 {
     const long nint = (long)g.n[0] * g.n[1] * (g.dim == 3 ? g.n[2] : 1);
+    // the stage mesh reads the displacement only where c_s is not zero (the
+    // 2D kernel tests c_s itself: it reads disp for the time metrics too)
+    const double* dx = cs != 0.0 ? disp : nullptr;
     if (vcl_only) {
         if (!jxt) return hipSuccess;
-        hipLaunchKernelGGL(k_vcl, dim3(grid_for(nint)), dim3(256), 0, s, g, disp, dt_dev, jxx, jxt);
+        hipLaunchKernelGGL(k_vcl, dim3(grid_for(nint)), dim3(256), 0, s, g, disp, dt_dev, jxx, jxt,
+                           (const int*)nullptr);
     } else if (g.dim == 2) {   // with its ghost layers
         long nzs, nys, nxs;
         shell_sizes(g, nzs, nys, nxs);
         hipLaunchKernelGGL(k_metric2, dim3(grid_for(nint)), dim3(256), 0, s, g, ph, xn, disp, cs, dt_dev,
-                           jxx, jxt, nzs, nys, nxs);
-        return hipGetLastError();
+                           jxx, jxt, nzs, nys, nxs, reuse);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess || !reuse || !jxt) return e;
+        // reused metrics: the time metrics of this step's displacement
+        hipLaunchKernelGGL(k_vcl, dim3(grid_for(nint)), dim3(256), 0, s, g, disp, dt_dev, jxx, jxt, reuse);
+        e = hipGetLastError();
+        return e != hipSuccess ? e : fill_ghosts(g, jxt, g.dim, GH_JXT, s);
     } else {
         // z chunks: enough blocks to fill the chip, chunks long against the
         // 6-plane ring start-up
@@ -591,12 +635,14 @@ hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double*
         const int nc1 = std::max(1, std::min(g.np[2] / 32, (1024 + bx1 * by1 - 1) / (bx1 * by1)));
         const int zc1 = (g.np[2] + nc1 - 1) / nc1;
         hipLaunchKernelGGL(k_metric_prod3, dim3(bx1, by1, (g.np[2] + zc1 - 1) / zc1), dim3(MT, MT), 0, s,
-                           g, ph, xn, disp, cs, G, zc1);
+                           g, ph, xn, dx, cs, G, zc1, reuse);
         const int bx2 = (g.n[0] + MX - 1) / MX, by2 = (g.n[1] + MY - 1) / MY;
         const int nc2 = std::max(1, std::min(g.n[2] / 16, (4096 + bx2 * by2 - 1) / (bx2 * by2)));
         const int zc2 = (g.n[2] + nc2 - 1) / nc2;
         hipLaunchKernelGGL(k_metric3, dim3(bx2, by2, (g.n[2] + zc2 - 1) / zc2), dim3(MX, MY), 0, s, g, ph,
-                           disp, G, dt_dev, jxx, jxt, zc2);
+                           disp, G, dt_dev, jxx, jxt, zc2, reuse);
+        if (reuse && jxt)
+            hipLaunchKernelGGL(k_vcl, dim3(grid_for(nint)), dim3(256), 0, s, g, disp, dt_dev, jxx, jxt, reuse);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

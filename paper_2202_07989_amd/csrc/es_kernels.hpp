@@ -53,12 +53,19 @@ hipError_t fill_state(const Geo& g, const InflowStates& in, double* JU, double* 
                       hipStream_t s);
 hipError_t copy(const double* src, double* dst, long n, hipStream_t s);
 hipError_t fill_value(double* dst, long n, double v, hipStream_t s);
-hipError_t add_inplace(double* a, const double* b, long n, hipStream_t s);
+hipError_t add(const double* a, const double* b, double* c, long n, hipStream_t s);
+// *flag = 1 if a and b hold the same n values, else 0 (device-side; NaN never matches)
+hipError_t same_values(const double* a, const double* b, long n, int* flag, hipStream_t s);
+// dst = src when *flag is 0
+hipError_t copy_unless(const double* src, double* dst, long n, const int* flag, hipStream_t s);
 hipError_t set_scalar(double* dst, double v, hipStream_t s);
 hipError_t jacobian(const Phys& ph, const Geo& g, const double* x, const double* jxx, double* J, hipStream_t s);
+// metrics of the stage mesh xn + cs disp, and with jxt the time metrics of the
+// mesh velocity disp / dt.  With reuse set on the device, jxx already holds
+// the metrics of this mesh (ghost layers included) and only jxt is formed.
 hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double* disp, double cs,
                    const double* dt_dev, double* jxx, double* jxt, int vcl_only, double* G,
-                   hipStream_t s);
+                   hipStream_t s, const int* reuse = nullptr);
 hipError_t wavespeed(const Phys& ph, const Geo& g, const double* JU, const double* J, const double* jxx,
                      double cfl, double* part, double* out2, unsigned* status, hipStream_t s);
 hipError_t entropy_sum(const Phys& ph, const Geo& g, const double* JU, const double* J, const double* dJU,
