@@ -408,22 +408,26 @@ int es_step(es_ctx* c, const es_monitor* m, double cfl, double dt_fixed, int mov
 
     ES_TRY(fill_state(g, c->inflow, JU, J, nc, ph.nspec, s));
     ES_TRY(fill_ghosts(g, x, d, GH_MESH, s));
+    // x^n is as a rule the previous step's c = 1 stage mesh, whose metrics
+    // that step left in jxx beside a copy mx of the mesh: a device-side
+    // comparison of x^n with mx (before the mesh step below overwrites mx)
+    // decides whether they are reused or formed afresh, so a caller may
+    // change x between steps
+    ES_TRY(same_values(x, c->mx, d * P, c->reuse, s));
     const double* disp = nullptr;
     if (move_mesh) {
+        // the displacement, and in mx the c = 1 stage mesh x^{n+1} = x^n + disp
+        // with its ghost layers by the face rules
         MonitorP mo = monitor_params(m);
-        ES_TRY(es::mesh_redistribute(ph, g, mo, JU, J, x, c->disp, c->mesh, dtau, nullptr, c->status, s));
+        ES_TRY(es::mesh_redistribute(ph, g, mo, JU, J, x, c->disp, c->mesh, dtau, nullptr, c->status, s,
+                                     c->mx));
         disp = c->disp;
     } else {
         ES_TRY(set_scalar(dtau, 0.0, s));
     }
-    // metrics of x^n and the CFL step (zero mesh velocity).  x^n is as a
-    // rule the previous step's c = 1 stage mesh, whose metrics that step left
-    // in jxx beside a copy mx of the mesh: a device-side comparison of x^n
-    // with mx decides whether they are reused or formed afresh, so a caller
-    // may change x between steps.  With a moving mesh the same pass leaves
-    // -sum_j disp_j J dxi_k/dx_j in jxt (divided by the device scalar 1);
-    // stage 0's sweeps divide it by dt once dt exists
-    ES_TRY(same_values(x, c->mx, d * P, c->reuse, s));
+    // metrics of x^n and the CFL step (zero mesh velocity).  With a moving
+    // mesh the same pass leaves -sum_j disp_j J dxi_k/dx_j in jxt (divided by
+    // the device scalar 1); stage 0's sweeps divide it by dt once dt exists
     ES_TRY(metrics(ph, g, x, disp, 0.0, disp ? c->scal + 5 : nullptr, c->jxx, disp ? c->jxt : nullptr, 0,
                    c->G, s, c->reuse));
     // a fixed mesh keeps these metrics for the steps that follow
@@ -443,12 +447,10 @@ int es_step(es_ctx* c, const es_monitor* m, double cfl, double dt_fixed, int mov
     double* jxs[3] = {c->jxx, c->jxx, disp ? c->jxx2 : c->jxx};
     for (int st = 0; st < 3; st++) {
         // stage mesh x^n + c_s disp (stage 0 has it from the pass above).
-        // The c = 1 stage mesh is x^{n+1} = x^n + disp: it is formed once, in
-        // mx, with its ghost layers by the face rules, and its metrics stay in
-        // jxx for the next step; the c = 1/2 stage's go to jxx2
+        // The c = 1 stage mesh is x^{n+1}, formed once in mx by the mesh step;
+        // its metrics stay in jxx for the next step, and the c = 1/2 stage's
+        // go to jxx2
         if (disp && st == 1) {
-            ES_TRY(add(x, disp, c->mx, d * P, s));
-            ES_TRY(fill_ghosts(g, c->mx, d, GH_MESH, s));
             ES_TRY(metrics(ph, g, c->mx, disp, 0.0, dt, c->jxx, c->jxt, 0, c->G, s));
         } else if (disp && st == 2) {
             ES_TRY(metrics(ph, g, x, disp, Cs[st], dt, c->jxx2, c->jxt, 0, c->G, s));

@@ -227,13 +227,6 @@ __global__ void k_fill_value(double* __restrict__ dst, long n, double v)
         dst[t] = v;
 }
 
-// c = a + b over n values
-__global__ void k_add(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ c, long n)
-{
-    for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
-        c[t] = a[t] + b[t];
-}
-
 __global__ void k_set_scalar(double* dst, double v) { if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v; }
 __global__ void k_set_int(int* dst, int v) { if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v; }
 
@@ -265,11 +258,6 @@ hipError_t copy(const double* src, double* dst, long n, hipStream_t s)
 hipError_t fill_value(double* dst, long n, double v, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill_value, dim3(grid_for(n)), dim3(256), 0, s, dst, n, v);
-    return hipGetLastError();
-}
-hipError_t add(const double* a, const double* b, double* c, long n, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_add, dim3(grid_for(n)), dim3(256), 0, s, a, b, c, n);
     return hipGetLastError();
 }
 hipError_t same_values(const double* a, const double* b, long n, int* flag, hipStream_t s)
@@ -1389,8 +1377,12 @@ __global__ void k_limiter(Geo g, const double* __restrict__ xmu, const double* _
     if (threadIdx.x == 0) part[blockIdx.x] = b;
 }
 
+// disp = Delta_tau (x^[mu] - x_n) with its ghost layers; with xnext, also
+// x_{n+1} = x_n + disp with the mesh's ghost layers (each ghost node from
+// the sum at its image node, as a ghost fill of x_{n+1} gives it)
 __global__ void k_disp(Geo g, const double* __restrict__ xmu, const double* __restrict__ xn,
-                       const double* __restrict__ dtau, double* __restrict__ disp, long nzs, long nys, long nxs)
+                       const double* __restrict__ dtau, double* __restrict__ disp, double* __restrict__ xnext,
+                       long nzs, long nys, long nxs)
 {
     const long P = g.P;
     const long nint = n_interior(g);
@@ -1398,15 +1390,22 @@ __global__ void k_disp(Geo g, const double* __restrict__ xmu, const double* __re
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
         int i0, i1, i2;
         const long i = interior_node(g, q, i0, i1, i2);
-        for (int c = 0; c < g.dim; c++) disp[c * P + i] = d * (xmu[c * P + i] - xn[c * P + i]);
+        for (int c = 0; c < g.dim; c++) {
+            const double v = d * (xmu[c * P + i] - xn[c * P + i]);
+            disp[c * P + i] = v;
+            if (xnext) xnext[c * P + i] = xn[c * P + i] + v;
+        }
     }
     for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < nzs + nys + nxs;
          t += (long)gridDim.x * blockDim.x) {
         int side[3];
         long di;
         const long si = shell_image(g, t, nzs, nys, side, di);
-        for (int c = 0; c < g.dim; c++)
-            disp[c * P + di] = ghost_value(g, GH_DISP, c, side, d * (xmu[c * P + si] - xn[c * P + si]));
+        for (int c = 0; c < g.dim; c++) {
+            const double v = d * (xmu[c * P + si] - xn[c * P + si]);
+            disp[c * P + di] = ghost_value(g, GH_DISP, c, side, v);
+            if (xnext) xnext[c * P + di] = ghost_value(g, GH_MESH, c, side, xn[c * P + si] + v);
+        }
     }
 }
 
@@ -1423,7 +1422,8 @@ static void launch_monitor(const Phys& ph, const Geo& g, const MonitorP& mo, boo
 
 hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo_in, const double* JU,
                              const double* J, const double* xn, double* disp, MeshWork& w,
-                             double* dtau_out, double* resid_out, unsigned* status, hipStream_t s)
+                             double* dtau_out, double* resid_out, unsigned* status, hipStream_t s,
+                             double* xnext)
 {
     MonitorP mo = mo_in;
     mo.phi = w.phi;
@@ -1504,7 +1504,7 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo_in
     else
         hipLaunchKernelGGL(k_limiter<3>, dim3(nb), dim3(256), 0, s, g, xcur, xn, w.part);
     hipLaunchKernelGGL(k_finish<RED_MIN>, dim3(1), dim3(256), 0, s, w.part, nb, w.scal + 6, 2, 0.0, status);
-    hipLaunchKernelGGL(k_disp, dim3(gi), dim3(256), 0, s, g, xcur, xn, w.scal + 6, disp, nzs, nys, nxs);
+    hipLaunchKernelGGL(k_disp, dim3(gi), dim3(256), 0, s, g, xcur, xn, w.scal + 6, disp, xnext, nzs, nys, nxs);
     if (dtau_out && (e = copy(w.scal + 6, dtau_out, 1, s)) != hipSuccess) return e;
     return hipGetLastError();
 }

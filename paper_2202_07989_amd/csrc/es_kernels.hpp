@@ -53,7 +53,6 @@ hipError_t fill_state(const Geo& g, const InflowStates& in, double* JU, double* 
                       hipStream_t s);
 hipError_t copy(const double* src, double* dst, long n, hipStream_t s);
 hipError_t fill_value(double* dst, long n, double v, hipStream_t s);
-hipError_t add(const double* a, const double* b, double* c, long n, hipStream_t s);
 // *flag = 1 if a and b hold the same n values, else 0 (device-side; NaN never matches)
 hipError_t same_values(const double* a, const double* b, long n, int* flag, hipStream_t s);
 // dst = src when *flag is 0
@@ -70,9 +69,11 @@ hipError_t wavespeed(const Phys& ph, const Geo& g, const double* JU, const doubl
                      double cfl, double* part, double* out2, unsigned* status, hipStream_t s);
 hipError_t entropy_sum(const Phys& ph, const Geo& g, const double* JU, const double* J, const double* dJU,
                        const double* dJ, double* part, double* out, hipStream_t s);
+// with xnext, also x_{n+1} = xn + disp with its ghost layers
 hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo, const double* JU,
                              const double* J, const double* xn, double* disp, MeshWork& w,
-                             double* dtau_out, double* resid_out, unsigned* status, hipStream_t s);
+                             double* dtau_out, double* resid_out, unsigned* status, hipStream_t s,
+                             double* xnext = nullptr);
 
 struct RkArgs {
     const double* JUn;
