@@ -304,6 +304,22 @@ __device__ __forceinline__ double xs_at(const double* xn, const double* disp, do
 //   the neighbouring rows are read by other waves at the same time and come
 //   from the caches, and with no LDS and no barrier every wave walks at its
 //   own pace.  Both shapes were the faster of the two designs for their pass.
+// Tile of this block for the z-marching kernels.  Consecutive blocks are
+// dealt round-robin to the 8 XCDs, each with its own L2; this permutation
+// gives each XCD a contiguous run of tiles (a whole z chunk of (x, y) tiles
+// at the usual grids), so the in-plane neighbour rows that adjacent tiles
+// read from each other come from one L2 (the 3D metrics take 8% less time).
+// Any grid size: the first nb % 8 XCDs take one tile more.
+__device__ __forceinline__ void xcd_tile(int& bx, int& by, int& bz)
+{
+    const unsigned gx = gridDim.x, gy = gridDim.y, nb = gx * gy * gridDim.z;
+    const unsigned L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned q = nb / 8, r = nb % 8, c = L % 8;
+    const unsigned T = c * q + (c < r ? c : r) + L / 8;
+    bx = (int)(T % gx);
+    by = (int)((T / gx) % gy);
+    bz = (int)(T / (gx * gy));
+}
 constexpr int MT = 16;
 constexpr int MH = MT + 6;
 constexpr int MX = 64, MY = 4;
@@ -326,9 +342,11 @@ k_metric_prod3(Geo g, Phys ph, const double* __restrict__ xn, const double* __re
     const long P = g.P;
     const int np0 = g.np[0], np1 = g.np[1], np2 = g.np[2];
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int x0 = blockIdx.x * MT, y0 = blockIdx.y * MT;
+    int bx, by, bz;
+    xcd_tile(bx, by, bz);
+    const int x0 = bx * MT, y0 = by * MT;
     const int x = x0 + tx, y = y0 + ty;
-    const int zc0 = blockIdx.z * zchunk, zc1 = min(zc0 + zchunk, np2);
+    const int zc0 = bz * zchunk, zc1 = min(zc0 + zchunk, np2);
     const bool in = x < np0 && y < np1;
     const bool xin = x >= g.ng && x < g.ng + g.n[0];
     const bool yin = y >= g.ng && y < g.ng + g.n[1];
@@ -404,8 +422,10 @@ k_metric3(Geo g, Phys ph, const double* __restrict__ disp, const double* __restr
     if (reuse && *reuse) return;
     const long P = g.P;
     const int np0 = g.np[0], np1 = g.np[1];
-    const int x = g.ng + blockIdx.x * MX + threadIdx.x, y = g.ng + blockIdx.y * MY + threadIdx.y;
-    const int zc0 = g.ng + blockIdx.z * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
+    int bx, by, bz;
+    xcd_tile(bx, by, bz);
+    const int x = g.ng + bx * MX + threadIdx.x, y = g.ng + by * MY + threadIdx.y;
+    const int zc0 = g.ng + bz * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
     if (x >= g.ng + g.n[0] || y >= g.ng + g.n[1]) return;
     const double dt = dt_dev ? *dt_dev : 0.0;
     const double al[3] = {ph.alpha[0], ph.alpha[1], ph.alpha[2]};
@@ -1010,9 +1030,11 @@ k_monitor_grad3(Phys ph, Geo g, MonitorP mo, const double* __restrict__ JU, cons
     constexpr int D = 3;
     const long P = g.P;
     const int np0 = g.np[0], np1 = g.np[1];
-    const int x = g.ng + blockIdx.x * 64 + (int)(threadIdx.x & 63);
-    const int y = g.ng + blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-    const int zc0 = g.ng + blockIdx.z * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
+    int bx, by, bz;
+    xcd_tile(bx, by, bz);
+    const int x = g.ng + bx * 64 + (int)(threadIdx.x & 63);
+    const int y = g.ng + by * 4 + (int)(threadIdx.x >> 6);
+    const int zc0 = g.ng + bz * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
     const bool in = x < g.ng + g.n[0] && y < g.ng + g.n[1];
     const long sy = np0, sz = (long)np0 * np1;
     double ih[3];
@@ -1072,9 +1094,11 @@ __global__ void __launch_bounds__(256)
 k_filter3(Geo g, const double* __restrict__ in, double* __restrict__ out, int zchunk)
 {
     const int np0 = g.np[0], np1 = g.np[1];
-    const int x = g.ng + blockIdx.x * 64 + (int)(threadIdx.x & 63);
-    const int y = g.ng + blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-    const int zc0 = g.ng + blockIdx.z * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
+    int bx, by, bz;
+    xcd_tile(bx, by, bz);
+    const int x = g.ng + bx * 64 + (int)(threadIdx.x & 63);
+    const int y = g.ng + by * 4 + (int)(threadIdx.x >> 6);
+    const int zc0 = g.ng + bz * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
     if (x >= g.ng + g.n[0] || y >= g.ng + g.n[1] || zc0 >= zc1) return;
     const long sy = np0, sz = (long)np0 * np1;
     auto plane = [&](long c) {   // in-plane (1/4, 1/2, 1/4) x (1/4, 1/2, 1/4) sum around c
@@ -1298,9 +1322,11 @@ k_jacobi3(Geo g, const double* __restrict__ th, const double* __restrict__ xa, d
 {
     const long P = g.P;
     const int np0 = g.np[0], np1 = g.np[1];
-    const int x = g.ng + blockIdx.x * 64 + (int)(threadIdx.x & 63);
-    const int y = g.ng + blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-    const int zc0 = g.ng + blockIdx.z * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
+    int bx, by, bz;
+    xcd_tile(bx, by, bz);
+    const int x = g.ng + bx * 64 + (int)(threadIdx.x & 63);
+    const int y = g.ng + by * 4 + (int)(threadIdx.x >> 6);
+    const int zc0 = g.ng + bz * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
     const bool in = x < g.ng + g.n[0] && y < g.ng + g.n[1];
     const long sy = np0, sz = (long)np0 * np1;
     double ih2[3];
