@@ -193,9 +193,15 @@ int ensure_step_ws(es_ctx* c)
     if (!rc) rc = dalloc(&c->reuse, 1);
     if (!rc) rc = ensure_metric_ws(c);
     if (!rc && !c->mx) {
-        rc = dalloc(&c->mx, d * P);
-        if (!rc && fill_value(c->mx, d * P, std::numeric_limits<double>::quiet_NaN(), 0) != hipSuccess) rc = ES_EHIP;
-        if (!rc && hipDeviceSynchronize() != hipSuccess) rc = ES_EHIP;
+        // kept only once it holds NaN, which no mesh equals
+        double* mx = nullptr;
+        rc = dalloc(&mx, d * P);
+        if (!rc && (fill_value(mx, d * P, std::numeric_limits<double>::quiet_NaN(), 0) != hipSuccess ||
+                    hipDeviceSynchronize() != hipSuccess)) {
+            (void)hipFree(mx);
+            rc = ES_EHIP;
+        }
+        if (!rc) c->mx = mx;
     }
     return rc;
 }
