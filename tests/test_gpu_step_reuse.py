@@ -22,8 +22,9 @@ from gpu_util import dev, host, say  # noqa: E402
 from cases import prepared  # noqa: E402
 from test_gpu_bc import bc_case  # noqa: E402
 
-CASES = [("2d-n2-bubble", True), ("3d-n2-bubble", True), ("2d-n1", False),
-         ("2d-shock-bubble", True), ("3d-mixed", True), ("3d-mixed", False)]
+CASES = [("2d-n2-bubble", True, "fp64"), ("3d-n2-bubble", True, "fp64"), ("2d-n1", False, "fp64"),
+         ("2d-shock-bubble", True, "fp64"), ("3d-mixed", True, "fp64"), ("3d-mixed", False, "fp64"),
+         ("2d-shock-bubble", True, "mixed"), ("3d-n2-bubble", True, "mixed")]
 
 
 def setup(name, move):
@@ -46,28 +47,29 @@ def assert_same(a, b, what):
         np.testing.assert_array_equal(host(u), host(v), err_msg=f"{what}: array {k}")
 
 
-def versus_fresh(sp, ctx, st, mon, move, what):
+def versus_fresh(sp, prec, ctx, st, mon, move, what):
     """One step on ctx and one on a fresh context from a copy of st."""
     other = [t.clone() for t in st]
     da = step(ctx, st, mon, move)
-    db = step(es.Context(sp), other, mon, move)
+    db = step(es.Context(sp, precision=prec), other, mon, move)
     assert_same(st + [da], other + [db], what)
 
 
-@pytest.mark.parametrize("name,move", CASES)
-def test_kept_metrics_equal_fresh_ones(name, move):
-    say(f"[metric reuse] {name} move={move}")
+@pytest.mark.parametrize("name,move,precision", CASES)
+def test_kept_metrics_equal_fresh_ones(name, move, precision):
+    say(f"[metric reuse] {name} move={move} {precision}")
     sp, JU, J, x, mon = setup(name, move)
-    ctx = es.Context(sp)
+    prec = es.ES_MIXED if precision == "mixed" else es.ES_FP64
+    ctx = es.Context(sp, precision=prec)
     st = [dev(JU), dev(J), dev(x)]
     step(ctx, st, mon, move)
-    versus_fresh(sp, ctx, st, mon, move, "second step")
+    versus_fresh(sp, prec, ctx, st, mon, move, "second step")
     # the caller moves one interior node by a thousandth of the spacing there
     ng, n = sp["ng"], sp["n"]
     z = ng + n[2] // 2 if sp["dim"] == 3 else 0
     y, i = ng + n[1] // 2, ng + n[0] // 2
     hx = host(st[2])
     st[2][0, z, y, i] += 1e-3 * (hx[0, z, y, i + 1] - hx[0, z, y, i])
-    versus_fresh(sp, ctx, st, mon, move, "after the caller moved a node")
-    versus_fresh(sp, ctx, st, mon, move, "the step after that")
+    versus_fresh(sp, prec, ctx, st, mon, move, "after the caller moved a node")
+    versus_fresh(sp, prec, ctx, st, mon, move, "the step after that")
     assert ctx.es_status()[0] == es.ES_OK
