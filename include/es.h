@@ -100,6 +100,17 @@ typedef struct {
                        /* (wall[k][1] > wall[k][0])                             */
     double inflow[3][2][6]; /* conserved state U (rho_1..rho_N, rho v, E) of    */
                        /* each ES_BC_INFLOW face (finite)                       */
+    double sign_tol;   /* zero tolerance of the sign matrix Y (Section 3.4,     */
+                       /* after eq HOstable) in FP64 arithmetic, and           */
+    double sign_tol32; /* in the FP32 arithmetic of ES_MIXED: Y_mm = 1 iff the  */
+                       /* WENO jump and the jump [[W_m]] agree in sign and      */
+                       /* |[[W_m]]| > tol * B_m, B_m a bound on the terms that  */
+                       /* form W_m at the two nodes (B_m >= sum_e |R_em|        */
+                       /* (|(T V_i)_e| + |(T V_i+1)_e|)).  0 is the paper's     */
+                       /* rule as printed; 0 <= tol < 1 (else ES_EINVAL).  The  */
+                       /* reading used for the paper's workloads is 1e-12 and  */
+                       /* 1e-6: where a contact leaves the acoustic jumps at    */
+                       /* rounding level, Y is then not decided by rounding    */
 } es_grid;
 
 typedef struct {

@@ -36,7 +36,7 @@ class Grid(C.Structure):
         ("gamma", C.c_double * 2), ("cv", C.c_double * 2), ("pinf", C.c_double * 2),
         ("chi", C.c_double * 3), ("weno_eps", C.c_double), ("dissipation", C.c_int),
         ("reconstruction", C.c_int), ("bc", (C.c_int * 2) * 3), ("wall", (C.c_double * 2) * 3),
-        ("inflow", ((C.c_double * 6) * 2) * 3),
+        ("inflow", ((C.c_double * 6) * 2) * 3), ("sign_tol", C.c_double),
     ]
 
 
@@ -72,6 +72,9 @@ def lib():
             "orc_rotation": (None, [_G, _D, _D]),
             "orc_interface_frame": (C.c_int, [_G, _D, _D, _D, _D, _D]),
             "orc_mr5": (C.c_double, [_D, _D, C.c_double]),
+            "orc_sign_bound": (C.c_int, [_G, _D, _D, _D, _D]),
+            "orc_sign_test": (C.c_int, [_G, _D, _D, _D, _D, C.c_int, C.c_int, C.POINTER(C.c_long),
+                                         _D, _D, _D, C.POINTER(C.c_int), _D]),
             "orc_js5": (C.c_double, [_D, C.c_double]),
             "orc_jacobian": (C.c_int, [_G, _D, _D, _D]),
             "orc_npoints": (C.c_long, [_G]),
@@ -139,6 +142,8 @@ def grid(spec) -> Grid:
     for (k, side), U in spec.get("inflow", {}).items():
         for c, u in enumerate(U):
             g.inflow[k][side][c] = u
+    # zero tolerance of the sign matrix (0: the paper's rule as printed)
+    g.sign_tol = spec.get("sign_tol", 1e-12)
     return g
 
 
@@ -222,6 +227,25 @@ class Oracle:
         args = [np.ascontiguousarray(a, dtype=np.float64) for a in (Ul, Ur, m)]
         self.L.orc_interface_frame(self.gp, *[_p(a) for a in args], _p(R), C.byref(s))
         return R, s.value
+
+    def sign_bound(self, Ul, Ur, m):
+        B = np.zeros(self.nc)
+        args = [np.ascontiguousarray(a, dtype=np.float64) for a in (Ul, Ur, m)]
+        rc = self.L.orc_sign_bound(self.gp, *[_p(a) for a in args], _p(B))
+        return rc, B
+
+    def sign_test(self, JU, J, jx, jt, k, flat_idx):
+        """Sign test at the interfaces right of the given nodes along k:
+        (rc, jump, WENO jump, bound, Y, s), per node and field."""
+        pts = np.ascontiguousarray(flat_idx, dtype=np.int64)
+        n = len(pts)
+        jump, jw, bound = np.zeros((n, self.nc)), np.zeros((n, self.nc)), np.zeros((n, self.nc))
+        Y = np.zeros((n, self.nc), dtype=np.int32)
+        s = np.zeros(n)
+        rc = self.L.orc_sign_test(self.gp, _p(JU), _p(J), _p(jx), _p(jt), k, n,
+                                  pts.ctypes.data_as(C.POINTER(C.c_long)), _p(jump), _p(jw),
+                                  _p(bound), Y.ctypes.data_as(C.POINTER(C.c_int)), _p(s))
+        return rc, jump, jw, bound, Y.astype(bool), s
 
     def js5(self, q, eps=None):
         eps = self.g.weno_eps if eps is None else eps

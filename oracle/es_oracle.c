@@ -56,6 +56,7 @@ static int valid_grid(const orc_grid *g)
         if (g->bc[k][0] != 0 && !(g->wall[k][1] > g->wall[k][0])) return 0;
     }
     if (g->dim == 2 && g->n[2] != 1) return 0;
+    if (!(g->sign_tol >= 0.0 && g->sign_tol < 1.0)) return 0;
     return 1;
 }
 
@@ -784,13 +785,53 @@ int orc_metrics(const orc_grid *g, const double *x_n, const double *disp,
 /* Readings: interface metrics nbar = (m_i + m_{i+1})/2 for the dissipation; */
 /* W_j = R^T T V(U_j) for j = i-2..i+3 with R, T frozen at the interface;    */
 /* W^+ is MR5 of the mirrored sequence W_{i+3..i-1}; Y_mm = 1 only if        */
-/* [[W_m]]^WENO [[W_m]] > 0 and [[W_m]] is not zero to working precision.    */
+/* [[W_m]]^WENO [[W_m]] > 0 and |[[W_m]]| > sign_tol B_m (sign_tol = 0: the  */
+/* paper's rule as printed).                                                 */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     const orc_grid *g;
     const double *JU, *J, *jxi_x, *jxi_t;
     long P;
 } fields_t;
+
+/* what the sign test saw at one interface (orc_sign_test) */
+typedef struct {
+    double jump[MAXC], jw[MAXC], bound[MAXC], s;
+    int Y[MAXC];
+} sign_info_t;
+
+/* Bound on the size of the terms that form W_c at nodes i and i+1.  With
+ * row magnitudes a_l = |V_l| (species), a_{N+j} = sum_j' |V_{N+j'}| (every
+ * momentum row: an orthogonal T gives |(T V)_{N+j}| <= ||V_mom||_2 <=
+ * ||V_mom||_1) and a_E = |V_E|, each summed over the two nodes,
+ *   B_c = max_l |R_lc| sum_l a_l + sum_{e >= N} |R_ec| a_e
+ *      >= sum_e |R_ec| (|(T V_i)_e| + |(T V_{i+1})_e|).
+ * Forming W_c and the difference W_c(i+1) - W_c(i) rounds each of those
+ * terms, so a jump of a few ulps of B_c is not resolved by the arithmetic. */
+static void sign_bound_of(const orc_grid *g, const double *Vl, const double *Vr,
+                          const double *R, double *B)
+{
+    int N = g->nspec, d = g->dim, nc = N + d + 1;
+    double arow[MAXC];
+    for (int e = 0; e < nc; e++) arow[e] = 0.0;
+    const double *V2[2] = {Vl, Vr};
+    for (int t = 0; t < 2; t++) {
+        const double *V = V2[t];
+        double vm = 0.0;
+        for (int j = 0; j < d; j++) vm += fabs(V[N + j]);
+        for (int l = 0; l < N; l++) arow[l] += fabs(V[l]);
+        for (int a = 0; a < d; a++) arow[N + a] += vm;
+        arow[nc - 1] += fabs(V[nc - 1]);
+    }
+    double ysum = 0.0;
+    for (int l = 0; l < N; l++) ysum += arow[l];
+    for (int c = 0; c < nc; c++) {
+        double rmax = 0.0;
+        for (int l = 0; l < N; l++) if (fabs(R[l * nc + c]) > rmax) rmax = fabs(R[l * nc + c]);
+        B[c] = rmax * ysum;
+        for (int e = N; e < nc; e++) B[c] += fabs(R[e * nc + c]) * arow[e];
+    }
+}
 
 static int node_load(const fields_t *f, long i, int k, double *U, prim_t *q, double *m)
 {
@@ -805,7 +846,8 @@ static int node_load(const fields_t *f, long i, int k, double *U, prim_t *q, dou
     return rc;
 }
 
-static int interface_flux(const fields_t *f, long i, int k, double *F, double *G, double *prod)
+static int interface_flux(const fields_t *f, long i, int k, double *F, double *G, double *prod,
+                          sign_info_t *info)
 {
     const orc_grid *g = f->g;
     int N = g->nspec, d = g->dim, nc = N + d + 1;
@@ -839,18 +881,12 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
     double R[MAXC * MAXC], s, Tv[3][3];
     frame_of(g, &q[2], &q[3], mbar, R, &s, Tv);
 
-    double W[6][MAXC], Wmag[MAXC], arow[MAXC];
-    for (int e = 0; e < nc; e++) arow[e] = 0.0;
+    double W[6][MAXC], Vi[MAXC], Vi1[MAXC], Wmag[MAXC];
     for (int t = 0; t < 6; t++) {
         double V[MAXC], TV[MAXC];
         entropy_vars_of(g, &q[t], V);
-        if (t == 2 || t == 3) {   /* row magnitudes: |V_l|; sum_j |V_{N+j}| >= |(T V)_{N+a}|; |V_E| */
-            double vm = 0.0;
-            for (int j = 0; j < d; j++) vm += fabs(V[N + j]);
-            for (int l = 0; l < N; l++) arow[l] += fabs(V[l]);
-            for (int a = 0; a < d; a++) arow[N + a] += vm;
-            arow[nc - 1] += fabs(V[nc - 1]);
-        }
+        if (t == 2) for (int c = 0; c < nc; c++) Vi[c] = V[c];
+        if (t == 3) for (int c = 0; c < nc; c++) Vi1[c] = V[c];
         for (int c = 0; c < nc; c++) TV[c] = V[c];
         for (int a = 0; a < d; a++) {
             TV[N + a] = 0.0;
@@ -861,17 +897,7 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
             for (int e = 0; e < nc; e++) W[t][c] += R[e * nc + c] * TV[e];   /* R^T */
         }
     }
-    /* bound on the size of the terms that make W_i and W_{i+1}:
-       sum_e |R_ec| |(T V)_e| <= max_l |R_lc| sum_l arow_l (species rows)
-       + sum_e |R_ec| arow_e (momentum and energy rows), both nodes summed */
-    double ysum = 0.0;
-    for (int l = 0; l < N; l++) ysum += arow[l];
-    for (int c = 0; c < nc; c++) {
-        double rmax = 0.0;
-        for (int l = 0; l < N; l++) if (fabs(R[l * nc + c]) > rmax) rmax = fabs(R[l * nc + c]);
-        Wmag[c] = rmax * ysum;
-        for (int e = N; e < nc; e++) Wmag[c] += fabs(R[e * nc + c]) * arow[e];
-    }
+    sign_bound_of(g, Vi, Vi1, R, Wmag);
     double Z[MAXC], pr = 0.0;
     for (int c = 0; c < nc; c++) {
         double qm[5] = {W[0][c], W[1][c], W[2][c], W[3][c], W[4][c]};
@@ -880,17 +906,23 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
         double Wplus = g->reconstruction ? orc_js5(qp, g->weno_eps) : orc_mr5(qp, g->chi, g->weno_eps);
         double JW = Wplus - Wminus;
         double jump = W[3][c] - W[2][c];
-        /* reading of sign(0) at working precision: a jump below 1e-12 of
-           a bound on the size of the terms that form W_i and W_{i+1},
-           max_l |R_lc| sum_l |V_l| plus sum_e |R_ec| a_e over the momentum
-           rows (a_e = sum_j |V_{N+j}|) and the energy row (|V_E|), summed
-           over both nodes, is zero (across a contact the acoustic
-           jumps vanish up to rounding, in an isentropic flow the entropy
-           field's jumps do), so Y_mm = 0 there */
-        int Y = (JW * jump > 0.0) && (fabs(jump) > 1.0e-12 * Wmag[c]);
+        /* sign matrix: Y_mm = 1 iff the WENO jump and the jump agree in
+           sign.  With sign_tol > 0, a jump no larger than sign_tol times
+           the bound on the terms that form it (sign_bound_of) counts as
+           zero, so Y_mm = 0 there: across a contact the acoustic jumps
+           vanish up to rounding, in an isentropic flow the entropy field's
+           do, and the sign of such a jump is decided by rounding order */
+        int Y = (JW * jump > 0.0) && (fabs(jump) > g->sign_tol * Wmag[c]);
         Z[c] = Y ? JW : 0.0;
         if (Y) pr += 0.5 * s * jump * JW;
+        if (info) {
+            info->jump[c] = jump;
+            info->jw[c] = JW;
+            info->bound[c] = Wmag[c];
+            info->Y[c] = Y;
+        }
     }
+    if (info) info->s = s;
     double RZ[MAXC], D[MAXC];
     for (int a = 0; a < nc; a++) {
         RZ[a] = 0.0;
@@ -910,6 +942,49 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
     return ORC_OK;
 }
 
+int orc_sign_bound(const orc_grid *g, const double *Ul, const double *Ur,
+                   const double *m, double *B)
+{
+    if (!valid_grid(g) || !Ul || !Ur || !m || !B) return ORC_EINVAL;
+    prim_t l, r;
+    int a = prim_of(g, Ul, &l), b = prim_of(g, Ur, &r);
+    double R[MAXC * MAXC], s, Tv[3][3], Vl[MAXC], Vr[MAXC];
+    frame_of(g, &l, &r, m, R, &s, Tv);
+    entropy_vars_of(g, &l, Vl);
+    entropy_vars_of(g, &r, Vr);
+    sign_bound_of(g, Vl, Vr, R, B);
+    return a ? a : b;
+}
+
+int orc_sign_test(const orc_grid *g, const double *JU, const double *J,
+                  const double *jxi_x, const double *jxi_t, int k, int npts,
+                  const long *pts, double *jump, double *jw, double *bound,
+                  int *Y, double *s_out)
+{
+    if (!valid_grid(g) || !JU || !J || !jxi_x || k < 0 || k >= g->dim || npts < 0 || !pts ||
+        !jump || !jw || !bound || !Y || !s_out || !g->dissipation)
+        return ORC_EINVAL;
+    fields_t f = {g, JU, J, jxi_x, jxi_t, orc_npoints(g)};
+    int nc = orc_ncomp(g), rc = ORC_OK;
+    for (int p = 0; p < npts; p++) {
+        double F[MAXC], G;
+        sign_info_t info;
+        int r = interface_flux(&f, pts[p], k, F, &G, NULL, &info);
+        if (r) {
+            if (!rc) rc = r;
+            continue;
+        }
+        for (int c = 0; c < nc; c++) {
+            jump[p * nc + c] = info.jump[c];
+            jw[p * nc + c] = info.jw[c];
+            bound[p * nc + c] = info.bound[c];
+            Y[p * nc + c] = info.Y[c];
+        }
+        s_out[p] = info.s;
+    }
+    return rc;
+}
+
 /* eq semi_U, eq semi_J at one node */
 static int node_rhs(const fields_t *f, long i, double *dU, double *dJ)
 {
@@ -920,8 +995,8 @@ static int node_rhs(const fields_t *f, long i, double *dU, double *dJ)
     for (int k = 0; k < g->dim; k++) {
         long st = stride_(g, k);
         double Fp[MAXC], Fm[MAXC], Gp, Gm;
-        int r1 = interface_flux(f, i, k, Fp, &Gp, NULL);
-        int r2 = interface_flux(f, i - st, k, Fm, &Gm, NULL);
+        int r1 = interface_flux(f, i, k, Fp, &Gp, NULL, NULL);
+        int r2 = interface_flux(f, i - st, k, Fm, &Gm, NULL, NULL);
         if (r1) return r1;
         if (r2) return r2;
         for (int c = 0; c < nc; c++) dU[c] -= (Fp[c] - Fm[c]) / g->dxi[k];
@@ -1361,7 +1436,7 @@ double orc_es_production(const orc_grid *g, const double *JU, const double *J,
             for (int i1 = lo_(g, 1); i1 < hi_(g, 1); i1++)
                 for (int i0 = lo_(g, 0); i0 < hi_(g, 0); i0++) {
                     double F[MAXC], G, pr = 0.0;
-                    interface_flux(&f, at(g, i0, i1, i2), k, F, &G, &pr);
+                    interface_flux(&f, at(g, i0, i1, i2), k, F, &G, &pr, NULL);
                     tot -= pr * dv / g->dxi[k];
                 }
     return tot;

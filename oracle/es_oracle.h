@@ -59,6 +59,11 @@ typedef struct {
                        /*    direction is periodic on both faces or neither    */
     double wall[3][2]; /* physical coordinate x_k of each non-periodic face    */
     double inflow[3][2][6]; /* prescribed conserved state U of inflow faces    */
+    double sign_tol;   /* zero tolerance of the sign matrix Y (Section 3.4,   */
+                       /*    after eq HOstable): Y_mm = 1 iff the WENO jump   */
+                       /*    and the jump [[W_m]] agree in sign and           */
+                       /*    |[[W_m]]| > sign_tol * B_m (B_m: orc_sign_bound);*/
+                       /*    0 is the paper's rule as printed; 0 <= tol < 1   */
 } orc_grid;
 
 typedef struct {
@@ -94,6 +99,24 @@ void   orc_rotation(const orc_grid *g, const double *n, double *T);
  * (Ul, Ur) for the averaged metric m = (n_t, n_1..n_d); s = max |eigenvalue| */
 int    orc_interface_frame(const orc_grid *g, const double *Ul, const double *Ur,
                            const double *m, double *R, double *s);
+/* bound B (nc values) on the size of the terms that form W_i and W_{i+1}
+ * (W = R^T T V at the interface of Ul, Ur with averaged metric m): for
+ * field c, B_c = max_l |R_lc| sum_l a_l (species rows) + sum_e |R_ec| a_e
+ * (momentum and energy rows), a_l = |V_l|, a_{N+j} = sum_j' |V_{N+j'}|,
+ * a_E = |V_E|, each summed over both nodes.  Since |(T V)_{N+j}| <=
+ * sum_j' |V_{N+j'}| for an orthogonal T, B_c >= sum_e |R_ec| (|(T V_i)_e| +
+ * |(T V_{i+1})_e|), the magnitude scale of the rounding of [[W_c]]. */
+int    orc_sign_bound(const orc_grid *g, const double *Ul, const double *Ur,
+                      const double *m, double *B);
+/* the sign test at the interfaces between node pts[p] and its right
+ * neighbour along direction k (p = 0..npts-1): per field c (index p*nc + c)
+ * the jump [[W_c]], the WENO jump [[W_c]]^WENO, the bound B_c and Y_cc
+ * (1 or 0) under g->sign_tol; s_out (npts values) the interface speed s.
+ * Returns 0, or the first nonzero code of a node's primitives. */
+int    orc_sign_test(const orc_grid *g, const double *JU, const double *J,
+                     const double *jxi_x, const double *jxi_t, int k, int npts,
+                     const long *pts, double *jump, double *jw, double *bound,
+                     int *Y, double *s_out);
 double orc_mr5(const double *q, const double *chi, double eps);
 /* classical fifth-order WENO (Jiang & Shu 1996) at the right face of q[2]
  * from q[0..4], linear weights (1/10, 6/10, 3/10), alpha_k = d_k/(eps+beta_k)^2 */

@@ -96,6 +96,8 @@ int check_grid(const es_grid* g)
         if (!(g->gamma[l] > 1.0) || !(g->cv[l] > 0.0) || !(g->pinf[l] >= 0.0)) return ES_EINVAL;
     if (!(g->chi[0] > 0.0) || !(g->chi[1] > 0.0) || !(g->chi[2] > 0.0) || !(g->weno_eps > 0.0))
         return ES_EINVAL;
+    if (!(g->sign_tol >= 0.0 && g->sign_tol < 1.0) || !(g->sign_tol32 >= 0.0 && g->sign_tol32 < 1.0))
+        return ES_EINVAL;
     long P = 1;
     for (int k = 0; k < g->dim; k++) P *= (long)(g->n[k] + 2 * g->ng);
     if (P * 9 > (1L << 31) - 1) return ES_EUNSUPPORTED;   // component offsets stay below 2^31
@@ -126,6 +128,8 @@ void build_params(const es_grid* g, Phys& ph, Geo& geo)
     for (int m = 0; m < 3; m++) ph.alpha[m] = A[g->w - 1][m];
     for (int m = 0; m < 3; m++) ph.chi[m] = g->chi[m];
     ph.eps = g->weno_eps;
+    ph.stol64 = g->sign_tol;
+    ph.stol32 = g->sign_tol32;
     ph.r21 = g->nspec == 2 ? ph.Rg[1] / ph.Rg[0] : 1.0;
     ph.sr21 = sqrt(ph.r21);
     ph.isr21 = 1.0 / ph.sr21;
@@ -503,7 +507,8 @@ namespace {
 bool same_scheme(const es_grid& a, const es_grid& b)
 {
     if (a.dim != b.dim || a.nspec != b.nspec || a.ng != b.ng || a.w != b.w || a.precision != b.precision ||
-        a.dissipation != b.dissipation || a.weno_eps != b.weno_eps || a.reconstruction != b.reconstruction)
+        a.dissipation != b.dissipation || a.weno_eps != b.weno_eps || a.reconstruction != b.reconstruction ||
+        a.sign_tol != b.sign_tol || a.sign_tol32 != b.sign_tol32)
         return false;
     for (int l = 0; l < a.nspec; l++)
         if (a.gamma[l] != b.gamma[l] || a.cv[l] != b.cv[l] || a.pinf[l] != b.pinf[l]) return false;

@@ -21,6 +21,7 @@ struct Phys {
     double chi[3], eps;       // MR-WENO linear weights and epsilon
     double r21;               // R_2 / R_1 (N = 2)
     double sr21, isr21;       // sqrt(R_2 / R_1) and its reciprocal
+    double stol64, stol32;    // zero tolerances of the sign matrix (FP64, FP32 arithmetic)
 };
 
 struct Geo {

@@ -352,9 +352,9 @@ __device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<
         R F[NC];
         if (ph.dissipation) {
             // zero tolerance of the sign test, relative to the size of the
-            // terms of W: ~4500 u in FP64; in FP32, where W carries about
-            // 3 u of that size in rounding, 1e-6 (~17 u)
-            const Weno<R> Wc = make_weno<R>(ph.chi, ph.eps, sizeof(R) == 8 ? 1e-12 : 1e-6);
+            // terms of W, in the precision of the arithmetic (0: the sign
+            // test as printed)
+            const Weno<R> Wc = make_weno<R>(ph.chi, ph.eps, sizeof(R) == 8 ? ph.stol64 : ph.stol32);
             int st[6];
 #pragma unroll
             for (int q = 0; q < 6; q++) st[q] = lidx(fl - 2 + q, fc);

@@ -38,6 +38,7 @@ class EsGrid(C.Structure):
         ("chi", C.c_double * 3), ("weno_eps", C.c_double), ("dissipation", C.c_int),
         ("precision", C.c_int), ("reconstruction", C.c_int), ("bc", (C.c_int * 2) * 3),
         ("wall", (C.c_double * 2) * 3), ("inflow", ((C.c_double * 6) * 2) * 3),
+        ("sign_tol", C.c_double), ("sign_tol32", C.c_double),
     ]
 
 
@@ -141,6 +142,9 @@ def make_grid(spec, precision=ES_FP64) -> EsGrid:
     for (k, side), U in spec.get("inflow", {}).items():
         for c, u in enumerate(U):
             g.inflow[k][side][c] = u
+    # zero tolerances of the sign matrix (0: the paper's rule as printed)
+    g.sign_tol = spec.get("sign_tol", 1e-12)
+    g.sign_tol32 = spec.get("sign_tol32", 1e-6)
     return g
 
 

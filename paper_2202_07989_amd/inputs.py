@@ -22,6 +22,11 @@ import numpy as np
 CHI_DEFAULT = (1.0 / 111.0, 10.0 / 111.0, 100.0 / 111.0)   # Appendix A default
 CHI_SHOCK = (0.95, 0.045, 0.005)                            # Ex. 5.3 / 5.10 weights
 WATER_AIR = dict(gamma=(4.4, 1.4), cv=(1.0, 1.0), pinf=(6.0e8, 0.0))
+# zero tolerances of the sign matrix, relative to the bound on the terms that
+# form a jump of the scaled entropy variables: FP64 arithmetic, and the FP32
+# arithmetic of the mixed-precision form (0 is the paper's rule as printed)
+SIGN_TOL_FP64 = 1.0e-12
+SIGN_TOL_FP32 = 1.0e-6
 
 
 # --------------------------------------------------------------------------
@@ -32,19 +37,22 @@ BC_PERIODIC, BC_REFLECT, BC_OUTFLOW, BC_INFLOW = 0, 1, 2, 3
 
 def make_spec(dim, nspec, n, *, box=None, gamma=(1.4,), cv=(1.0,), pinf=(0.0,),
               chi=CHI_DEFAULT, w=3, ng=3, dissipation=1, weno_eps=1e-10, reconstruction=0,
-              bc=None, wall=None, inflow=None):
+              bc=None, wall=None, inflow=None, sign_tol=SIGN_TOL_FP64, sign_tol32=SIGN_TOL_FP32):
     """Workload spec.  Periodic in every direction unless bc gives per-face
     conditions [(low, high), ...] (BC_*); wall then holds the physical
     coordinates [(x_low, x_high), ...] of the faces (the computational box is
     [0, x_high - x_low]) and inflow maps (direction, side) to the conserved
-    state U prescribed on an inflow face."""
+    state U prescribed on an inflow face.  sign_tol / sign_tol32 are the
+    zero tolerances of the sign matrix in FP64 and in the FP32 arithmetic of
+    the mixed-precision form."""
     n = tuple(n) + (1,) * (3 - len(n))
     box = box or (1.0,) * dim
     box = tuple(box) + (1.0,) * (3 - len(box))
     dxi = tuple(box[k] / n[k] if k < dim else 1.0 for k in range(3))
     sp = dict(dim=dim, nspec=nspec, n=n, ng=ng, dxi=dxi, len=box, w=w,
               gamma=tuple(gamma), cv=tuple(cv), pinf=tuple(pinf), chi=tuple(chi),
-              weno_eps=weno_eps, dissipation=dissipation, reconstruction=reconstruction)
+              weno_eps=weno_eps, dissipation=dissipation, reconstruction=reconstruction,
+              sign_tol=sign_tol, sign_tol32=sign_tol32)
     if bc is not None:
         sp["bc"] = [tuple(b) for b in bc]
         sp["wall"] = [tuple(wl) for wl in (wall or [(0.0, box[k]) for k in range(dim)])]

@@ -45,7 +45,8 @@ def test_invalid_arguments_rejected_before_any_launch(lib):
     for bad, code in (("dim", es.ES_EUNSUPPORTED), ("nspec", es.ES_EUNSUPPORTED), ("w", es.ES_EUNSUPPORTED),
                       ("ng", es.ES_EUNSUPPORTED), ("dxi", es.ES_EINVAL), ("gamma", es.ES_EINVAL),
                       ("chi", es.ES_EINVAL), ("precision", es.ES_EUNSUPPORTED),
-                      ("reconstruction", es.ES_EUNSUPPORTED), ("js-mixed", es.ES_EUNSUPPORTED)):
+                      ("reconstruction", es.ES_EUNSUPPORTED), ("js-mixed", es.ES_EUNSUPPORTED),
+                      ("sign_tol", es.ES_EINVAL), ("sign_tol32", es.ES_EINVAL), ("sign_tol-nan", es.ES_EINVAL)):
         g = es.make_grid(sp)
         if bad == "dim":
             g.dim = 4
@@ -67,6 +68,12 @@ def test_invalid_arguments_rejected_before_any_launch(lib):
             g.reconstruction = 2
         elif bad == "js-mixed":
             g.reconstruction, g.precision = es.ES_WENO_JS, es.ES_MIXED
+        elif bad == "sign_tol":
+            g.sign_tol = -1e-12
+        elif bad == "sign_tol32":
+            g.sign_tol32 = 1.0
+        elif bad == "sign_tol-nan":
+            g.sign_tol = float("nan")
         assert es.lib.es_create(C.byref(g), C.byref(h)) == code, bad
     assert es.lib.es_create(None, C.byref(h)) == es.ES_EINVAL
     null = None

@@ -1,0 +1,128 @@
+"""The GPU path with the sign matrix exactly as the paper prints it
+(Section 3.4, after eq HOstable: Y_mm = 1 iff [[W_m]]^WENO [[W_m]] > 0),
+i.e. es_grid.sign_tol = 0, against the oracle with the same setting.
+
+Where every interface's jump and WENO jump lie far above the rounding scale
+B of the terms that form them (|.| > 1e-9 B, the oracle's own sign-test
+data), no sign is decided by rounding and the literal rule is well
+conditioned: the right-hand sides must then agree to the FP64 bar on every
+node.  The shock-bubble data have contacts whose acoustic jumps vanish in
+exact arithmetic; there the nodes next to such an interface are left out and
+every other node must agree to the bar."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_07989_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_2202_07989_amd import es  # noqa: E402
+from gpu_util import TOL_FP64, dev, host, parity, rhs_scale, say  # noqa: E402
+
+from cases import CASES, prepared  # noqa: E402
+
+WELL = 1e-9   # a jump or WENO jump above WELL * B has a sign rounding cannot flip
+
+
+def ill_conditioned_nodes(o, sp, JU, J, jx, jt):
+    """Mask (interior shape) of nodes next to an interface whose sign test is
+    decided near the rounding scale, and the smallest margin seen."""
+    d, ng = sp["dim"], sp["ng"]
+    Iin = I.interior(sp)
+    shape = J.shape[1:]
+    idx = np.arange(o.P).reshape(shape)
+    bad = np.zeros(shape, dtype=bool)
+    margin = np.inf
+    for k in range(d):
+        ax = 2 - k
+        # interfaces from the left face of the first interior node to the right face of the last
+        sl = list(Iin[1:])
+        s = sl[ax]
+        sl[ax] = slice(s.start - 1, s.stop)
+        pts = idx[tuple(sl)].ravel()
+        rc, jump, jw, bound, Y, s_ = o.sign_test(JU, J, jx, jt, k, pts)
+        assert rc == 0
+        r = np.minimum(np.abs(jump), np.abs(jw)) / bound
+        margin = min(margin, float(r.min()))
+        ill = (r <= WELL).any(axis=1).reshape(idx[tuple(sl)].shape)
+        # an interface between nodes i and i+1 feeds both
+        left = np.zeros(shape, dtype=bool)
+        left[tuple(sl)] = ill
+        right = np.roll(left, 1, axis=ax)
+        bad |= left | right
+    return bad[Iin[1:]], margin
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_rhs_parity_literal_sign_matrix(name):
+    say(f"[literal sign matrix] {name}")
+    sp, _, JU, J, x, disp, jx, jt = prepared(name, 1)
+    sp = dict(sp, sign_tol=0.0)
+    o = oracle.Oracle(sp)
+    bad, margin = ill_conditioned_nodes(o, sp, JU, J, jx, jt)
+    random_case = "bubble" not in name
+    if random_case:
+        # the literal rule is well conditioned on noisy random states
+        assert margin > WELL, (name, margin)
+        assert not bad.any()
+    else:
+        assert bad.mean() < 0.5, (name, bad.mean())
+    say(f"    min |jump|/B {margin:.2e}; nodes next to rounding-decided interfaces: {int(bad.sum())}")
+    rc, dU, dJ = o.rhs(JU, J, jx, jt)
+    assert rc == 0
+    _, lam, _ = o.max_wavespeed(JU, J, jx, 1.0)
+    ctx = es.Context(sp)
+    gU, gJ = torch.zeros_like(dev(JU)), torch.zeros_like(dev(J))
+    ctx.es_rhs(dev(JU), dev(J), dev(jx), dev(jt), gU, gJ)
+    hU, hJ = host(gU), host(gJ)
+    Iin = I.interior(sp)
+    sU, sJ = rhs_scale(JU, J, lam, Iin, sp)
+    keep = ~bad
+    worst = 0.0
+    for c in range(o.nc):
+        e = parity(hU[c][Iin[1:]][keep], dU[c][Iin[1:]][keep], sU[c])
+        worst = max(worst, e)
+        assert e <= TOL_FP64, (name, c, e)
+    assert parity(hJ[Iin][0][keep], dJ[Iin][0][keep], sJ) <= TOL_FP64
+    assert ctx.es_status()[0] == es.ES_OK
+    say(f"    worst component parity {worst:.2e} on {int(keep.sum())} nodes")
+
+
+def test_literal_and_default_differ_only_at_rounding_decided_interfaces():
+    """On the 2D shock-bubble case, the GPU right-hand sides with the sign
+    test as printed and with its zero tolerance differ only at nodes next to
+    an interface whose jump the tolerance zeroes."""
+    say("[literal vs default on the GPU] 2d-n2-bubble")
+    sp, _, JU, J, x, disp, jx, jt = prepared("2d-n2-bubble", 1)
+    out = {}
+    for tol in (0.0, I.SIGN_TOL_FP64):
+        s = dict(sp, sign_tol=tol)
+        ctx = es.Context(s)
+        gU, gJ = torch.zeros_like(dev(JU)), torch.zeros_like(dev(J))
+        ctx.es_rhs(dev(JU), dev(J), dev(jx), dev(jt), gU, gJ)
+        out[tol] = host(gU)
+    o = oracle.Oracle(dict(sp, sign_tol=I.SIGN_TOL_FP64))
+    Iin = I.interior(sp)
+    d = sp["dim"]
+    shape = J.shape[1:]
+    idx = np.arange(o.P).reshape(shape)
+    near = np.zeros(shape, dtype=bool)
+    for k in range(d):
+        ax = 2 - k
+        sl = list(Iin[1:])
+        s = sl[ax]
+        sl[ax] = slice(s.start - 1, s.stop)
+        pts = idx[tuple(sl)].ravel()
+        rc, jump, jw, bound, Y, s_ = o.sign_test(JU, J, jx, jt, k, pts)
+        zeroed = ((jw * jump > 0) & (np.abs(jump) <= I.SIGN_TOL_FP64 * bound)).any(axis=1)
+        left = np.zeros(shape, dtype=bool)
+        left[tuple(sl)] = zeroed.reshape(idx[tuple(sl)].shape)
+        near |= left | np.roll(left, 1, axis=ax)
+    diff = (out[0.0] != out[I.SIGN_TOL_FP64]).any(axis=0)
+    assert not np.any(diff[Iin[1:]] & ~near[Iin[1:]])
+    say(f"    nodes that differ: {int(diff[Iin[1:]].sum())}, next to zeroed interfaces: {int(near[Iin[1:]].sum())}")

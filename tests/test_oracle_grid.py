@@ -192,15 +192,19 @@ def test_ec_scheme_conserves_entropy(dim, nspec, pinf):
     assert abs(rate) < 1e-12 * entropy_scale(o, sp, JU, J, dJU, dJ)
 
 
+@pytest.mark.parametrize("sign_tol", [0.0, I.SIGN_TOL_FP64])
 @pytest.mark.parametrize("recon", [0, 1])
 @pytest.mark.parametrize("dim,nspec,pinf", [(2, 1, (0.0,)), (2, 2, (6e8, 0.0)), (3, 2, (100.0, 0.0))])
-def test_es_scheme_entropy_production(dim, nspec, pinf, recon):
+def test_es_scheme_entropy_production(dim, nspec, pinf, recon, sign_tol):
     """The ES flux adds -s/2 sum_m Y_mm [[W_m]][[W_m]]^WENO <= 0 per interface
     (eq HOstable with the sign matrix), nothing else; with either
-    reconstruction (multi-resolution, or the classical WENO5 of MM-WENOJS)."""
+    reconstruction (multi-resolution, or the classical WENO5 of MM-WENOJS)
+    and with the sign test as printed (sign_tol = 0) or with its zero
+    tolerance."""
     n = (14, 12) if dim == 2 else (8, 9, 7)
     kw = dict(gamma=(4.4, 1.4)[:nspec] if nspec == 2 else (1.4,), cv=(1.0, 2.0)[:nspec],
-              pinf=pinf, chi=I.CHI_SHOCK, reconstruction=recon, weno_eps=1e-6 if recon else 1e-10)
+              pinf=pinf, chi=I.CHI_SHOCK, reconstruction=recon, weno_eps=1e-6 if recon else 1e-10,
+              sign_tol=sign_tol)
     sp_es = I.make_spec(dim, nspec, n, dissipation=1, **kw)
     sp_ec = I.make_spec(dim, nspec, n, dissipation=0, **kw)
     o_es, o_ec = oracle.Oracle(sp_es), oracle.Oracle(sp_ec)
