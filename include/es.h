@@ -144,8 +144,14 @@ enum { ES_MONITOR_GRAD2 = 0, ES_MONITOR_GRAD_LAP = 1 };
 
 typedef struct es_ctx es_ctx;
 
-/* Create a context for one grid (validates g, allocates reduction scratch and
- * the status word on the current device).  Owns only its workspace. */
+/* Create a context for one grid on the current device: validates g, then
+ * allocates and initialises the whole workspace of the context (status word,
+ * reduction scratch, the metric, mesh and stage buffers of es_step and the
+ * kept-metrics copy): 67 P doubles in 3D with two species (9.6 GB at
+ * 256^3).  This is the only call that allocates or synchronises the
+ * device; every other call only launches work on its stream, so it may be
+ * captured in a graph from its first use.  Owns only its workspace;
+ * ES_EHIP when an allocation fails. */
 int es_create(const es_grid *g, es_ctx **out);
 int es_destroy(es_ctx *c);
 
@@ -239,9 +245,8 @@ int es_entropy_rate(es_ctx *c, const double *JU, const double *J,
  * move_mesh = 0.  The context keeps the metrics of x_{n+1} (the c = 1 stage
  * mesh, whose ghost layers the face rules give) with a copy of that mesh,
  * and the next call reuses them when its x_n equals the copy value for value
- * (compared on the device), so x may be changed between calls; the first
- * call allocates this copy (d P doubles) and a second metric buffer (d^2 P).
- * Calls on one context must not overlap. */
+ * (compared on the device), so x may be changed between calls.  Calls on
+ * one context must not overlap. */
 int es_step(es_ctx *c, const es_monitor *m, double cfl, double dt_fixed,
             int move_mesh, double *JU, double *J, double *x, double *dt_dev,
             double *dtau_dev, void *stream);

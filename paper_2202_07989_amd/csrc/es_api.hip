@@ -18,14 +18,13 @@ struct es_ctx {
     Geo geo;
     InflowStates inflow;
     int device;
+    // every buffer below is allocated and initialised by es_create, so no
+    // compute call allocates, frees or synchronises the device
     unsigned* status = nullptr;   // device status word
     double* scal = nullptr;       // 16 device scalars: [0] lambda [1] dt [2..] scratch
     double* part = nullptr;       // 4 x 2048 reduction partials
-    // lazily sized workspace
     double* G = nullptr;          // 3D metric pass-1 buffer (9 P)
     MeshWork mesh{};
-    bool mesh_ready = false;
-    int mesh_nsig = 0;
     double *bufA = nullptr, *bufB = nullptr;
     double *jxx = nullptr, *jxt = nullptr, *disp = nullptr;
     // es_step: the metrics in jxx are those of the mesh mx (ghost layers
@@ -158,17 +157,15 @@ int dalloc(T** p, size_t count)
     return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) == hipSuccess ? ES_OK : ES_EHIP;
 }
 
-int ensure_metric_ws(es_ctx* c)
+// the whole workspace of a context, allocated once by es_create and
+// initialised there (Theta's ghost layers read as 1 before the first fill,
+// and the kept mesh holds NaN, which no mesh equals)
+int alloc_workspace(es_ctx* c)
 {
-    if (c->geo.dim == 3) return dalloc(&c->G, 9 * (size_t)c->geo.P);
-    return ES_OK;
-}
-
-int ensure_mesh_ws(es_ctx* c, int nsig)
-{
-    const size_t P = c->geo.P, d = c->geo.dim;
-    if (c->mesh_ready && nsig <= c->mesh_nsig) return ES_OK;
-    int rc = dalloc(&c->mesh.grad, MON_CH * P);
+    const size_t P = c->geo.P, d = c->geo.dim, nc = c->ph.nc;
+    int rc = ES_OK;
+    if (c->geo.dim == 3) rc = dalloc(&c->G, 9 * P);
+    if (!rc) rc = dalloc(&c->mesh.grad, MON_CH * P);
     if (!rc) rc = dalloc(&c->mesh.th0, P);
     if (!rc) rc = dalloc(&c->mesh.th1, P);
     if (!rc) rc = dalloc(&c->mesh.xa, d * P);
@@ -176,38 +173,19 @@ int ensure_mesh_ws(es_ctx* c, int nsig)
     if (!rc) rc = dalloc(&c->mesh.phi, P);
     if (!rc) rc = dalloc(&c->mesh.part, 8 * 2048);
     if (!rc) rc = dalloc(&c->mesh.scal, 8);
-    if (rc) return rc;
-    // theta ghosts are read by the filter before the first fill
-    if (fill_value(c->mesh.th0, P, 1.0, 0) != hipSuccess) return ES_EHIP;
-    if (fill_value(c->mesh.th1, P, 1.0, 0) != hipSuccess) return ES_EHIP;
-    c->mesh_ready = true;
-    c->mesh_nsig = MON_CH;
-    return hipDeviceSynchronize() == hipSuccess ? ES_OK : ES_EHIP;
-}
-
-int ensure_step_ws(es_ctx* c)
-{
-    const size_t P = c->geo.P, d = c->geo.dim, nc = c->ph.nc;
-    int rc = dalloc(&c->bufA, (nc + 1) * P);
+    if (!rc) rc = dalloc(&c->bufA, (nc + 1) * P);
     if (!rc) rc = dalloc(&c->bufB, (nc + 1) * P);
     if (!rc) rc = dalloc(&c->jxx, d * d * P);
     if (!rc) rc = dalloc(&c->jxt, d * P);
     if (!rc) rc = dalloc(&c->disp, d * P);
     if (!rc) rc = dalloc(&c->jxx2, d * d * P);
+    if (!rc) rc = dalloc(&c->mx, d * P);
     if (!rc) rc = dalloc(&c->reuse, 1);
-    if (!rc) rc = ensure_metric_ws(c);
-    if (!rc && !c->mx) {
-        // kept only once it holds NaN, which no mesh equals
-        double* mx = nullptr;
-        rc = dalloc(&mx, d * P);
-        if (!rc && (fill_value(mx, d * P, std::numeric_limits<double>::quiet_NaN(), 0) != hipSuccess ||
-                    hipDeviceSynchronize() != hipSuccess)) {
-            (void)hipFree(mx);
-            rc = ES_EHIP;
-        }
-        if (!rc) c->mx = mx;
-    }
-    return rc;
+    if (rc) return rc;
+    if (fill_value(c->mesh.th0, P, 1.0, 0) != hipSuccess) return ES_EHIP;
+    if (fill_value(c->mesh.th1, P, 1.0, 0) != hipSuccess) return ES_EHIP;
+    if (fill_value(c->mx, d * P, std::numeric_limits<double>::quiet_NaN(), 0) != hipSuccess) return ES_EHIP;
+    return hipDeviceSynchronize() == hipSuccess ? ES_OK : ES_EHIP;
 }
 
 MonitorP monitor_params(const es_monitor* m)
@@ -269,6 +247,7 @@ int es_create(const es_grid* g, es_ctx** out)
         const double one = 1.0;   // scal[5]: the unit divisor of the step's first metric pass
         if (hipMemcpy(c->scal + 5, &one, sizeof(double), hipMemcpyHostToDevice) != hipSuccess) rc = ES_EHIP;
     }
+    if (!rc) rc = alloc_workspace(c);
     if (rc) { es_destroy(c); return rc; }
     *out = c;
     return ES_OK;
@@ -314,10 +293,6 @@ int es_metrics(es_ctx* c, const double* x_n, const double* disp, double c_s, con
     if (!vcl_only && !x_n) return ES_EINVAL;
     if (vcl_only && !jxi_t) return ES_EINVAL;
     if (!std::isfinite(c_s)) return ES_EINVAL;
-    if (!vcl_only) {
-        int rc = ensure_metric_ws(c);
-        if (rc) return rc;
-    }
     return hip_rc(metrics(c->ph, c->geo, x_n, disp, c_s, dt_dev, jxi_x, jxi_t, vcl_only, c->G, S(stream)));
 }
 
@@ -368,9 +343,7 @@ int mesh_redistribute(es_ctx* c, const es_monitor* m, const double* JU, const do
                       double* disp, double* dtau_dev, double* resid_dev, void* stream)
 {
     if (!c || !JU || !J || !x_n || !disp) return ES_EINVAL;
-    int rc = check_monitor(m);
-    if (rc) return rc;
-    rc = ensure_mesh_ws(c, m->nsig);
+    const int rc = check_monitor(m);
     if (rc) return rc;
     MonitorP mo = monitor_params(m);
     return hip_rc(es::mesh_redistribute(c->ph, c->geo, mo, JU, J, x_n, disp, c->mesh, dtau_dev, resid_dev,
@@ -396,13 +369,9 @@ int es_step(es_ctx* c, const es_monitor* m, double cfl, double dt_fixed, int mov
     if (!c || !JU || !J || !x) return ES_EINVAL;
     if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return ES_EINVAL;
     if (move_mesh) {
-        int rc = check_monitor(m);
-        if (rc) return rc;
-        rc = ensure_mesh_ws(c, m->nsig);
+        const int rc = check_monitor(m);
         if (rc) return rc;
     }
-    int rc = ensure_step_ws(c);
-    if (rc) return rc;
     hipStream_t s = S(stream);
     const Geo& g = c->geo;
     const Phys& ph = c->ph;

@@ -24,6 +24,12 @@ def case_spec(name, dissipation=1):
     elif name == "3d-n2-bubble":
         sp = I.make_spec(3, 2, (21, 18, 17), chi=I.CHI_SHOCK, **WATER)
         init = lambda s: I.init_shock_bubble(s)
+    elif name == "2d-n2-random":
+        sp = I.make_spec(2, 2, (31, 22), chi=I.CHI_SHOCK, **WATER)
+        init = lambda s: I.init_random(s, seed=15, noise=0.4, p_range=(1e5, 1e9))
+    elif name == "3d-n2-water":
+        sp = I.make_spec(3, 2, (17, 16, 19), chi=I.CHI_SHOCK, **WATER)
+        init = lambda s: I.init_random(s, seed=16, noise=0.4, p_range=(1e5, 1e9))
     elif name == "3d-n2-random":
         sp = I.make_spec(3, 2, (17, 19, 18), gamma=(4.4, 1.4), cv=(1.0, 2.0), pinf=(100.0, 0.0),
                          chi=I.CHI_SHOCK)
@@ -35,6 +41,8 @@ def case_spec(name, dissipation=1):
 
 
 CASES = ["2d-n1", "2d-n1-stiff", "2d-n2-bubble", "3d-n1", "3d-n2-bubble", "3d-n2-random"]
+# noisy random states, one and two species, up to the water stiffness
+RANDOM_CASES = ["2d-n1", "2d-n1-stiff", "2d-n2-random", "3d-n1", "3d-n2-random", "3d-n2-water"]
 
 
 def prepared(name, dissipation=1, moving=True):

@@ -2,13 +2,15 @@
 (Section 3.4, after eq HOstable: Y_mm = 1 iff [[W_m]]^WENO [[W_m]] > 0),
 i.e. es_grid.sign_tol = 0, against the oracle with the same setting.
 
-Where every interface's jump and WENO jump lie far above the rounding scale
-B of the terms that form them (|.| > 1e-9 B, the oracle's own sign-test
-data), no sign is decided by rounding and the literal rule is well
-conditioned: the right-hand sides must then agree to the FP64 bar on every
-node.  The shock-bubble data have contacts whose acoustic jumps vanish in
-exact arithmetic; there the nodes next to such an interface are left out and
-every other node must agree to the bar."""
+On noisy random states (one and two species, up to the water stiffness
+p_inf = 6e8) every interface's jump and WENO jump lie far above the
+rounding scale B of the terms that form them (> 1e-9 B, from the oracle's
+own sign-test data; rounding moves a jump by at most ~16 u B), so no sign is
+decided by rounding and the literal rule is well conditioned: the
+right-hand sides must agree to the FP64 bar at every node.  On the
+shock-bubble data, whose contacts leave acoustic jumps at rounding level,
+the GPU results with and without the tolerance differ only next to the
+interfaces the tolerance zeroes."""
 import numpy as np
 import pytest
 
@@ -24,7 +26,7 @@ if not torch.cuda.is_available():
 from paper_2202_07989_amd import es  # noqa: E402
 from gpu_util import TOL_FP64, dev, host, parity, rhs_scale, say  # noqa: E402
 
-from cases import CASES, prepared  # noqa: E402
+from cases import RANDOM_CASES, prepared  # noqa: E402
 
 WELL = 1e-9   # a jump or WENO jump above WELL * B has a sign rounding cannot flip
 
@@ -58,21 +60,17 @@ def ill_conditioned_nodes(o, sp, JU, J, jx, jt):
     return bad[Iin[1:]], margin
 
 
-@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("name", RANDOM_CASES)
 def test_rhs_parity_literal_sign_matrix(name):
     say(f"[literal sign matrix] {name}")
     sp, _, JU, J, x, disp, jx, jt = prepared(name, 1)
     sp = dict(sp, sign_tol=0.0)
     o = oracle.Oracle(sp)
     bad, margin = ill_conditioned_nodes(o, sp, JU, J, jx, jt)
-    random_case = "bubble" not in name
-    if random_case:
-        # the literal rule is well conditioned on noisy random states
-        assert margin > WELL, (name, margin)
-        assert not bad.any()
-    else:
-        assert bad.mean() < 0.5, (name, bad.mean())
-    say(f"    min |jump|/B {margin:.2e}; nodes next to rounding-decided interfaces: {int(bad.sum())}")
+    # the literal rule is well conditioned on noisy random states
+    assert margin > WELL, (name, margin)
+    assert not bad.any()
+    say(f"    min over interfaces of min(|jump|, |WENO jump|)/B: {margin:.2e}")
     rc, dU, dJ = o.rhs(JU, J, jx, jt)
     assert rc == 0
     _, lam, _ = o.max_wavespeed(JU, J, jx, 1.0)
@@ -82,21 +80,21 @@ def test_rhs_parity_literal_sign_matrix(name):
     hU, hJ = host(gU), host(gJ)
     Iin = I.interior(sp)
     sU, sJ = rhs_scale(JU, J, lam, Iin, sp)
-    keep = ~bad
     worst = 0.0
     for c in range(o.nc):
-        e = parity(hU[c][Iin[1:]][keep], dU[c][Iin[1:]][keep], sU[c])
+        e = parity(hU[c][Iin[1:]], dU[c][Iin[1:]], sU[c])
         worst = max(worst, e)
         assert e <= TOL_FP64, (name, c, e)
-    assert parity(hJ[Iin][0][keep], dJ[Iin][0][keep], sJ) <= TOL_FP64
+    assert parity(hJ[Iin], dJ[Iin], sJ) <= TOL_FP64
     assert ctx.es_status()[0] == es.ES_OK
-    say(f"    worst component parity {worst:.2e} on {int(keep.sum())} nodes")
+    say(f"    worst component parity {worst:.2e}")
 
 
 def test_literal_and_default_differ_only_at_rounding_decided_interfaces():
     """On the 2D shock-bubble case, the GPU right-hand sides with the sign
     test as printed and with its zero tolerance differ only at nodes next to
-    an interface whose jump the tolerance zeroes."""
+    an interface whose jump lies inside the tolerance band (|[[W]]| <=
+    sign_tol B by the oracle's numbers)."""
     say("[literal vs default on the GPU] 2d-n2-bubble")
     sp, _, JU, J, x, disp, jx, jt = prepared("2d-n2-bubble", 1)
     out = {}
@@ -119,7 +117,10 @@ def test_literal_and_default_differ_only_at_rounding_decided_interfaces():
         sl[ax] = slice(s.start - 1, s.stop)
         pts = idx[tuple(sl)].ravel()
         rc, jump, jw, bound, Y, s_ = o.sign_test(JU, J, jx, jt, k, pts)
-        zeroed = ((jw * jump > 0) & (np.abs(jump) <= I.SIGN_TOL_FP64 * bound)).any(axis=1)
+        # jumps inside the tolerance band: the tolerance zeroes them, and
+        # where the oracle's jump is exactly 0 the GPU's may be a rounding
+        # residue that the literal rule lets through
+        zeroed = (np.abs(jump) <= I.SIGN_TOL_FP64 * bound).any(axis=1)
         left = np.zeros(shape, dtype=bool)
         left[tuple(sl)] = zeroed.reshape(idx[tuple(sl)].shape)
         near |= left | np.roll(left, 1, axis=ax)
