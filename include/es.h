@@ -216,6 +216,22 @@ int max_wavespeed(es_ctx *c, const double *JU, const double *J,
                   const double *jxi_x, double cfl, double *lambda_dev,
                   double *dt_dev, void *stream);
 
+/* max_wavespeed for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same reduction and result, with no context.  g is validated as by
+ * es_create (same error codes) but nothing is allocated: the per-block
+ * maxima, lambda, dt and (when status_dev is NULL) the status bits go to a
+ * static device array of 2056 doubles (16 KiB) that the library holds on each
+ * device it runs on until the process ends.  Any grid es_create accepts
+ * fits (at most 2048 partial maxima; ES_EUNSUPPORTED otherwise, and on a
+ * device index >= 64).  lambda_dev / dt_dev may be NULL; status_dev, when
+ * given, gets ES_ST_NONPHYS or-ed in for a non-physical node.  Calls on one
+ * device share that array: calls that overlap on one device (two streams,
+ * two host threads) race and must be serialised by the caller. */
+int max_wavespeed_noalloc(const es_grid *g, const double *JU, const double *J,
+                          const double *jxi_x, double cfl, double *lambda_dev,
+                          double *dt_dev, unsigned *status_dev, void *stream);
+
 /* Section 4: monitor eq monitor from sigma = JU/J components, n_smooth
  * passes of the low-pass filter, n_sweeps Jacobi iterations of the mesh
  * equations, movement limiter Delta_tau and disp = Delta_tau (x^[mu] - x_n).

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 #include <limits>
+#include <mutex>
 #include <vector>
 
 #include "../../include/es.h"
@@ -732,3 +733,65 @@ int es_batch_status(es_batch* b, void* stream, unsigned* flags, int reset)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// max_wavespeed_noalloc: the CFL reduction for callers that cannot allocate.
+// Its scratch (per-block maxima, lambda and dt, a status word) is a static
+// device array; host code reaches it only through the address that
+// hipGetSymbolAddress returns on each device (the array's name is a host-side
+// stand-in, not a device address).
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int NOALLOC_PARTS = 2048;                  // per-block maxima
+constexpr int NOALLOC_DOUBLES = NOALLOC_PARTS + 8;   // + lambda, dt, status word
+constexpr int NOALLOC_MAX_DEVICES = 64;
+}  // namespace
+
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+std::mutex scratch_mu;
+double* scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// device address of scratch on device dev (current), looked up once per device
+int scratch_address(int dev, double** out)
+{
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ES_EHIP;
+        scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = scratch_dev[dev];
+    return ES_OK;
+}
+}  // namespace
+
+extern "C" int max_wavespeed_noalloc(const es_grid* g, const double* JU, const double* J, const double* jxi_x,
+                                     double cfl, double* lambda_dev, double* dt_dev, unsigned* status_dev,
+                                     void* stream)
+{
+    if (!JU || !J || !jxi_x || !(cfl > 0.0)) return ES_EINVAL;
+    int rc = check_grid(g);
+    if (rc) return rc;
+    Phys ph;
+    Geo geo;
+    build_params(g, ph, geo);
+    const long nint = (long)geo.n[0] * geo.n[1] * geo.n[2];
+    if (reduction_blocks(nint) > NOALLOC_PARTS) return ES_EUNSUPPORTED;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return ES_EHIP;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return ES_EUNSUPPORTED;
+    double* sc = nullptr;
+    rc = scratch_address(dev, &sc);
+    if (rc) return rc;
+    // every partial the finishing pass reads is written by its block first,
+    // and the status word in the scratch is only ever or-ed (never read), so
+    // nothing has to be cleared between calls
+    unsigned* st = status_dev ? status_dev : reinterpret_cast<unsigned*>(sc + NOALLOC_PARTS + 2);
+    hipStream_t s = S(stream);
+    if (wavespeed(ph, geo, JU, J, jxi_x, cfl, sc, sc + NOALLOC_PARTS, st, s) != hipSuccess) return ES_EHIP;
+    if (lambda_dev && copy(sc + NOALLOC_PARTS, lambda_dev, 1, s) != hipSuccess) return ES_EHIP;
+    if (dt_dev && copy(sc + NOALLOC_PARTS + 1, dt_dev, 1, s) != hipSuccess) return ES_EHIP;
+    return ES_OK;
+}

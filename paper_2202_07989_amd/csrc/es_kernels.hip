@@ -811,6 +811,8 @@ __global__ void k_entropy(Phys ph, Geo g, const double* __restrict__ JU, const d
 
 static int red_grid(long nint) { return (int)std::max<long>(1, std::min<long>((nint + 255) / 256, RED_BLOCKS)); }
 
+int reduction_blocks(long nint) { return red_grid(nint); }
+
 #define ES_DISPATCH_ND(ph, g, FN, ...)                                   \
     do {                                                                 \
         if (ph.nspec == 1 && g.dim == 2) FN<1, 2>(__VA_ARGS__);          \

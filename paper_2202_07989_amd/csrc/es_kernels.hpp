@@ -67,6 +67,8 @@ hipError_t metrics(const Phys& ph, const Geo& g, const double* xn, const double*
                    hipStream_t s, const int* reuse = nullptr);
 hipError_t wavespeed(const Phys& ph, const Geo& g, const double* JU, const double* J, const double* jxx,
                      double cfl, double* part, double* out2, unsigned* status, hipStream_t s);
+// number of per-block partials the reductions write for nint interior nodes
+int reduction_blocks(long nint);
 hipError_t entropy_sum(const Phys& ph, const Geo& g, const double* JU, const double* J, const double* dJU,
                        const double* dJ, double* part, double* out, hipStream_t s);
 // with xnext, also x_{n+1} = xn + disp with its ghost layers

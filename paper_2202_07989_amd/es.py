@@ -61,6 +61,7 @@ _SIGS = {
     "es_rhs": [_P, _P, _P, _P, _P, _P, _P, _P],
     "es_rk_stage": [_P, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "max_wavespeed": [_P, _P, _P, _P, C.c_double, _P, _P, _P],
+    "max_wavespeed_noalloc": [C.POINTER(EsGrid), _P, _P, _P, C.c_double, _P, _P, _P, _P],
     "mesh_redistribute": [_P, C.POINTER(EsMonitor), _P, _P, _P, _P, _P, _P, _P],
     "es_jacobian": [_P, _P, _P, _P, _P],
     "es_entropy": [_P, _P, _P, _P, _P],
@@ -161,6 +162,22 @@ def make_monitor(mon) -> EsMonitor:
     for t, q in enumerate(mon.get("psi", [])):
         m.psi[t] = q
     return m
+
+
+def max_wavespeed_noalloc(spec, JU, J, jxi_x, cfl, lambda_dev=None, dt_dev=None, status_dev=None,
+                          precision=ES_FP64, stream=None):
+    """max_wavespeed without a context and without any allocation (the
+    library's static device scratch); status_dev is an int32 device tensor
+    of one element or None."""
+    g = make_grid(spec, precision)
+    st = None
+    if status_dev is not None:
+        if status_dev.device.type != "cuda" or status_dev.dtype != torch.int32:
+            raise ValueError("status_dev must be a one-element int32 device tensor")
+        st = C.c_void_p(status_dev.data_ptr())
+    _check("max_wavespeed_noalloc",
+           lib.max_wavespeed_noalloc(C.byref(g), _ptr(JU), _ptr(J), _ptr(jxi_x), cfl, _ptr(lambda_dev),
+                                     _ptr(dt_dev), st, _stream(stream)))
 
 
 class Context:
