@@ -73,6 +73,8 @@ def lib():
             "orc_interface_frame": (C.c_int, [_G, _D, _D, _D, _D, _D]),
             "orc_mr5": (C.c_double, [_D, _D, C.c_double]),
             "orc_sign_bound": (C.c_int, [_G, _D, _D, _D, _D]),
+            "orc_mixed_bound": (C.c_int, [_G, _D, _D, _D, _D, C.c_double, C.c_double, C.c_double,
+                                           C.c_double, C.c_int, C.POINTER(C.c_long), _D]),
             "orc_sign_test": (C.c_int, [_G, _D, _D, _D, _D, C.c_int, C.c_int, C.POINTER(C.c_long),
                                          _D, _D, _D, C.POINTER(C.c_int), _D]),
             "orc_js5": (C.c_double, [_D, C.c_double]),
@@ -246,6 +248,21 @@ class Oracle:
                                   pts.ctypes.data_as(C.POINTER(C.c_long)), _p(jump), _p(jw),
                                   _p(bound), Y.ctypes.data_as(C.POINTER(C.c_int)), _p(s))
         return rc, jump, jw, bound, Y.astype(bool), s
+
+    # constants of the a-priori bound of the mixed-precision path
+    MIXED_KF, MIXED_KW, U32 = 16.0, 64.0, 2.0 ** -24
+
+    def mixed_bound(self, JU, J, jx, jt, flat_idx, tol32=None):
+        """Per-node a-priori bound (npts, nc) on |mixed GPU - FP64| of the
+        right-hand side at the given nodes."""
+        pts = np.ascontiguousarray(flat_idx, dtype=np.int64)
+        n = len(pts)
+        tol32 = self.spec.get("sign_tol32", 1e-6) if tol32 is None else tol32
+        out = np.zeros((n, self.nc))
+        rc = self.L.orc_mixed_bound(self.gp, _p(JU), _p(J), _p(jx), _p(jt), self.MIXED_KF, self.MIXED_KW,
+                                    self.U32, tol32, n, pts.ctypes.data_as(C.POINTER(C.c_long)), _p(out))
+        assert rc == 0, rc
+        return out
 
     def js5(self, q, eps=None):
         eps = self.g.weno_eps if eps is None else eps

@@ -285,6 +285,56 @@ static void ec_flux_of(const orc_grid *g, const prim_t *l, const prim_t *r,
     }
 }
 
+/* Sum of the absolute values of the summands of each component of the pair
+   flux of ec_flux_of (same printed form n_t Utilde + sum_j n_j Ftilde_j):
+   the size of the terms whose rounding a lower-precision evaluation of the
+   flux suffers (test infrastructure for the mixed-precision bound). */
+static void ec_flux_mag_of(const orc_grid *g, const prim_t *l, const prim_t *r,
+                           const double *ml, const double *mr, double *Fm)
+{
+    int N = g->nspec, d = g->dim, nc = N + d + 1;
+    double rln[2], rmean[2], vmean[3];
+    double bl = 1.0 / l->T, br = 1.0 / r->T;
+    double bmean = 0.5 * (bl + br);
+    double bln = orc_logmean(bl, br);
+    double pinf = 0.0, sum_rln = 0.0, sum_v2 = 0.0, sum_vsq = 0.0;
+    for (int s = 0; s < N; s++) {
+        rln[s] = orc_logmean(l->rho[s], r->rho[s]);
+        rmean[s] = 0.5 * (l->rho[s] + r->rho[s]);
+        sum_rln += rln[s];
+        pinf += g->pinf[s];
+    }
+    for (int m = 0; m < d; m++) {
+        vmean[m] = 0.5 * (l->v[m] + r->v[m]);
+        sum_v2 += 0.5 * (l->v[m] * l->v[m] + r->v[m] * r->v[m]);
+        sum_vsq += vmean[m] * vmean[m];
+    }
+    double Ut[MAXC], Ft[3][MAXC];
+    for (int s = 0; s < N; s++) Ut[s] = rln[s];
+    for (int m = 0; m < d; m++) Ut[N + m] = fabs(vmean[m]) * sum_rln;
+    Ut[N + d] = 0.0;
+    for (int s = 0; s < N; s++) Ut[N + d] += rln[s] * (g->cv[s] / bln + 0.5 * sum_v2);
+    Ut[N + d] += sum_rln * sum_vsq + pinf;
+    double Rrho = 0.0;
+    for (int s = 0; s < N; s++) Rrho += gas_const(g, s) * rmean[s];
+    for (int j = 0; j < d; j++) {
+        double sumF = 0.0;
+        for (int s = 0; s < N; s++) { Ft[j][s] = rln[s] * fabs(vmean[j]); sumF += Ft[j][s]; }
+        for (int m = 0; m < d; m++) {
+            Ft[j][N + m] = fabs(vmean[m]) * sumF;
+            if (m == j) Ft[j][N + m] += Rrho / bmean + pinf;
+        }
+        Ft[j][N + d] = 0.0;
+        for (int s = 0; s < N; s++) Ft[j][N + d] += Ft[j][s] * (g->cv[s] / bln + 0.5 * sum_v2);
+        for (int m = 0; m < d; m++) Ft[j][N + d] += fabs(vmean[m]) * Ft[j][N + m];
+        Ft[j][N + d] += pinf * fabs(vmean[j]);
+    }
+    for (int c = 0; c < nc; c++) {
+        Fm[c] = fabs(0.5 * (ml[0] + mr[0])) * Ut[c];
+        for (int j = 0; j < d; j++) Fm[c] += fabs(0.5 * (ml[1 + j] + mr[1 + j])) * Ft[j][c];
+    }
+}
+
 int orc_ec_flux(const orc_grid *g, const double *Ul, const double *Ur,
                 const double *ml, const double *mr, double *F)
 {
@@ -794,10 +844,14 @@ typedef struct {
     long P;
 } fields_t;
 
-/* what the sign test saw at one interface (orc_sign_test) */
+/* what the sign test saw at one interface (orc_sign_test), and the term
+   magnitudes of the interface flux (orc_mixed_bound) */
 typedef struct {
     double jump[MAXC], jw[MAXC], bound[MAXC], s;
     int Y[MAXC];
+    double ecmag[MAXC];          /* sum_m |alpha_m| sum_s |terms| of the pair fluxes */
+    double w6[MAXC];             /* sum over the six stencil nodes of sum_e |R_ec| |(T V)_e| */
+    double hsTR[MAXC * MAXC];    /* 1/2 s |(T^T R)_cm| */
 } sign_info_t;
 
 /* Bound on the size of the terms that form W_c at nodes i and i+1.  With
@@ -865,6 +919,7 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
     orc_alpha(g->w, al);
     for (int c = 0; c < nc; c++) F[c] = 0.0;
     *G = 0.0;
+    if (info) memset(info, 0, sizeof(*info));
     for (int m = 1; m <= g->w; m++)
         for (int s = 0; s < m; s++) {
             int a = 2 - s, b = 2 - s + m;   /* slots of nodes i-s and i-s+m */
@@ -872,6 +927,11 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
             ec_flux_of(g, &q[a], &q[b], M[a], M[b], Fh);
             for (int c = 0; c < nc; c++) F[c] += al[m - 1] * Fh[c];
             *G += al[m - 1] * 0.5 * (M[a][0] + M[b][0]);
+            if (info) {
+                double Fm[MAXC];
+                ec_flux_mag_of(g, &q[a], &q[b], M[a], M[b], Fm);
+                for (int c = 0; c < nc; c++) info->ecmag[c] += fabs(al[m - 1]) * Fm[c];
+            }
         }
     if (prod) *prod = 0.0;
     if (!g->dissipation) return ORC_OK;
@@ -895,6 +955,8 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
         for (int c = 0; c < nc; c++) {
             W[t][c] = 0.0;
             for (int e = 0; e < nc; e++) W[t][c] += R[e * nc + c] * TV[e];   /* R^T */
+            if (info)
+                for (int e = 0; e < nc; e++) info->w6[c] += fabs(R[e * nc + c]) * fabs(TV[e]);
         }
     }
     sign_bound_of(g, Vi, Vi1, R, Wmag);
@@ -939,6 +1001,16 @@ static int interface_flux(const fields_t *f, long i, int k, double *F, double *G
     }
     for (int c = 0; c < nc; c++) F[c] -= D[c];
     if (prod) *prod = pr;
+    if (info) {   /* 1/2 s |T^T R| (T^T acts on the velocity rows) */
+        for (int c = 0; c < nc; c++)
+            for (int mm = 0; mm < nc; mm++) info->hsTR[c * nc + mm] = 0.5 * s * fabs(R[c * nc + mm]);
+        for (int a = 0; a < d; a++)
+            for (int mm = 0; mm < nc; mm++) {
+                double t = 0.0;
+                for (int b = 0; b < d; b++) t += Tv[b][a] * R[(N + b) * nc + mm];
+                info->hsTR[(N + a) * nc + mm] = 0.5 * s * fabs(t);
+            }
+    }
     return ORC_OK;
 }
 
@@ -981,6 +1053,41 @@ int orc_sign_test(const orc_grid *g, const double *JU, const double *J,
             Y[p * nc + c] = info.Y[c];
         }
         s_out[p] = info.s;
+    }
+    return rc;
+}
+
+int orc_mixed_bound(const orc_grid *g, const double *JU, const double *J,
+                    const double *jxi_x, const double *jxi_t, double kf, double kw,
+                    double u, double tol32, int npts, const long *pts, double *bound)
+{
+    if (!valid_grid(g) || !JU || !J || !jxi_x || npts < 0 || !pts || !bound) return ORC_EINVAL;
+    fields_t f = {g, JU, J, jxi_x, jxi_t, orc_npoints(g)};
+    int nc = orc_ncomp(g), rc = ORC_OK;
+    for (int p = 0; p < npts; p++) {
+        double E[MAXC];
+        for (int c = 0; c < nc; c++) E[c] = 0.0;
+        for (int k = 0; k < g->dim; k++) {
+            long st = stride_(g, k);
+            for (int side = 0; side < 2; side++) {
+                double F[MAXC], G;
+                sign_info_t info;
+                int r = interface_flux(&f, side ? pts[p] : pts[p] - st, k, F, &G, NULL, &info);
+                if (r) { if (!rc) rc = r; continue; }
+                for (int c = 0; c < nc; c++) {
+                    double e = kf * u * info.ecmag[c];
+                    if (g->dissipation)
+                        for (int m = 0; m < nc; m++) {
+                            double ajw = fabs(info.jw[m]);
+                            int unresolved = fabs(info.jump[m]) <= (tol32 + kw * u) * info.bound[m];
+                            e += info.hsTR[c * nc + m] *
+                                 (kw * u * info.w6[m] + kf * u * ajw + (unresolved ? ajw : 0.0));
+                        }
+                    E[c] += e / g->dxi[k];
+                }
+            }
+        }
+        for (int c = 0; c < nc; c++) bound[p * nc + c] = E[c];
     }
     return rc;
 }

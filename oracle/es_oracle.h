@@ -117,6 +117,20 @@ int    orc_sign_test(const orc_grid *g, const double *JU, const double *J,
                      const double *jxi_x, const double *jxi_t, int k, int npts,
                      const long *pts, double *jump, double *jw, double *bound,
                      int *Y, double *s_out);
+/* a-priori bound on |lower-precision - FP64| of the right-hand side at the
+ * nodes pts (npts * nc values), for arithmetic of unit roundoff u in the
+ * pair fluxes, frame, projections and reconstructions (test infrastructure,
+ * not a step of the scheme).  Per node i and component c, summed over the
+ * directions k and the two interfaces f of the node along k, divided by
+ * dxi_k:  kf u |EC|_c(f) + sum_m 1/2 s |(T^T R)_cm| (kw u W6_m + kf u
+ * |[[W_m]]^WENO| + [|[[W_m]]| <= (tol32 + kw u) B_m] |[[W_m]]^WENO|), with
+ * |EC|_c the absolute summands of the six pair fluxes weighted by
+ * |alpha_m|, W6_m = sum over the six stencil nodes of sum_e |R_em| |(T V)_e|,
+ * B_m the sign-test bound; the last term covers a sign test that the lower
+ * precision cannot resolve against its tolerance tol32. */
+int    orc_mixed_bound(const orc_grid *g, const double *JU, const double *J,
+                       const double *jxi_x, const double *jxi_t, double kf, double kw,
+                       double u, double tol32, int npts, const long *pts, double *bound);
 double orc_mr5(const double *q, const double *chi, double eps);
 /* classical fifth-order WENO (Jiang & Shu 1996) at the right face of q[2]
  * from q[0..4], linear weights (1/10, 6/10, 3/10), alpha_k = d_k/(eps+beta_k)^2 */

@@ -72,3 +72,31 @@ def moving_metrics(o, sp, x, seed, amp=0.01, c_s=0.5, dt=0.01):
     o.fill_ghosts(disp, sp["dim"])
     jx, jt = o.metrics(x, disp, c_s=c_s, dt=dt)
     return disp, jx, jt
+
+
+# ---------------------------------------------------------------------------
+# a-priori bound of the mixed-precision path (the oracle's orc_mixed_bound):
+# per node and component, with K_F = 16, K_W = 64, u = 2^-24 fixed in advance
+# ---------------------------------------------------------------------------
+def interior_flat(sp, shape):
+    """Flat padded indices of the interior nodes, in interior order."""
+    return np.arange(int(np.prod(shape))).reshape(shape)[interior_slices(sp)].ravel()
+
+
+def mixed_rhs_bound(o, sp, JU, J, jx, jt):
+    """Bound (nc, *interior shape) on |mixed - FP64| of the right-hand side."""
+    shape = J.shape[1:]
+    idx = interior_flat(sp, shape)
+    b = o.mixed_bound(JU, J, jx, jt, idx)
+    ishape = J[I.interior(sp)].shape[1:]
+    return b.T.reshape((o.nc,) + ishape)
+
+
+def mixed_ratio(h, ref, bound):
+    """max |h - ref| / bound over nodes (per component arrays of equal shape)."""
+    return float((np.abs(h - ref) / bound).max())
+
+
+def mixed_step_growth(cfl):
+    """Assumed max-norm growth of a perturbation over one step (stated a priori)."""
+    return 1.0 + 6.0 * cfl
