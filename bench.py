@@ -55,15 +55,30 @@ def load_traffic():
     return t.get("bytes_per_stage")
 
 
-def cpu_baseline(sp, JU, J, x, n):
-    """The CPU oracle (never tuned) on a bounded sample of the same workload:
-    one fused RK stage on a 64^3 box of the same shock-bubble data, all host
-    cores (OpenMP)."""
-    import numpy as np
+def host_cpu():
+    """Host CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
 
+
+def oracle_stage_rate(m, seconds, max_reps):
+    """Cell-stage rate of the oracle's fused RK stage on an m^3 box of the
+    shock-bubble data (threads as OMP_NUM_THREADS says); returns (rate,
+    reps, elapsed)."""
     import oracle
     from paper_2202_07989_amd import inputs as I
-    m = 64 if n >= 64 else n
     sps = I.spec_c3(m)
     o = oracle.Oracle(sps)
     JUs, Js, xs = I.init_shock_bubble(sps)
@@ -78,13 +93,37 @@ def cpu_baseline(sp, JU, J, x, n):
         o.rk_stage(1, dt, JUs, Js, JUs, Js, jx, jt)
         reps += 1
         el = time.perf_counter() - t0
-        if el > 10.0 or reps >= 20:
+        if el > seconds or reps >= max_reps:
             break
+    return m ** 3 * reps / el, reps, el
+
+
+def cpu_baseline(sp, JU, J, x, n):
+    """The CPU oracle (never tuned) on a bounded sample of the same workload:
+    fused RK stages on a 64^3 box of the same shock-bubble data, with all the
+    host cores given to this process (OpenMP), then with one thread (a
+    child process with OMP_NUM_THREADS=1)."""
+    import subprocess
+    m = 64 if n >= 64 else n
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    rate = m ** 3 * reps / el
-    return {"value": rate, "unit": "cell-stage updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{reps} fused RK stage(s) of the oracle on a {m}^3 box of the same "
-                      f"3D two-species shock-bubble data ({el:.1f} s)"}
+    rate, reps, el = oracle_stage_rate(m, 10.0, 20)
+    model, avail = host_cpu()
+    one = None
+    try:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--mode", "oracle-rate", "--n", str(m)],
+                           env=env, capture_output=True, text=True, timeout=120)
+        one = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+    except (subprocess.TimeoutExpired, ValueError, IndexError):
+        one = None
+    out = {"value": rate, "unit": "cell-stage updates/s", "cores": threads, "kind": "oracle",
+           "host_cpu": model, "host_cores_available": avail,
+           "sample": f"{reps} fused RK stage(s) of the oracle on a {m}^3 box of the same "
+                     f"3D two-species shock-bubble data ({el:.1f} s, {threads} threads)"}
+    if one:
+        out["value_1_thread"] = one["value"]
+        out["sample_1_thread"] = one["sample"]
+    return out
 
 
 def stage_inputs(ctx, mon, cfl, gU, gJ, gx, dt_dev):
@@ -177,14 +216,113 @@ def run_precision(args, prec_name, n, steps, warmup, stage_reps):
     s1.record(stream)
     torch.cuda.synchronize()
     ms_stage = s0.elapsed_time(s1) / stage_reps
+    # es_rhs alone (three direction sweeps writing d(JU)/dt, dJ/dt; no stage
+    # combination) on the same state and metrics
+    ctx.es_rhs(gU, gJ, jx, jt, JUo, Jo)
+    torch.cuda.synchronize()
+    s0.record(stream)
+    for _ in range(stage_reps):
+        ctx.es_rhs(gU, gJ, jx, jt, JUo, Jo)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    ms_rhs = s0.elapsed_time(s1) / stage_reps
     key = (3, 2)
     achieved = FLOPS_PER_CELL_STAGE[key] * cells / (ms_stage / 1e3) / 1e12
     peak = PEAK_FP64_TFLOPS if prec == es.ES_FP64 else PEAK_FP32_TFLOPS
     hbm_gbs = BYTES_PER_CELL_STAGE[key] * cells / (ms_stage / 1e3) / 1e9
     del ctx
     torch.cuda.empty_cache()
-    return dict(value=value, ms_step=ms_step, wall=wall, status=rc, ms_stage=ms_stage,
+    return dict(value=value, ms_step=ms_step, wall=wall, status=rc, ms_stage=ms_stage, ms_rhs=ms_rhs,
                 achieved=achieved, peak=peak, hbm_gbs=hbm_gbs, sp=sp, JU=JU, J=J, x=x)
+
+
+def config_rates(steps=20):
+    """Whole-step rates of the 2D configurations, FP64 and mixed:
+    64^2 one-species smooth advection on the fixed curvilinear mesh (CFL
+    0.5), and the 512^2 two-species shock-bubble on the moving mesh (10
+    Jacobi sweeps, 3 filter passes, alpha 1200, CFL 0.4)."""
+    import numpy as np
+    import torch
+
+    from paper_2202_07989_amd import es
+    from paper_2202_07989_amd import inputs as I
+
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, sp, init, move, cfl in (
+            ("2d_1species_64_fixed_curvilinear", I.spec_c1(64), I.init_c1, False, 0.5),
+            ("2d_2species_512_moving_shock_bubble", I.spec_c2(512), I.init_shock_bubble, True, 0.4)):
+        JU, J, x = init(sp)
+        mon = I.monitor_spec(n_sweeps=10, n_smooth=3, sigma=(0,), alpha=(1200.0,)) if move else None
+        row = {}
+        for prec_name, prec in (("fp64", es.ES_FP64), ("mixed", es.ES_MIXED)):
+            ctx = es.Context(sp, precision=prec)
+            gU, gJ, gx = dev(JU), dev(J), dev(x)
+            dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+            for _ in range(3):
+                ctx.es_step(gU, gJ, gx, mon=mon, cfl=cfl, move_mesh=move, dt_dev=dt)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                ctx.es_step(gU, gJ, gx, mon=mon, cfl=cfl, move_mesh=move, dt_dev=dt)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            cells = sp["n"][0] * sp["n"][1]
+            row[prec_name] = {"ms_per_step": ms, "cell_stage_updates_per_s": 3 * cells / (ms / 1e3),
+                              "status": ctx.es_status()[0]}
+            del ctx
+        row["mixed_speedup"] = row["fp64"]["ms_per_step"] / row["mixed"]["ms_per_step"]
+        out[name] = row
+    return out
+
+
+def full_length(args):
+    """The 2D 512^2 moving-mesh shock-bubble for its 200 steps and the 3D
+    256^3 one for its 50, FP64 and mixed, from the seeded initial data:
+    status after every 10 steps (stops at the first non-physical state),
+    smallest partial densities and J at the end, time."""
+    import numpy as np
+    import torch
+
+    from paper_2202_07989_amd import es
+    from paper_2202_07989_amd import inputs as I
+
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = {"mode": "full-length"}
+    for name, sp, steps, mon, cfl in (
+            ("2d_512_200_steps", I.spec_c2(512), 200,
+             I.monitor_spec(n_sweeps=10, n_smooth=3, sigma=(0,), alpha=(1200.0,)), 0.4),
+            ("3d_256_50_steps", I.spec_c3(256), 50,
+             I.monitor_spec(n_sweeps=5, n_smooth=3, sigma=(0,), alpha=(1200.0,)), 0.3)):
+        JU, J, x = I.init_shock_bubble(sp)
+        Iin = I.interior(sp)
+        for prec_name, prec in (("fp64", es.ES_FP64), ("mixed", es.ES_MIXED)):
+            ctx = es.Context(sp, precision=prec)
+            gU, gJ, gx = dev(JU), dev(J), dev(x)
+            dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+            t, done, rc = 0.0, 0, 0
+            t0 = time.perf_counter()
+            while done < steps:
+                for _ in range(10):
+                    ctx.es_step(gU, gJ, gx, mon=mon, cfl=cfl, move_mesh=True, dt_dev=dt)
+                    t += float(dt.item())
+                    done += 1
+                rc, flags = ctx.es_status()
+                print(json.dumps({"run": name, "precision": prec_name, "step": done, "status": rc}), flush=True)
+                if rc != 0:
+                    break
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            rho = (gU[Iin][:2] / gJ[Iin]).reshape(2, -1)
+            out[f"{name}_{prec_name}"] = {"steps_done": done, "status": rc, "t_end": t, "wall_s": wall,
+                                          "min_partial_density": [float(rho[0].min()), float(rho[1].min())],
+                                          "min_J": float(gJ[Iin].min())}
+            del ctx, gU, gJ, gx
+            torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
 
 
 def accuracy_study(args):
@@ -664,14 +802,17 @@ def main():
                     help="both: FP64 gives the reported value, the mixed form is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=10)
-    ap.add_argument("--mode", choices=["step", "stage", "accuracy", "batch", "vortex", "example"],
+    ap.add_argument("--mode", choices=["step", "stage", "accuracy", "batch", "vortex", "example", "full-length",
+                                       "oracle-rate"],
                     default="step",
                     help="stage: only the fused-RK-stage loop and a 2 GiB device copy (for "
                          "rocprofv3 counter runs; the copy calibrates FETCH_SIZE/WRITE_SIZE); "
                          "accuracy: FP64 vs mixed (and vs an oracle reference file) after --steps steps; "
                          "batch: the 64-instance batched 2D form, FP64 and mixed, vs sequential launches; "
                          "vortex: the isentropic-vortex convergence and entropy studies; "
-                         "example: one of the paper's walled examples to its final time")
+                         "example: one of the paper's walled examples to its final time; "
+                         "full-length: the 512^2 (200 steps) and 256^3 (50 steps) shock-bubble runs "
+                         "with their status; oracle-rate: the CPU oracle's stage rate alone (no GPU)")
     ap.add_argument("--example", choices=sorted(EXAMPLES), default="shock-bubble-he")
     ap.add_argument("--mesh", choices=["moving", "uniform"], default="moving",
                     help="example mode: MM (moving mesh) or UM (uniform mesh) runs")
@@ -682,6 +823,7 @@ def main():
     ap.add_argument("--reconstruction", choices=["mr", "js"], default="mr",
                     help="step/stage modes: multi-resolution WENO (the method) or the classical "
                          "WENO5 of the comparison variant MM-WENOJS")
+    ap.add_argument("--no-configs", action="store_true", help="step mode: skip the 2D configuration rates")
     ap.add_argument("--oracle-ref", default=None,
                     help="accuracy mode: .npz written by the oracle's reference script")
     args = ap.parse_args()
@@ -691,6 +833,13 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+
+    if args.mode == "oracle-rate":
+        rate, reps, el = oracle_stage_rate(args.n, 10.0, 20)
+        th = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+        print(json.dumps({"value": rate, "sample": f"{reps} fused RK stage(s) of the oracle on a {args.n}^3 "
+                          f"box of the same data ({el:.1f} s, {th} thread(s))"}), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -711,6 +860,9 @@ def main():
         return
     if args.mode == "example":
         example_run(args)
+        return
+    if args.mode == "full-length":
+        full_length(args)
         return
     if args.mode == "stage":
         sp = spec_for(args, I, n)
@@ -761,6 +913,9 @@ def main():
                      "algorithmic_hbm_frac": r["hbm_gbs"] / PEAK_HBM_GBS},
         "status": r["status"],
         "wall_s": r["wall"],
+        "es_rhs_alone": {"ms_per_call": r["ms_rhs"], "cell_updates_per_s": cells / (r["ms_rhs"] / 1e3),
+                         "note": "three direction sweeps writing d(JU)/dt and dJ/dt, same state and metrics"},
+        "es_rk_stage": {"ms_per_call": r["ms_stage"], "cell_stage_updates_per_s": cells / (r["ms_stage"] / 1e3)},
     }
     if args.precision == "both":
         m = run_precision(args, "mixed", n, args.steps, args.warmup, args.stage_reps)
@@ -768,7 +923,10 @@ def main():
                         "speedup_vs_fp64": m["value"] / r["value"],
                         "stage_ms_per_launch": m["ms_stage"],
                         "stage_achieved_TFLOPs": m["achieved"], "peak_fp32_TFLOPs": m["peak"],
-                        "stage_frac": m["achieved"] / m["peak"], "status": m["status"]}
+                        "stage_frac": m["achieved"] / m["peak"], "status": m["status"],
+                        "es_rhs_alone_ms": m["ms_rhs"]}
+    if not args.no_configs:
+        out["configs_2d"] = config_rates()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r["sp"], r["JU"], r["J"], r["x"], n)
     print(json.dumps(out), flush=True)
