@@ -19,14 +19,21 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
-def build(openmp: bool = True) -> str:
-    """Compile liboracle.so with gcc (plain -O2, no fast-math)."""
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+def build(openmp: bool = True, out: str | None = None, sanitize: bool = False) -> str:
+    """Compile liboracle.so with gcc (plain -O2, no fast-math).  sanitize:
+    an AddressSanitizer + UndefinedBehaviorSanitizer build (for the CPU
+    sanitizer run of the pins; load it with ES_ORACLE_LIB and libasan
+    preloaded)."""
+    out = out or _LIB
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", out + ".tmp", _SRC, "-lm"]
     if openmp:
         cmd.insert(1, "-fopenmp")
+    if sanitize:
+        cmd[1:1] = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=undefined"]
     subprocess.check_call(cmd)
-    os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 class Grid(C.Structure):
@@ -55,9 +62,12 @@ _G = C.POINTER(Grid)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = C.CDLL(_LIB)
+        path = os.environ.get("ES_ORACLE_LIB")   # another build of the same source (sanitizers)
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+        L = C.CDLL(path)
         sig = {
             "orc_ncomp": (C.c_int, [_G]),
             "orc_alpha": (None, [C.c_int, _D]),

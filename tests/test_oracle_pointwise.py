@@ -522,3 +522,145 @@ def test_rk3_stability_polynomial_and_abscissae():
             a, b, c = o.rk_coeffs(s)
             y = a * y0 + b * (y + (c ** deg))
         assert y == pytest.approx(1.0 / (deg + 1), rel=1e-15)
+
+
+# -- the same pins at the stiffness of the water/air workloads ---------------
+# Finite differences of FP64 functions cannot resolve the derivatives of a
+# stiffened gas with p_inf = 6e8 at p ~ 1e5 to a useful tolerance, so here the
+# entropy eta(U) and the fluxes F_k(U) are written from the problem statement
+# (Section 1, eq StiffenedEOS; Definition 1.1 of the entropy pair) in 60-digit
+# mpmath and differentiated there; the oracle's closed forms (V, the entropy
+# flux pair, the sound speed, the scaled eigenvectors R) are checked against
+# those derivatives at the water/air states of the workloads.
+STIFF = [c for c in CASES if sum(c[2]) >= 1e3]
+
+
+def _mp_prims(sp, U):
+    N, d = sp["nspec"], sp["dim"]
+    cv = [mpmath.mpf(c) for c in sp["cv"][:N]]
+    Rg = [mpmath.mpf(c) * (mpmath.mpf(g) - 1) for c, g in zip(sp["cv"][:N], sp["gamma"][:N])]
+    pinf = sum(mpmath.mpf(p) for p in sp["pinf"][:N])
+    rho = U[:N]
+    rt = sum(rho)
+    v = [U[N + j] / rt for j in range(d)]
+    kin = sum(U[N + j] * v[j] for j in range(d)) / 2
+    T = (U[N + d] - kin - pinf) / sum(cv[l] * rho[l] for l in range(N))
+    p = T * sum(Rg[l] * rho[l] for l in range(N)) - pinf
+    return rho, v, T, p, cv, Rg
+
+
+def _mp_eta(sp, U):
+    rho, v, T, p, cv, Rg = _mp_prims(sp, U)
+    return -sum(rho[l] * (cv[l] * mpmath.log(T) - Rg[l] * mpmath.log(rho[l])) for l in range(sp["nspec"]))
+
+
+def _mp_flux(sp, U, k):
+    N, d = sp["nspec"], sp["dim"]
+    rho, v, T, p, cv, Rg = _mp_prims(sp, U)
+    F = [rho[l] * v[k] for l in range(N)]
+    F += [U[N + j] * v[k] + (p if j == k else 0) for j in range(d)]
+    F += [(U[N + d] + p) * v[k]]
+    return F
+
+
+def _mp_grad(f, U, rel=mpmath.mpf("1e-18")):
+    g = []
+    for c in range(len(U)):
+        h = rel * max(abs(U[c]), mpmath.mpf(1))
+        Up, Um = list(U), list(U)
+        Up[c] += h
+        Um[c] -= h
+        g.append((f(Up) - f(Um)) / (2 * h))
+    return g
+
+
+def _mp_state(o, rng):
+    mpmath.mp.dps = 60
+    U = rand_state(o, rng)
+    return U, [mpmath.mpf(float(u)) for u in U]
+
+
+@pytest.mark.parametrize("dim,nspec,pinf", STIFF)
+def test_stiff_entropy_variables_are_gradient(dim, nspec, pinf):
+    o = oracle.Oracle(spec(dim, nspec, pinf=pinf))
+    rng = np.random.default_rng(31)
+    for _ in range(8):
+        U, Um = _mp_state(o, rng)
+        V = o.entropy_vars(U)
+        g = [float(x) for x in _mp_grad(lambda X: _mp_eta(o.spec, X), Um)]
+        np.testing.assert_allclose(V, g, rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("dim,nspec,pinf", STIFF)
+def test_stiff_entropy_flux_pair(dim, nspec, pinf):
+    """q_k'(U) = V^T F_k'(U) with q_k = eta v_k, the derivatives in mpmath."""
+    o = oracle.Oracle(spec(dim, nspec, pinf=pinf))
+    rng = np.random.default_rng(32)
+    N = nspec
+    for _ in range(4):
+        U, Um = _mp_state(o, rng)
+        V = [mpmath.mpf(float(x)) for x in o.entropy_vars(U)]
+        for k in range(dim):
+            cols = [_mp_grad(lambda X, e=e: _mp_flux(o.spec, X, k)[e], Um) for e in range(o.nc)]
+            VA = [sum(V[e] * cols[e][c] for e in range(o.nc)) for c in range(o.nc)]
+            gq = _mp_grad(lambda X: _mp_eta(o.spec, X) * X[N + k] / sum(X[:N]), Um)
+            scale = max(abs(V[e] * cols[e][c]) for e in range(o.nc) for c in range(o.nc))
+            for c in range(o.nc):
+                assert abs(VA[c] - gq[c]) <= 1e-9 * scale, (k, c, float(VA[c]), float(gq[c]))
+
+
+@pytest.mark.parametrize("dim,nspec,pinf", STIFF)
+def test_stiff_sound_speed_is_eigenvalue(dim, nspec, pinf):
+    """Eigenvalues of dF_1/dU (mpmath Jacobian of the EOS flux) are v_1 - c,
+    v_1 (N + d - 1 fold) and v_1 + c with the oracle's c."""
+    o = oracle.Oracle(spec(dim, nspec, pinf=pinf))
+    rng = np.random.default_rng(33)
+    for _ in range(4):
+        U, Um = _mp_state(o, rng)
+        A = mpmath.matrix(o.nc, o.nc)
+        for e in range(o.nc):
+            row = _mp_grad(lambda X, e=e: _mp_flux(o.spec, X, 0)[e], Um)
+            for c in range(o.nc):
+                A[e, c] = row[c]
+        ev = sorted(float(mpmath.re(x)) for x in mpmath.eig(A)[0])
+        v1 = U[nspec] / U[:nspec].sum()
+        c = o.sound_speed(U)
+        assert ev[0] == pytest.approx(v1 - c, rel=1e-10)
+        assert ev[-1] == pytest.approx(v1 + c, rel=1e-10)
+        np.testing.assert_allclose(ev[1:-1], v1, rtol=0, atol=1e-10 * (abs(v1) + c))
+
+
+@pytest.mark.parametrize("dim,nspec,pinf", STIFF)
+def test_stiff_scaled_eigenvectors(dim, nspec, pinf):
+    """R R^T = dU/dV = (d^2 eta/dU^2)^-1 at a single state (normal e_1), the
+    Hessian of eta in mpmath; R^-1 (dF_1/dU) R is diagonal with v_1 -+ c."""
+    o = oracle.Oracle(spec(dim, nspec, pinf=pinf))
+    rng = np.random.default_rng(34)
+    m = np.concatenate([[0.0], np.eye(dim)[0]])
+    for _ in range(3):
+        U, Um = _mp_state(o, rng)
+        R, s = o.interface_frame(U, U, m)
+        H = mpmath.matrix(o.nc, o.nc)
+        A = mpmath.matrix(o.nc, o.nc)
+        for e in range(o.nc):
+            grow = _mp_grad(lambda X, e=e: _mp_grad(lambda Y: _mp_eta(o.spec, Y), X)[e], Um,
+                            rel=mpmath.mpf("1e-12"))
+            frow = _mp_grad(lambda X, e=e: _mp_flux(o.spec, X, 0)[e], Um)
+            for c in range(o.nc):
+                H[e, c] = grow[c]
+                A[e, c] = frow[c]
+        dUdV = mpmath.inverse(H)
+        Rm = mpmath.matrix(R.tolist())
+        RR = Rm * Rm.T
+        scale = max(abs(dUdV[a, b]) for a in range(o.nc) for b in range(o.nc))
+        for a in range(o.nc):
+            for b in range(o.nc):
+                assert abs(RR[a, b] - dUdV[a, b]) <= 1e-9 * scale, (a, b)
+        Lam = mpmath.inverse(Rm) * A * Rm
+        v1 = U[nspec] / U[:nspec].sum()
+        c = o.sound_speed(U)
+        lam = [v1 - c] + [v1] * (o.nc - 2) + [v1 + c]
+        for a in range(o.nc):
+            for b in range(o.nc):
+                ref = lam[a] if a == b else 0.0
+                assert abs(float(Lam[a, b]) - ref) <= 1e-9 * (abs(v1) + c), (a, b)
