@@ -824,6 +824,9 @@ def main():
                     help="step/stage modes: multi-resolution WENO (the method) or the classical "
                          "WENO5 of the comparison variant MM-WENOJS")
     ap.add_argument("--no-configs", action="store_true", help="step mode: skip the 2D configuration rates")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="step mode: end with a 2 GiB device-to-device copy (calibrates the FETCH_SIZE and "
+                         "WRITE_SIZE counters of rocprofv3 runs)")
     ap.add_argument("--oracle-ref", default=None,
                     help="accuracy mode: .npz written by the oracle's reference script")
     args = ap.parse_args()
@@ -929,6 +932,13 @@ def main():
         out["configs_2d"] = config_rates()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r["sp"], r["JU"], r["J"], r["x"], n)
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")     # 2 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes_each_way"] = a.numel() * 8
+        del a, b
     print(json.dumps(out), flush=True)
 
 

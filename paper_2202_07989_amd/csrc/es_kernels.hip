@@ -782,11 +782,13 @@ __global__ void k_entropy(Phys ph, Geo g, const double* __restrict__ JU, const d
         const long i = interior_node(g, q, i0, i1, i2);
         NodeState<N, D> s;
         load_state<N, D>(ph, JU, Jv, P, i, s);
-        const double lT = log(s.T);
+        // logarithms as the flux kernels take them (within 2 ulp); a
+        // non-positive T or rho_l is a non-physical state the steps report
+        const double lT = ln_pos(s.T);
         if (!dJU) {   // J eta, eta = -sum rho_l (c_vl ln T - R_l ln rho_l)
             double eta = 0.0;
 #pragma unroll
-            for (int l = 0; l < N; l++) eta -= s.U[l] * (ph.cv[l] * lT - ph.Rg[l] * log(s.U[l]));
+            for (int l = 0; l < N; l++) eta -= s.U[l] * (ph.cv[l] * lT - ph.Rg[l] * ln_pos(s.U[l]));
             acc += Jv[i] * eta;
         } else {      // V . dJU - phi dJ
             double v2 = 0.0;
@@ -795,7 +797,7 @@ __global__ void k_entropy(Phys ph, Geo g, const double* __restrict__ JU, const d
             double t = 0.0, phi = 0.0;
 #pragma unroll
             for (int l = 0; l < N; l++) {
-                const double Vl = -(ph.cv[l] * lT - ph.Rg[l] * log(s.U[l])) - v2 / (2.0 * s.T) + ph.cvgam[l];
+                const double Vl = -(ph.cv[l] * lT - ph.Rg[l] * ln_pos(s.U[l])) - v2 / (2.0 * s.T) + ph.cvgam[l];
                 t += Vl * dJU[l * P + i];
                 phi += ph.Rg[l] * s.U[l] - ph.pinf[l] / s.T;
             }
@@ -947,13 +949,17 @@ hipError_t entropy_sum(const Phys& ph, const Geo& g, const double* JU, const dou
 // differences) as channel nsig + s.  Variables: 0 rho, 1 rho_1, 2 rho_2,
 // 3 p, 4 the speed |v| (the u of Example 5.9's monitor), 5 the schlieren
 // function of eq schlieren, read from its array (with ghost layers).
-template <int N, int D, bool EXT = true>
+// monitor variable sig at node i.  SIG: which variables the monitor may
+// use, so that the kernels carry only the code (and registers) they need:
+// 0 the densities (rho, rho_1, rho_2), 1 also the pressure, 2 also the
+// speed and the schlieren function
+template <int N, int D, int SIG = 0>
 __device__ __forceinline__ double sigma_of(const Phys& ph, const double* JU, const double* Jv, long P,
                                            long i, int sig, const double* phi)
 {
-    if (EXT && sig == 5) return phi[i];
+    if (SIG == 2 && sig == 5) return phi[i];
     const double Jq = Jv[i];
-    if (EXT && sig == 4) {
+    if (SIG == 2 && sig == 4) {
         double r = 0.0, m2 = 0.0;
 #pragma unroll
         for (int l = 0; l < N; l++) r += JU[l * P + i] / Jq;
@@ -971,15 +977,13 @@ __device__ __forceinline__ double sigma_of(const Phys& ph, const double* JU, con
         return r;
     }
     if (sig == 1) return JU[i] / Jq;
-    if (sig == 2) return JU[(N > 1 ? 1 : 0) * P + i] / Jq;
+    if (sig == 2 || SIG == 0) return JU[(N > 1 ? 1 : 0) * P + i] / Jq;
     NodeState<N, D> s;
     load_state<N, D>(ph, JU, Jv, P, i, s);
     return s.p;
 }
 
-// EXT: the monitor uses the speed or the schlieren function (without them
-// the kernels need fewer registers)
-template <int N, int D, bool EXT>
+template <int N, int D, int SIG>
 __global__ void k_monitor_grad(Phys ph, Geo g, MonitorP mo, const double* __restrict__ JU,
                                const double* __restrict__ Jv, double* __restrict__ grad,
                                double* __restrict__ part)
@@ -992,12 +996,12 @@ __global__ void k_monitor_grad(Phys ph, Geo g, MonitorP mo, const double* __rest
         const long i = interior_node(g, q, i0, i1, i2);
         for (int s = 0; s < mo.nsig; s++) {
             double g2 = 0.0, lap = 0.0;
-            const double sc = mo.form ? sigma_of<N, D, EXT>(ph, JU, Jv, P, i, mo.sigma[s], mo.phi) : 0.0;
+            const double sc = mo.form ? sigma_of<N, D, SIG>(ph, JU, Jv, P, i, mo.sigma[s], mo.phi) : 0.0;
 #pragma unroll
             for (int k = 0; k < D; k++) {
                 const long st = dir_stride(g, k);
-                const double sp = sigma_of<N, D, EXT>(ph, JU, Jv, P, i + st, mo.sigma[s], mo.phi);
-                const double sm = sigma_of<N, D, EXT>(ph, JU, Jv, P, i - st, mo.sigma[s], mo.phi);
+                const double sp = sigma_of<N, D, SIG>(ph, JU, Jv, P, i + st, mo.sigma[s], mo.phi);
+                const double sm = sigma_of<N, D, SIG>(ph, JU, Jv, P, i - st, mo.sigma[s], mo.phi);
                 const double dk = (sp - sm) / (2.0 * g.dxi[k]);
                 g2 += dk * dk;
                 lap += (sp - 2.0 * sc + sm) / (g.dxi[k] * g.dxi[k]);
@@ -1024,7 +1028,7 @@ __global__ void k_monitor_grad(Phys ph, Geo g, MonitorP mo, const double* __rest
 // planes; sigma at z-1, z, z+1 of the own column comes from a 3-plane ring,
 // the four in-plane neighbours are evaluated from the state directly.
 // Per-block maxima go to part[s * RED_BLOCKS + block] in block order.
-template <int N, bool EXT>
+template <int N, int SIG>
 __global__ void __launch_bounds__(256)
 k_monitor_grad3(Phys ph, Geo g, MonitorP mo, const double* __restrict__ JU, const double* __restrict__ Jv,
                 double* __restrict__ grad, double* __restrict__ part, int zchunk)
@@ -1047,15 +1051,15 @@ k_monitor_grad3(Phys ph, Geo g, MonitorP mo, const double* __restrict__ JU, cons
         for (int s = 0; s < mo.nsig; s++) {
             const int sg = mo.sigma[s];
             long i = ((long)zc0 * np1 + y) * np0 + x;
-            double sm = sigma_of<N, D, EXT>(ph, JU, Jv, P, i - sz, sg, mo.phi);
-            double s0 = sigma_of<N, D, EXT>(ph, JU, Jv, P, i, sg, mo.phi);
+            double sm = sigma_of<N, D, SIG>(ph, JU, Jv, P, i - sz, sg, mo.phi);
+            double s0 = sigma_of<N, D, SIG>(ph, JU, Jv, P, i, sg, mo.phi);
             double mg = 0.0, ml = 0.0;     // this channel's maxima over the column
             for (int z = zc0; z < zc1; z++, i += sz) {
-                const double sp = sigma_of<N, D, EXT>(ph, JU, Jv, P, i + sz, sg, mo.phi);
-                const double xp = sigma_of<N, D, EXT>(ph, JU, Jv, P, i + 1, sg, mo.phi);
-                const double xm = sigma_of<N, D, EXT>(ph, JU, Jv, P, i - 1, sg, mo.phi);
-                const double yp = sigma_of<N, D, EXT>(ph, JU, Jv, P, i + sy, sg, mo.phi);
-                const double ym = sigma_of<N, D, EXT>(ph, JU, Jv, P, i - sy, sg, mo.phi);
+                const double sp = sigma_of<N, D, SIG>(ph, JU, Jv, P, i + sz, sg, mo.phi);
+                const double xp = sigma_of<N, D, SIG>(ph, JU, Jv, P, i + 1, sg, mo.phi);
+                const double xm = sigma_of<N, D, SIG>(ph, JU, Jv, P, i - 1, sg, mo.phi);
+                const double yp = sigma_of<N, D, SIG>(ph, JU, Jv, P, i + sy, sg, mo.phi);
+                const double ym = sigma_of<N, D, SIG>(ph, JU, Jv, P, i - sy, sg, mo.phi);
                 const double d0 = (xp - xm) * ih[0];
                 const double d1 = (yp - ym) * ih[1];
                 const double d2 = (sp - sm) * ih[2];
@@ -1438,14 +1442,15 @@ __global__ void k_disp(Geo g, const double* __restrict__ xmu, const double* __re
 }
 
 template <int N, int D>
-static void launch_monitor(const Phys& ph, const Geo& g, const MonitorP& mo, bool ext, const double* JU,
+static void launch_monitor(const Phys& ph, const Geo& g, const MonitorP& mo, int sigmode, const double* JU,
                            const double* J, double* grad, double* part, int nb, hipStream_t s)
 {
-    if (ext)
-        hipLaunchKernelGGL((k_monitor_grad<N, D, true>), dim3(nb), dim3(256), 0, s, ph, g, mo, JU, J, grad, part);
+    if (sigmode == 2)
+        hipLaunchKernelGGL((k_monitor_grad<N, D, 2>), dim3(nb), dim3(256), 0, s, ph, g, mo, JU, J, grad, part);
+    else if (sigmode == 1)
+        hipLaunchKernelGGL((k_monitor_grad<N, D, 1>), dim3(nb), dim3(256), 0, s, ph, g, mo, JU, J, grad, part);
     else
-        hipLaunchKernelGGL((k_monitor_grad<N, D, false>), dim3(nb), dim3(256), 0, s, ph, g, mo, JU, J, grad,
-                           part);
+        hipLaunchKernelGGL((k_monitor_grad<N, D, 0>), dim3(nb), dim3(256), 0, s, ph, g, mo, JU, J, grad, part);
 }
 
 hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo_in, const double* JU,
@@ -1469,11 +1474,14 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo_in
     const bool march = g.dim == 3 && jblocks <= RED_BLOCKS;
     // the schlieren function first when the monitor uses it (th1 holds
     // |grad rho| until the filter overwrites it)
-    bool use_phi = false, ext = false;
+    bool use_phi = false, ext = false, press = false;
     for (int q = 0; q < mo.nsig; q++) {
         use_phi = use_phi || mo.sigma[q] == 5;
         ext = ext || mo.sigma[q] >= 4;
+        press = press || mo.sigma[q] == 3;
     }
+    // the monitor kernels carry only the variables they are asked for
+    const int sigmode = ext ? 2 : (press ? 1 : 0);
     if (use_phi) {
         ES_DISPATCH_ND(ph, g, launch_schlieren, ph, g, mo, JU, J, w.th1, w.part + 6 * RED_BLOCKS, w.scal + 7,
                        w.phi, nb, gi, s);
@@ -1482,11 +1490,12 @@ hipError_t mesh_redistribute(const Phys& ph, const Geo& g, const MonitorP& mo_in
     }
     // monitor and its global maxima
     if (march) {
-        auto* kern = ph.nspec == 1 ? (ext ? k_monitor_grad3<1, true> : k_monitor_grad3<1, false>)
-                                   : (ext ? k_monitor_grad3<2, true> : k_monitor_grad3<2, false>);
+        auto* kern = ph.nspec == 1
+                         ? (sigmode == 2 ? k_monitor_grad3<1, 2> : (sigmode == 1 ? k_monitor_grad3<1, 1> : k_monitor_grad3<1, 0>))
+                         : (sigmode == 2 ? k_monitor_grad3<2, 2> : (sigmode == 1 ? k_monitor_grad3<2, 1> : k_monitor_grad3<2, 0>));
         hipLaunchKernelGGL(kern, jgrid, dim3(256), 0, s, ph, g, mo, JU, J, w.grad, w.part, jchunk);
     } else {
-        ES_DISPATCH_ND(ph, g, launch_monitor, ph, g, mo, ext, JU, J, w.grad, w.part, nb, s);
+        ES_DISPATCH_ND(ph, g, launch_monitor, ph, g, mo, sigmode, JU, J, w.grad, w.part, nb, s);
     }
     for (int q = 0; q < (mo.form ? 2 * mo.nsig : mo.nsig); q++)
         hipLaunchKernelGGL(k_finish<RED_MAX>, dim3(1), dim3(256), 0, s, w.part + q * RED_BLOCKS,
