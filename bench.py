@@ -42,17 +42,18 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic():
-    """HBM bytes per fused stage measured with rocprofv3 counters (FETCH_SIZE,
-    WRITE_SIZE, calibrated on a copy kernel), if taken on the current kernel."""
+def load_counters():
+    """What rocprofv3 counters measured on the fused stage, if taken on the
+    current kernel source: HBM bytes per stage (FETCH_SIZE + WRITE_SIZE,
+    calibrated on a copy kernel) and executed FP64 flops per cell-stage."""
     p = os.path.join(ROOT, "profiles", "rk_stage_c3_256_traffic.json")
     if not os.path.exists(p):
-        return None
+        return {}
     with open(p) as fh:
         t = json.load(fh)
     if t.get("kernel_hash") != kernel_hash():
-        return None
-    return t.get("bytes_per_stage")
+        return {}
+    return t
 
 
 def host_cpu():
@@ -886,7 +887,9 @@ def main():
 
     main_prec = "mixed" if args.precision == "mixed" else "fp64"
     r = run_precision(args, main_prec, n, args.steps, args.warmup, args.stage_reps)
-    traffic = load_traffic() if main_prec == "fp64" else None
+    counters = load_counters() if main_prec == "fp64" else {}
+    traffic = counters.get("bytes_per_stage")
+    executed = counters.get("executed_fp64_flops_per_cell_stage")
     cells = n ** 3
     key = (3, 2)
     out = {
@@ -913,7 +916,10 @@ def main():
                      "frac": r["achieved"] / r["peak"], "traffic": traffic,
                      "kernel": "es_rk_stage (k_rhs_dir x3 directions, fused stage epilogue)",
                      "ms_per_launch": r["ms_stage"], "algorithmic_hbm_GBs": r["hbm_gbs"],
-                     "algorithmic_hbm_frac": r["hbm_gbs"] / PEAK_HBM_GBS},
+                     "algorithmic_hbm_frac": r["hbm_gbs"] / PEAK_HBM_GBS,
+                     "flops_per_cell_stage": FLOPS_PER_CELL_STAGE[key],
+                     "executed_flops_per_cell_stage": executed,
+                     "executed_frac": (executed * cells / (r["ms_stage"] / 1e3) / 1e12 / r["peak"]) if executed else None},
         "status": r["status"],
         "wall_s": r["wall"],
         "es_rhs_alone": {"ms_per_call": r["ms_rhs"], "cell_updates_per_s": cells / (r["ms_rhs"] / 1e3),
