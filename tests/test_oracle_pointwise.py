@@ -664,3 +664,37 @@ def test_stiff_scaled_eigenvectors(dim, nspec, pinf):
             for b in range(o.nc):
                 ref = lam[a] if a == b else 0.0
                 assert abs(float(Lam[a, b]) - ref) <= 1e-9 * (abs(v1) + c), (a, b)
+
+
+# -- C-9: the two-species averaged interface state ----------------------------
+# The paper leaves the average of two different states open; any symmetric,
+# consistent choice with a nonsingular R keeps the scheme entropy stable.
+# These pins check those properties (the particular average stays fixed only
+# by the agreement of the two implementations).
+@pytest.mark.parametrize("dim", [2, 3])
+def test_two_species_frame_symmetric_consistent_nonsingular(dim):
+    o = oracle.Oracle(spec(dim, 2))
+    rng = np.random.default_rng(35)
+    for _ in range(20):
+        Ul, Ur = rand_state(o, rng), rand_state(o, rng)
+        m = rand_metric(rng, dim)
+        R, s = o.interface_frame(Ul, Ur, m)
+        R2, s2 = o.interface_frame(Ur, Ul, m)
+        # symmetric in the two states
+        np.testing.assert_allclose(R2, R, rtol=1e-13, atol=1e-13 * np.abs(R).max())
+        assert s2 == pytest.approx(s, rel=1e-13)
+        # nonsingular: R R^T symmetric positive definite, and well conditioned
+        # once scaled to a unit diagonal (the stiff EOS spreads its entries
+        # over ~17 decades)
+        A = R @ R.T
+        d = np.sqrt(np.diag(A))
+        ev = np.linalg.eigvalsh(A / np.outer(d, d))
+        assert ev.min() > 1e-3, ev
+        # consistent: tends to the single-state frame, to first order in the jump
+        Rl, _ = o.interface_frame(Ul, Ul, m)
+        errs = []
+        for h in (1e-3, 1e-4):
+            Uh = Ul + h * (Ur - Ul)
+            Rh, _ = o.interface_frame(Ul, Uh, m)
+            errs.append(np.abs(Rh - Rl).max() / np.abs(Rl).max())
+        assert errs[1] < 0.2 * errs[0] + 1e-13, errs
