@@ -292,9 +292,10 @@ typedef struct es_batch es_batch;
 
 /* Check the grids (dim must be 2; every field of es_grid that is not an
  * extent, spacing or length must agree with grids[0]) and allocate the
- * batch: work lists of three region sizes (10, 15, 21 nodes square), the
- * wave-speed partials and two stage buffers per instance for
- * es_step_batched.  The region size defaults to 15, persistent grid. */
+ * batch: work lists of six region shapes (TX x TY nodes on a block: 10 x 10,
+ * 15 x 15, 16 x 15, 15 x 16, 18 x 13 and 21 x 21), the wave-speed partials
+ * and two stage buffers per instance for es_step_batched.  The shape
+ * defaults to 15 x 15 on a persistent grid. */
 int es_batch_create(const es_grid *grids, int count, es_batch **out);
 int es_batch_destroy(es_batch *b);
 
@@ -335,17 +336,19 @@ int es_step_batched(es_batch *b, double cfl, double *const *JU,
                     const double *const *jxi_t, double *dt_dev, void *stream);
 
 /* Autotuner: times stage 0 (output into the batch's own buffers) `reps`
- * times for every region size (10, 15, 21) with a persistent grid and with
- * one block per region, keeps the fastest, and returns it in
- * region_out[0] (size) and region_out[1] (1 = persistent).  Synchronises
- * the stream; call it before capturing a graph. */
+ * times for every region shape with a persistent grid (as many blocks as
+ * fit the device at once) and with one block per region, keeps the fastest,
+ * and returns it in region_out[0] (TX), region_out[1] (TY) and
+ * region_out[2] (1 = persistent).  Synchronises the stream; call it before
+ * capturing a graph. */
 int es_batch_autotune(es_batch *b, const double *const *JU,
                       const double *const *J, const double *const *jxi_x,
                       const double *const *jxi_t, const double *dt_dev,
                       int reps, void *stream, int *region_out);
 
-/* Select a region size (10, 15 or 21) and grid kind by hand. */
-int es_batch_set_tiling(es_batch *b, int region, int persistent);
+/* Select a region shape (one of those of es_batch_create; else ES_EINVAL)
+ * and the grid kind by hand. */
+int es_batch_set_tiling(es_batch *b, int tx, int ty, int persistent);
 
 /* es_status for the batch's status word. */
 int es_batch_status(es_batch *b, void *stream, unsigned *flags, int reset);

@@ -45,13 +45,13 @@ struct es_batch {
     std::vector<Geo> geo_h;
     Geo* geos = nullptr;          // device copy of geo_h
     unsigned* status = nullptr;
-    // work lists of the batched stage, one per region size
-    static constexpr int NVAR = 3;
-    int T[NVAR] = {10, 15, 21};
-    int4* tiles[NVAR] = {nullptr, nullptr, nullptr};
-    int ntiles[NVAR] = {0, 0, 0};
-    int occ[NVAR] = {0, 0, 0};    // resident blocks per CU
-    int var = 1;                  // chosen region size (index into T)
+    // work lists of the batched stage, one per region shape (batch_shape)
+    static constexpr int NVAR = 6;
+    int tx[NVAR] = {}, ty[NVAR] = {};
+    int4* tiles[NVAR] = {};
+    int ntiles[NVAR] = {};
+    int occ[NVAR] = {};           // resident blocks per CU
+    int var = 1;                  // chosen shape (15 x 15 until tuned)
     int persistent = 1;           // grid = resident capacity (1) or one block per region (0)
     // wave-speed work list and partials
     int4* wl = nullptr;
@@ -490,7 +490,7 @@ bool same_scheme(const es_grid& a, const es_grid& b)
 BatchTiling batch_tiling(const es_batch* b)
 {
     BatchTiling tl{};
-    tl.T = b->T[b->var];
+    tl.v = b->var;
     tl.tiles = b->tiles[b->var];
     tl.ntiles = b->ntiles[b->var];
     const long cap = (long)b->occ[b->var] * b->ncu;
@@ -547,17 +547,19 @@ int es_batch_create(const es_grid* grids, int count, es_batch** out)
         rc = ES_EHIP;
     if (!rc && hipMemset(b->status, 0, 4 * sizeof(unsigned)) != hipSuccess) rc = ES_EHIP;
     // region work lists
+    if (batch_nshapes() != es_batch::NVAR) rc = ES_EHIP;
     for (int v = 0; v < es_batch::NVAR && !rc; v++) {
-        const int T = b->T[v];
+        int nt = 0;
+        batch_shape(v, &b->tx[v], &b->ty[v], &nt);
         std::vector<int4> tl;
         for (int i = 0; i < count; i++)
-            for (int oy = 0; oy < b->geo_h[i].n[1]; oy += T)
-                for (int ox = 0; ox < b->geo_h[i].n[0]; ox += T) tl.push_back(make_int4(i, ox, oy, 0));
+            for (int oy = 0; oy < b->geo_h[i].n[1]; oy += b->ty[v])
+                for (int ox = 0; ox < b->geo_h[i].n[0]; ox += b->tx[v]) tl.push_back(make_int4(i, ox, oy, 0));
         b->ntiles[v] = (int)tl.size();
         rc = dalloc(&b->tiles[v], tl.size());
         if (!rc && hipMemcpy(b->tiles[v], tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
             rc = ES_EHIP;
-        if (!rc && batch_occupancy(b->ph.nspec, b->grid0.precision == ES_MIXED, b->ph.recon, T, &b->occ[v]) != hipSuccess)
+        if (!rc && batch_occupancy(b->ph.nspec, b->grid0.precision == ES_MIXED, b->ph.recon, v, &b->occ[v]) != hipSuccess)
             rc = ES_EHIP;
     }
     // wave-speed work list: blocks of about 4096 nodes
@@ -609,10 +611,11 @@ int es_batch_create(const es_grid* grids, int count, es_batch** out)
 int es_batch_destroy(es_batch* b)
 {
     if (!b) return ES_EINVAL;
-    void* bufs[] = {b->geos, b->status, b->wl, b->wfirst, b->part, b->ws, b->tab,
-                    b->tiles[0], b->tiles[1], b->tiles[2]};
+    void* bufs[] = {b->geos, b->status, b->wl, b->wfirst, b->part, b->ws, b->tab};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
+    for (int v = 0; v < es_batch::NVAR; v++)
+        if (b->tiles[v]) (void)hipFree(b->tiles[v]);
     delete b;
     return ES_OK;
 }
@@ -697,17 +700,18 @@ int es_batch_autotune(es_batch* b, const double* const* JU, const double* const*
     b->var = best_var;
     b->persistent = best_pers;
     if (region_out) {
-        region_out[0] = b->T[best_var];
-        region_out[1] = best_pers;
+        region_out[0] = b->tx[best_var];
+        region_out[1] = b->ty[best_var];
+        region_out[2] = best_pers;
     }
     return rc;
 }
 
-int es_batch_set_tiling(es_batch* b, int region, int persistent)
+int es_batch_set_tiling(es_batch* b, int tx, int ty, int persistent)
 {
     if (!b) return ES_EINVAL;
     for (int v = 0; v < es_batch::NVAR; v++)
-        if (b->T[v] == region) {
+        if (b->tx[v] == tx && b->ty[v] == ty) {
             b->var = v;
             b->persistent = persistent ? 1 : 0;
             return ES_OK;

@@ -2,8 +2,8 @@
 // instances of uneven size in one persistent launch; each instance is the
 // semi-discrete scheme of Sections 3.1-3.4 on its own periodic grid.
 //
-// The work list holds square regions of T x T nodes of every instance.  A
-// block takes regions round-robin and, for each,
+// The work list holds regions of TX x TY nodes of every instance (the
+// autotuner picks the shape).  A block takes regions round-robin and, for each,
 //   - stages the node quantities of the region plus a 3-node halo along both
 //     directions (a plus-shaped patch) in LDS once,
 //   - sweeps direction 1 and then direction 2 over the patch with the
@@ -18,7 +18,7 @@
 
 namespace es {
 
-template <int N, int T, int NT, typename R, int RC>
+template <int N, int TX, int TY, int NT, typename R, int RC>
 __global__ void __launch_bounds__(NT)
 k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict__ tiles, int ntiles,
                   BatchTables tb, double ca, double cb, const double* __restrict__ dt_dev,
@@ -26,18 +26,19 @@ k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict_
 {
     constexpr int D = 2;
     constexpr int NC = N + D + 1;
-    constexpr int NE = T + 6;              // patch edge: region + 3-node halo on each side
-    constexpr int NN = NE * NE;
-    constexpr int NI = (T + 1) * T;        // interfaces of one sweep
-    constexpr int NS = T + 4;              // exchange slots per line
-    constexpr int NX = NS * T;
+    constexpr int NEX = TX + 6, NEY = TY + 6;   // patch: region + 3-node halo on each side
+    constexpr int NN = NEX * NEY;
+    // per sweep: TX + 1 interfaces on TY lines (x), TY + 1 on TX lines (y);
+    // exchange slots: along + 4 per line
+    constexpr int NX = ((TX + 4) * TY > (TY + 4) * TX) ? (TX + 4) * TY : (TY + 4) * TX;
     constexpr int NW = NT / 64;
-    static_assert(NI <= NT && 3 * T <= 64 && T * T <= NT && NT % 64 == 0, "region does not fit");
+    static_assert((TX + 1) * TY <= NT && (TY + 1) * TX <= NT && 3 * TX <= 64 && 3 * TY <= 64 && NT % 64 == 0,
+                  "region does not fit");
     __shared__ NodeTile<N, D, NN> S;
-    __shared__ R X[NC][NX];
+    __shared__ R Xbuf[NC * NX];
 
     const int t = threadIdx.x;
-    auto lidx = [](int lx, int ly) { return lx + NE * ly; };
+    auto lidx = [](int lx, int ly) { return lx + NEX * ly; };
     unsigned bad = 0;
 
     for (int w = blockIdx.x; w < ntiles; w += gridDim.x) {
@@ -55,8 +56,8 @@ k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict_
 
         // ---- node quantities of the plus-shaped patch ---------------------
         for (int q = t; q < NN; q += NT) {
-            const int lx = q % NE, ly = q / NE;
-            const bool cx = lx >= 3 && lx < 3 + T, cy = ly >= 3 && ly < 3 + T;
+            const int lx = q % NEX, ly = q / NEX;
+            const bool cx = lx >= 3 && lx < 3 + TX, cy = ly >= 3 && ly < 3 + TY;
             if (!(cx || cy)) continue;                       // corners are never read
             const int gx = ox + lx - 3, gy = oy + ly - 3;
             if (gx >= nx + 3 || gy >= ny + 3) continue;      // beyond a ragged last region
@@ -64,17 +65,21 @@ k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict_
         }
 
         // node owned by this thread in the node phases
-        const int ni = t % T, nj = t / T;
+        const int ni = t % TX, nj = t / TX;
         double acc[NC], accJ = 0.0;
 #pragma unroll
         for (int cc = 0; cc < NC; cc++) acc[cc] = 0.0;
 
         auto sweep = [&](auto kc) {
             constexpr int K = decltype(kc)::value;
+            constexpr int TL = (K == 0) ? TX : TY;     // nodes along the sweep
+            constexpr int TC = (K == 0) ? TY : TX;     // lines of the sweep
+            constexpr int NEL = TL + 6;
+            constexpr int NS = TL + 4;
             // metrics of direction K on the lines of this sweep
-            for (int q = t; q < NE * T; q += NT) {
-                const int lx = (K == 0) ? q % NE : 3 + q % T;
-                const int ly = (K == 0) ? 3 + q / NE : q / T;
+            for (int q = t; q < NEL * TC; q += NT) {
+                const int lx = (K == 0) ? q % NEL : 3 + q % TC;
+                const int ly = (K == 0) ? 3 + q / NEL : q / TC;
                 const int gx = ox + lx - 3, gy = oy + ly - 3;
                 if (gx >= nx + 3 || gy >= ny + 3) continue;
                 const long gi = gidx(gx, gy);
@@ -86,21 +91,22 @@ k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict_
             __syncthreads();
             // line c of the sweep is row oy + c (K = 0) or column ox + c (K = 1);
             // node l of a line sits at patch along-coordinate l
-            auto tidx = [](int l, int c) { return (K == 0) ? (l + NE * (c + 3)) : ((c + 3) + NE * l); };
+            auto tidx = [](int l, int c) { return (K == 0) ? (l + NEX * (c + 3)) : ((c + 3) + NEX * l); };
             auto xidx = [](int s, int c) { return s + NS * c; };
+            R (*X)[NS * TC] = reinterpret_cast<R (*)[NS * TC]>(&Xbuf[0]);
             const int nK = (K == 0) ? nx : ny, nL = (K == 0) ? ny : nx;
             const int o_along = (K == 0) ? ox : oy, o_line = (K == 0) ? oy : ox;
-            const int fi = t % (T + 1), fc = t / (T + 1);
+            const int fi = t % (TL + 1), fc = t / (TL + 1);
             // the interface's right stencil node fi + 5 (patch coordinate) must be loaded
-            const bool f_ok = (t < NI) && (o_line + fc < nL) && (o_along + fi + 2 < nK + 3);
+            const bool f_ok = (t < (TL + 1) * TC) && (o_line + fc < nL) && (o_along + fi + 2 < nK + 3);
             // the acoustic and species fields in two groups in both
             // precisions: the region's right-hand sides stay in registers
             // across the two sweeps, and the FP32 kernel then fits three
             // waves per SIMD (2.0 ms against 2.65 ms per stage)
-            interface_fluxes<N, D, NN, T, T, false, RC, R, 2>(ph, S, X, tidx, xidx,
+            interface_fluxes<N, D, NN, TL, TC, false, RC, R, 2>(ph, S, X, tidx, xidx,
                                                 [&](int c) { return o_line + c < nL; }, fi, fc, f_ok,
                                                 t - (int)((blockIdx.x + w) % NW) * 64);
-            if (t < T * T) {
+            if (t < TX * TY) {
                 const int lo = (K == 0) ? ni : nj, c = (K == 0) ? nj : ni;
                 if (o_along + lo < nK && o_line + c < nL) {
                     const int l = lo + 3;
@@ -127,7 +133,7 @@ k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict_
         sweep(std::integral_constant<int, 1>{});
 
         // ---- Shu-Osher combination, written to the node and its ghost images
-        if (t < T * T && ox + ni < nx && oy + nj < ny) {
+        if (t < TX * TY && ox + ni < nx && oy + nj < ny) {
             const int gx = ox + ni, gy = oy + nj;
             const long gi = gidx(gx, gy);
             const double dt = dt_dev[bi];
@@ -161,39 +167,59 @@ k_stage2d_batched(Phys ph, const Geo* __restrict__ geos, const int4* __restrict_
     if (bad) atomicOr(status, bad);
 }
 
+// the region shapes of the autotuner's search: (TX, TY, threads); every
+// sweep of a shape has at most as many interfaces as threads
+#define ES_BATCH_SHAPES(X) X(0, 10, 10, 128) X(1, 15, 15, 256) X(2, 16, 15, 256) X(3, 15, 16, 256) \
+                           X(4, 18, 13, 256) X(5, 21, 21, 512)
+
+int batch_nshapes() { return 6; }
+
+void batch_shape(int v, int* tx, int* ty, int* nt)
+{
+#define ES_SHAPE(V_, TX_, TY_, NT_) if (v == V_) { *tx = TX_; *ty = TY_; *nt = NT_; return; }
+    ES_BATCH_SHAPES(ES_SHAPE)
+#undef ES_SHAPE
+    *tx = *ty = *nt = 0;
+}
+
 template <int N, typename R, int RC>
-static hipError_t launch_variant(int T, const Phys& ph, const Geo* geos, const BatchTiling& tl,
+static hipError_t launch_variant(int v, const Phys& ph, const Geo* geos, const BatchTiling& tl,
                                  const BatchTables& tb, double ca, double cb, const double* dt_dev,
                                  unsigned* status, hipStream_t s)
 {
-#define ES_BATCH_CASE(T_, NT_)                                                                       \
-    if (T == T_) {                                                                                   \
-        hipLaunchKernelGGL((k_stage2d_batched<N, T_, NT_, R, RC>), dim3(tl.blocks), dim3(NT_), 0, s, ph, \
-                           geos, tl.tiles, tl.ntiles, tb, ca, cb, dt_dev, status);                   \
+#define ES_BATCH_CASE(V_, TX_, TY_, NT_)                                                             \
+    if (v == V_) {                                                                                   \
+        hipLaunchKernelGGL((k_stage2d_batched<N, TX_, TY_, NT_, R, RC>), dim3(tl.blocks), dim3(NT_), 0, s, \
+                           ph, geos, tl.tiles, tl.ntiles, tb, ca, cb, dt_dev, status);               \
         return hipGetLastError();                                                                    \
     }
-    ES_BATCH_CASE(10, 128)
-    ES_BATCH_CASE(15, 256)
-    ES_BATCH_CASE(21, 512)
+    ES_BATCH_SHAPES(ES_BATCH_CASE)
 #undef ES_BATCH_CASE
     return hipErrorInvalidValue;
 }
 
-int batch_threads(int T) { return T == 10 ? 128 : (T == 15 ? 256 : (T == 21 ? 512 : 0)); }
-
-hipError_t batch_occupancy(int nspec, int mixed, int recon, int T, int* blocks_per_cu)
+template <int N, typename R, int RC>
+static hipError_t occupancy_variant(int v, int* blocks_per_cu)
 {
-#define ES_OCC1(N_, R_, T_, NT_, RC_)                                                                \
-    if (nspec == N_ && (mixed != 0) == std::is_same<R_, float>::value && T == T_ && recon == RC_)     \
+#define ES_OCC_CASE(V_, TX_, TY_, NT_)                                                               \
+    if (v == V_)                                                                                     \
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,                          \
-                                                            k_stage2d_batched<N_, T_, NT_, R_, RC_>, \
-                                                            NT_, 0);
-#define ES_OCC(N_, R_, RC_) ES_OCC1(N_, R_, 10, 128, RC_) ES_OCC1(N_, R_, 15, 256, RC_) ES_OCC1(N_, R_, 21, 512, RC_)
-    ES_OCC(1, double, 0) ES_OCC(2, double, 0) ES_OCC(1, float, 0) ES_OCC(2, float, 0)
-    ES_OCC(1, double, 1) ES_OCC(2, double, 1)   // classical WENO5: FP64 only
-#undef ES_OCC
-#undef ES_OCC1
+                                                            k_stage2d_batched<N, TX_, TY_, NT_, R, RC>, NT_, 0);
+    ES_BATCH_SHAPES(ES_OCC_CASE)
+#undef ES_OCC_CASE
     return hipErrorInvalidValue;
+}
+
+hipError_t batch_occupancy(int nspec, int mixed, int recon, int v, int* blocks_per_cu)
+{
+    if (recon == 1) {   // classical WENO5: FP64 only
+        if (mixed) return hipErrorInvalidValue;
+        return nspec == 1 ? occupancy_variant<1, double, 1>(v, blocks_per_cu)
+                          : occupancy_variant<2, double, 1>(v, blocks_per_cu);
+    }
+    if (nspec == 1)
+        return mixed ? occupancy_variant<1, float, 0>(v, blocks_per_cu) : occupancy_variant<1, double, 0>(v, blocks_per_cu);
+    return mixed ? occupancy_variant<2, float, 0>(v, blocks_per_cu) : occupancy_variant<2, double, 0>(v, blocks_per_cu);
 }
 
 hipError_t launch_stage_batched(const Phys& ph, const Geo* geos, int mixed, const BatchTiling& tl,
@@ -203,14 +229,14 @@ hipError_t launch_stage_batched(const Phys& ph, const Geo* geos, int mixed, cons
     if (tl.ntiles == 0) return hipSuccess;
     if (ph.recon == 1) {   // classical WENO5: FP64 only (checked at create)
         if (mixed) return hipErrorInvalidValue;
-        return ph.nspec == 1 ? launch_variant<1, double, 1>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s)
-                             : launch_variant<2, double, 1>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s);
+        return ph.nspec == 1 ? launch_variant<1, double, 1>(tl.v, ph, geos, tl, tb, ca, cb, dt_dev, status, s)
+                             : launch_variant<2, double, 1>(tl.v, ph, geos, tl, tb, ca, cb, dt_dev, status, s);
     }
     if (ph.nspec == 1)
-        return mixed ? launch_variant<1, float, 0>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s)
-                     : launch_variant<1, double, 0>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s);
-    return mixed ? launch_variant<2, float, 0>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s)
-                 : launch_variant<2, double, 0>(tl.T, ph, geos, tl, tb, ca, cb, dt_dev, status, s);
+        return mixed ? launch_variant<1, float, 0>(tl.v, ph, geos, tl, tb, ca, cb, dt_dev, status, s)
+                     : launch_variant<1, double, 0>(tl.v, ph, geos, tl, tb, ca, cb, dt_dev, status, s);
+    return mixed ? launch_variant<2, float, 0>(tl.v, ph, geos, tl, tb, ca, cb, dt_dev, status, s)
+                 : launch_variant<2, double, 0>(tl.v, ph, geos, tl, tb, ca, cb, dt_dev, status, s);
 }
 
 }  // namespace es

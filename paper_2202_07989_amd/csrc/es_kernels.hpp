@@ -108,16 +108,19 @@ struct BatchTables {
     double* const* Jo;
 };
 
-// one region size of the batched stage: the work list and the grid
+// one region shape of the batched stage: the work list and the grid
 struct BatchTiling {
-    int T;                // region edge (10, 15 or 21)
+    int v;                // shape index (batch_shape)
     int blocks;           // launch grid (persistent when below ntiles)
     const int4* tiles;    // (instance, x origin, y origin, 0) per region
     int ntiles;
 };
 
-int batch_threads(int T);
-hipError_t batch_occupancy(int nspec, int mixed, int recon, int T, int* blocks_per_cu);
+// region shapes of the batched stage: v = 0 .. batch_nshapes() - 1 has
+// TX x TY nodes on nt threads
+int batch_nshapes();
+void batch_shape(int v, int* tx, int* ty, int* nt);
+hipError_t batch_occupancy(int nspec, int mixed, int recon, int v, int* blocks_per_cu);
 hipError_t launch_stage_batched(const Phys& ph, const Geo* geos, int mixed, const BatchTiling& tl,
                                 const BatchTables& tb, double ca, double cb, const double* dt_dev,
                                 unsigned* status, hipStream_t s);

@@ -75,7 +75,7 @@ _SIGS = {
     "max_wavespeed_batched": [_P, _P, _P, _P, C.c_double, _P, _P, _P],
     "es_step_batched": [_P, C.c_double, _P, _P, _P, _P, _P, _P],
     "es_batch_autotune": [_P, _P, _P, _P, _P, _P, C.c_int, _P, _P],
-    "es_batch_set_tiling": [_P, C.c_int, C.c_int],
+    "es_batch_set_tiling": [_P, C.c_int, C.c_int, C.c_int],
     "es_batch_status": [_P, _P, C.POINTER(C.c_uint), C.c_int],
 }
 
@@ -342,14 +342,16 @@ class Batch:
 
     def es_batch_autotune(self, JU, J, jxi_x, jxi_t, dt_dev, reps=3, stream=None):
         tabs = [_table(a) for a in (JU, J, jxi_x, jxi_t)]
-        out = (C.c_int * 2)()
+        out = (C.c_int * 3)()
         _check("es_batch_autotune", lib.es_batch_autotune(
             self.h, tabs[0].ptr, tabs[1].ptr, tabs[2].ptr, tabs[3].ptr if tabs[3] is not None else None,
             _ptr(dt_dev), int(reps), _stream(stream), C.cast(out, C.c_void_p)))
-        return out[0], out[1]
+        return (out[0], out[1]), out[2]
 
     def es_batch_set_tiling(self, region, persistent=True):
-        _check("es_batch_set_tiling", lib.es_batch_set_tiling(self.h, int(region), int(bool(persistent))))
+        """region: (TX, TY), one of the batch's region shapes."""
+        tx, ty = region
+        _check("es_batch_set_tiling", lib.es_batch_set_tiling(self.h, int(tx), int(ty), int(bool(persistent))))
 
     def es_batch_status(self, stream=None, reset=False):
         f = C.c_uint()

@@ -4,10 +4,10 @@ CPU FP64 oracle.
 Each instance of a batch runs the same scheme as es_rk_stage on its own
 grid, with the same per-interface arithmetic in the same order, so the
 batched stage must equal the single-instance stage bit for bit for every
-region size and grid kind; against the oracle the FP64 bar (1e-11 of the
+region shape and grid kind; against the oracle the FP64 bar (1e-11 of the
 state scale) applies, ghost layers included (the batched stage writes the
-periodic ghost images itself).  Sizes are ragged against the 10/15/21
-regions."""
+periodic ghost images itself).  Sizes are ragged against the region
+shapes (10 x 10 .. 21 x 21)."""
 import numpy as np
 import pytest
 
@@ -68,8 +68,11 @@ def test_wavespeed_batched(batch_inputs):
         assert hd[k] == pytest.approx(t, rel=1e-13)
 
 
+SHAPES = [(10, 10), (15, 15), (16, 15), (15, 16), (18, 13), (21, 21)]
+
+
 @pytest.mark.parametrize("precision", [es.ES_FP64, es.ES_MIXED])
-@pytest.mark.parametrize("region,persistent", [(10, 1), (15, 1), (21, 1), (15, 0)])
+@pytest.mark.parametrize("region,persistent", [(r, 1) for r in SHAPES] + [((15, 15), 0), ((18, 13), 0)])
 def test_stage_batched_equals_single(batch_inputs, precision, region, persistent):
     say(f"[batch stage] precision={precision} region={region} persistent={persistent}")
     inst = batch_inputs
@@ -174,9 +177,9 @@ def test_autotune_picks_a_variant_with_equal_results(batch_inputs):
     gx = [dev(d["jx"]) for d in inst]
     dt_dev = torch.tensor(oracle_dt(inst, 0.4), dtype=torch.float64, device="cuda")
     region, pers = b.es_batch_autotune(gU, gJ, gx, None, dt_dev, reps=2)
-    assert region in (10, 15, 21) and pers in (0, 1)
+    assert region in SHAPES and pers in (0, 1)
     outs = []
-    for r, p in ((region, pers), (15, 1)):
+    for r, p in ((region, pers), ((15, 15), 1)):
         b.es_batch_set_tiling(r, p)
         oU = [torch.zeros_like(t) for t in gU]
         oJ = [torch.zeros_like(t) for t in gJ]
