@@ -532,4 +532,21 @@ __device__ __forceinline__ double block_reduce(double v)
     return r;
 }
 
+// Tile of this block for the z-marching and plane-tile kernels.  Consecutive
+// blocks are dealt round-robin to the 8 XCDs, each with its own L2; this
+// permutation gives each XCD a contiguous run of tiles (a whole z chunk of
+// (x, y) tiles at the usual grids), so the in-plane neighbour rows that
+// adjacent tiles read from each other come from one L2 (the 3D metrics take
+// 8% less time).  Any grid size: the first nb % 8 XCDs take one tile more.
+__device__ __forceinline__ void xcd_tile(int& bx, int& by, int& bz)
+{
+    const unsigned gx = gridDim.x, gy = gridDim.y, nb = gx * gy * gridDim.z;
+    const unsigned L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned q = nb / 8, r = nb % 8, c = L % 8;
+    const unsigned T = c * q + (c < r ? c : r) + L / 8;
+    bx = (int)(T % gx);
+    by = (int)((T / gx) % gy);
+    bz = (int)(T / (gx * gy));
+}
+
 }  // namespace es

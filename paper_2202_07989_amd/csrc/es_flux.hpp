@@ -45,17 +45,18 @@ __device__ __forceinline__ void mixture(const Phys& ph, const NodeTile<N, D, NN>
 // p_inf ({v}.n + n_t) with the two p_inf {v}.n terms cancelled by hand, and
 // Pi is formed in FP64 in both precisions: with a stiffened gas Pi and
 // p_inf are both ~p_inf, so neither difference may be left to FP32.
+// (M: the halved metrics of the direction, indexed like the tile)
 template <int N, int D, int NN, typename R>
-__device__ __forceinline__ void ec_pair(const Phys& ph, const NodeTile<N, D, NN>& S, int ia, int ib,
-                                        R* F)
+__device__ __forceinline__ void ec_pair(const Phys& ph, const NodeTile<N, D, NN>& S, const double (*M)[NN],
+                                        int ia, int ib, R* F)
 {
     constexpr int NC = N + D + 1;
-    const R nt = R(S.m[0][ia]) + R(S.m[0][ib]);
+    const R nt = R(M[0][ia]) + R(M[0][ib]);
     R n[D], vm[D];
     R vdn = R(0), v2 = R(0);
 #pragma unroll
     for (int j = 0; j < D; j++) {
-        n[j] = R(S.m[1 + j][ia]) + R(S.m[1 + j][ib]);
+        n[j] = R(M[1 + j][ia]) + R(M[1 + j][ib]);
         const R va = R(S.v[j][ia]), vb = R(S.v[j][ib]);
         vm[j] = R(0.5) * (va + vb);
         v2 += va * va + vb * vb;
@@ -92,18 +93,18 @@ __device__ __forceinline__ void ec_pair(const Phys& ph, const NodeTile<N, D, NN>
 // i-2..i+3.  Interface metrics, averages and R follow Section 3.4.  MG: the
 // acoustic and species fields in one group or two.
 template <int N, int D, int NN, int RC, typename R, int MG>
-__device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D, NN>& S,
+__device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D, NN>& S, const double (*M)[NN],
                                             const int st[6], const Weno<R>& Wc, R* Dout)
 {
     constexpr int NC = N + D + 1;
     const int iL = st[2], iR = st[3];
     // interface metric: mean of the two nodes
     R n[D];
-    const R nt = R(S.m[0][iL]) + R(S.m[0][iR]);
+    const R nt = R(M[0][iL]) + R(M[0][iR]);
     R nn2 = R(0);
 #pragma unroll
     for (int j = 0; j < D; j++) {
-        n[j] = R(S.m[1 + j][iL]) + R(S.m[1 + j][iR]);
+        n[j] = R(M[1 + j][iL]) + R(M[1 + j][iR]);
         nn2 += n[j] * n[j];
     }
     const bool nz = nn2 > R(0);
@@ -338,11 +339,16 @@ __device__ __forceinline__ void dissipation(const Phys& ph, const NodeTile<N, D,
 // this (it holds barriers).
 // (MG: the dissipation's acoustic and species fields in one group or two;
 // two in FP64, where they keep the sweeps within fewer registers)
-template <int N, int D, int NN, int TL, int TC, bool XALIAS, int RC, typename R,
-          int MG = (sizeof(R) == 8 ? 2 : 1), typename LI, typename XI, typename LOK>
-__device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<N, D, NN>& S,
-                                                 R (*X)[(TL + 4) * TC], LI lidx, XI xidx,
-                                                 LOK line_ok, int fi, int fc, bool f_ok, int hid)
+// interface_fluxes_m is the general form: the metrics M of the direction
+// are passed in, X rows are XS slots long, and the tile's TL and TC may be
+// run-time values (a block that sweeps two directions at once picks them per
+// wave); interface_fluxes takes the tile's own metrics and fixed sizes.
+template <int N, int D, int NN, int XS, bool XALIAS, int RC, typename R, int MG, typename LI, typename XI,
+          typename LOK>
+__device__ __forceinline__ void interface_fluxes_m(const Phys& ph, const NodeTile<N, D, NN>& S,
+                                                   const double (*M)[NN], R (*X)[XS], LI lidx, XI xidx,
+                                                   LOK line_ok, int fi, int fc, bool f_ok, int hid,
+                                                   int TL, int TC)
 {
     constexpr int NC = N + D + 1;
     const R a1 = R(ph.alpha[0]), a2 = R(ph.alpha[1]), a3 = R(ph.alpha[2]);
@@ -358,16 +364,16 @@ __device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<
             int st[6];
 #pragma unroll
             for (int q = 0; q < 6; q++) st[q] = lidx(fl - 2 + q, fc);
-            dissipation<N, D, NN, RC, R, MG>(ph, S, st, Wc, G);
+            dissipation<N, D, NN, RC, R, MG>(ph, S, M, st, Wc, G);
         } else {
 #pragma unroll
             for (int cc = 0; cc < NC; cc++) G[cc] = R(0);
         }
-        ec_pair<N, D, NN, R>(ph, S, lidx(fl, fc), lidx(fl + 1, fc), F);
+        ec_pair<N, D, NN, R>(ph, S, M, lidx(fl, fc), lidx(fl + 1, fc), F);
 #pragma unroll
         for (int cc = 0; cc < NC; cc++) G[cc] = a1 * F[cc] - G[cc];
         if (a2 != R(0)) {
-            ec_pair<N, D, NN, R>(ph, S, lidx(fl, fc), lidx(fl + 2, fc), F);
+            ec_pair<N, D, NN, R>(ph, S, M, lidx(fl, fc), lidx(fl + 2, fc), F);
         } else {
 #pragma unroll
             for (int cc = 0; cc < NC; cc++) F[cc] = R(0);
@@ -375,7 +381,7 @@ __device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<
 #pragma unroll
         for (int cc = 0; cc < NC; cc++) A2[cc] = a2 * F[cc];
         if (a3 != R(0)) {
-            ec_pair<N, D, NN, R>(ph, S, lidx(fl, fc), lidx(fl + 3, fc), F);
+            ec_pair<N, D, NN, R>(ph, S, M, lidx(fl, fc), lidx(fl + 3, fc), F);
         } else {
 #pragma unroll
             for (int cc = 0; cc < NC; cc++) F[cc] = R(0);
@@ -393,7 +399,7 @@ __device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<
         const R am = (h == 2) ? a2 : a3;
         hslot = (h == 0) ? 0 : ((h == 1) ? 1 : TL + 3);
         if (line_ok(hc) && am != R(0)) {
-            ec_pair<N, D, NN, R>(ph, S, lidx(h == 0 ? 0 : 1, hc), lidx(h == 1 ? 4 : 3, hc), Bh);
+            ec_pair<N, D, NN, R>(ph, S, M, lidx(h == 0 ? 0 : 1, hc), lidx(h == 1 ? 4 : 3, hc), Bh);
         } else {
 #pragma unroll
             for (int cc = 0; cc < NC; cc++) Bh[cc] = R(0);
@@ -441,6 +447,16 @@ __device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<
         }
     }
     __syncthreads();
+}
+
+template <int N, int D, int NN, int TL, int TC, bool XALIAS, int RC, typename R,
+          int MG = (sizeof(R) == 8 ? 2 : 1), typename LI, typename XI, typename LOK>
+__device__ __forceinline__ void interface_fluxes(const Phys& ph, const NodeTile<N, D, NN>& S,
+                                                 R (*X)[(TL + 4) * TC], LI lidx, XI xidx,
+                                                 LOK line_ok, int fi, int fc, bool f_ok, int hid)
+{
+    interface_fluxes_m<N, D, NN, (TL + 4) * TC, XALIAS, RC, R, MG>(ph, S, S.m, X, lidx, xidx, line_ok, fi, fc,
+                                                                  f_ok, hid, TL, TC);
 }
 
 // primitive node quantities of node gi of (JU, J) into tile slot li; returns

@@ -304,22 +304,6 @@ __device__ __forceinline__ double xs_at(const double* xn, const double* disp, do
 //   the neighbouring rows are read by other waves at the same time and come
 //   from the caches, and with no LDS and no barrier every wave walks at its
 //   own pace.  Both shapes were the faster of the two designs for their pass.
-// Tile of this block for the z-marching kernels.  Consecutive blocks are
-// dealt round-robin to the 8 XCDs, each with its own L2; this permutation
-// gives each XCD a contiguous run of tiles (a whole z chunk of (x, y) tiles
-// at the usual grids), so the in-plane neighbour rows that adjacent tiles
-// read from each other come from one L2 (the 3D metrics take 8% less time).
-// Any grid size: the first nb % 8 XCDs take one tile more.
-__device__ __forceinline__ void xcd_tile(int& bx, int& by, int& bz)
-{
-    const unsigned gx = gridDim.x, gy = gridDim.y, nb = gx * gy * gridDim.z;
-    const unsigned L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-    const unsigned q = nb / 8, r = nb % 8, c = L % 8;
-    const unsigned T = c * q + (c < r ? c : r) + L / 8;
-    bx = (int)(T % gx);
-    by = (int)((T / gx) % gy);
-    bz = (int)(T / (gx * gy));
-}
 constexpr int MT = 16;
 constexpr int MH = MT + 6;
 constexpr int MX = 64, MY = 4;
@@ -428,6 +412,7 @@ k_metric3(Geo g, Phys ph, const double* __restrict__ disp, const double* __restr
     const int zc0 = g.ng + bz * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
     if (x >= g.ng + g.n[0] || y >= g.ng + g.n[1]) return;
     const double dt = dt_dev ? *dt_dev : 0.0;
+    const double idt = dt > 0.0 ? 1.0 / dt : 0.0;   // mesh velocity = disp / dt
     const double al[3] = {ph.alpha[0], ph.alpha[1], ph.alpha[2]};
     const double s01 = g.idxi[0] * g.idxi[1], s12 = g.idxi[1] * g.idxi[2], s20 = g.idxi[2] * g.idxi[0];
     const long sy = np0;
@@ -476,7 +461,7 @@ k_metric3(Geo g, Phys ph, const double* __restrict__ disp, const double* __restr
             double w[3] = {0.0, 0.0, 0.0};
             if (disp && dt > 0.0)
 #pragma unroll
-                for (int j = 0; j < 3; j++) w[j] = disp[j * P + i] / dt;
+                for (int j = 0; j < 3; j++) w[j] = disp[j * P + i] * idt;
 #pragma unroll
             for (int k = 0; k < 3; k++) {
                 double nt = 0.0;
@@ -515,7 +500,7 @@ __device__ __forceinline__ void metric2_node(const Geo& g, const Phys& ph, const
         nt[k] = 0.0;
         if (disp && dt > 0.0)
 #pragma unroll
-            for (int j = 0; j < 2; j++) nt[k] -= (disp[j * P + i] / dt) * M[k][j];
+            for (int j = 0; j < 2; j++) nt[k] -= (disp[j * P + i] * (1.0 / dt)) * M[k][j];
     }
 }
 
@@ -567,13 +552,14 @@ __global__ void k_vcl(Geo g, const double* __restrict__ disp, const double* __re
     const int D = g.dim;
     const long nint = n_interior(g);
     const double dt = dt_dev ? *dt_dev : 0.0;
+    const double idt = dt > 0.0 ? 1.0 / dt : 0.0;   // mesh velocity = disp / dt
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nint; q += (long)gridDim.x * blockDim.x) {
         int i0, i1, i2;
         const long i = interior_node(g, q, i0, i1, i2);
         for (int k = 0; k < D; k++) {
             double nt = 0.0;
             if (disp && dt > 0.0)
-                for (int j = 0; j < D; j++) nt -= (disp[j * P + i] / dt) * jxx[(k * D + j) * P + i];
+                for (int j = 0; j < D; j++) nt -= (disp[j * P + i] * idt) * jxx[(k * D + j) * P + i];
             jxt[k * P + i] = nt;
         }
     }
@@ -959,25 +945,28 @@ __device__ __forceinline__ double sigma_of(const Phys& ph, const double* JU, con
 {
     if (SIG == 2 && sig == 5) return phi[i];
     const double Jq = Jv[i];
-    if (SIG == 2 && sig == 4) {
+    if (SIG == 2 && sig == 4) {   // |v| = |J rho v| / (J rho)
         double r = 0.0, m2 = 0.0;
 #pragma unroll
-        for (int l = 0; l < N; l++) r += JU[l * P + i] / Jq;
+        for (int l = 0; l < N; l++) r += JU[l * P + i];
 #pragma unroll
         for (int j = 0; j < D; j++) {
-            const double vj = (JU[(N + j) * P + i] / Jq) / r;
-            m2 += vj * vj;
+            const double mj = JU[(N + j) * P + i];
+            m2 += mj * mj;
         }
-        return sqrt(m2);
+        return sqrt(m2) * rcp(r);
     }
+    // densities: one reciprocal of J (the monitor gradient evaluates sigma
+    // five times per node)
+    const double iJ = rcp(Jq);
     if (sig == 0) {
         double r = 0.0;
 #pragma unroll
-        for (int l = 0; l < N; l++) r += JU[l * P + i] / Jq;
+        for (int l = 0; l < N; l++) r += JU[l * P + i] * iJ;
         return r;
     }
-    if (sig == 1) return JU[i] / Jq;
-    if (sig == 2 || SIG == 0) return JU[(N > 1 ? 1 : 0) * P + i] / Jq;
+    if (sig == 1) return JU[i] * iJ;
+    if (sig == 2 || SIG == 0) return JU[(N > 1 ? 1 : 0) * P + i] * iJ;
     NodeState<N, D> s;
     load_state<N, D>(ph, JU, Jv, P, i, s);
     return s.p;
@@ -1256,25 +1245,31 @@ __global__ void k_filter(Geo g, const double* __restrict__ in, double* __restric
 template <int D>
 __device__ __forceinline__ void jacobi_node(const Geo& g, const double* th, const double* xa, long i, double* xn)
 {
+    // Theta_{k+-1/2} / dxi_k^2, and one reciprocal of the denominator the D
+    // coordinates share
     const long P = g.P;
-    double tp[D], tm[D], ih2[D];
+    double tp[D], tm[D];
+    double den = 0.0;
 #pragma unroll
     for (int k = 0; k < D; k++) {
         const long st = dir_stride(g, k);
+        const double w2 = 1.0 / (g.dxi[k] * g.dxi[k]);
         tp[k] = 0.5 * (th[i] + th[i + st]);
         tm[k] = 0.5 * (th[i] + th[i - st]);
-        ih2[k] = g.dxi[k] * g.dxi[k];
+        tp[k] *= w2;
+        tm[k] *= w2;
+        den += tp[k] + tm[k];
     }
+    const double iden = rcp(den);
 #pragma unroll
     for (int c = 0; c < D; c++) {
-        double num = 0.0, den = 0.0;
+        double num = 0.0;
 #pragma unroll
         for (int k = 0; k < D; k++) {
             const long st = dir_stride(g, k);
-            num += (tp[k] * xa[c * P + i + st] + tm[k] * xa[c * P + i - st]) / ih2[k];
-            den += (tp[k] + tm[k]) / ih2[k];
+            num += tp[k] * xa[c * P + i + st] + tm[k] * xa[c * P + i - st];
         }
-        xn[c] = num / den;
+        xn[c] = num * iden;
     }
 }
 
@@ -1335,9 +1330,11 @@ k_jacobi3(Geo g, const double* __restrict__ th, const double* __restrict__ xa, d
     const int zc0 = g.ng + bz * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
     const bool in = x < g.ng + g.n[0] && y < g.ng + g.n[1];
     const long sy = np0, sz = (long)np0 * np1;
-    double ih2[3];
+    // weights 1/dxi_k^2, formed once: the sweep then takes one reciprocal
+    // per node (the denominator is common to the three coordinates)
+    double w2[3];
 #pragma unroll
-    for (int k = 0; k < 3; k++) ih2[k] = g.dxi[k] * g.dxi[k];
+    for (int k = 0; k < 3; k++) w2[k] = 1.0 / (g.dxi[k] * g.dxi[k]);
     double r = 0.0;
     if (in && zc0 < zc1) {
         long i = ((long)zc0 * np1 + y) * np0 + x;
@@ -1360,17 +1357,21 @@ k_jacobi3(Geo g, const double* __restrict__ th, const double* __restrict__ xa, d
             tm[1] = 0.5 * (t0 + th[i - sy]);
             tp[2] = 0.5 * (t0 + tp1);
             tm[2] = 0.5 * (t0 + tm1);
+            double den = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                tp[k] *= w2[k];
+                tm[k] *= w2[k];
+                den += tp[k] + tm[k];
+            }
+            const double iden = rcp(den);
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 const double* xc = xa + c * P + i;
-                double num = 0.0, den = 0.0;
-                num += (tp[0] * xc[1] + tm[0] * xc[-1]) / ih2[0];
-                den += (tp[0] + tm[0]) / ih2[0];
-                num += (tp[1] * xc[sy] + tm[1] * xc[-sy]) / ih2[1];
-                den += (tp[1] + tm[1]) / ih2[1];
-                num += (tp[2] * xp1[c] + tm[2] * xm1[c]) / ih2[2];
-                den += (tp[2] + tm[2]) / ih2[2];
-                const double xn = num / den;
+                double num = tp[0] * xc[1] + tm[0] * xc[-1];
+                num += tp[1] * xc[sy] + tm[1] * xc[-sy];
+                num += tp[2] * xp1[c] + tm[2] * xm1[c];
+                const double xn = num * iden;
                 xb[c * P + i] = xn;
                 r = fmax(r, fabs(xn - x0[c]));
             }

@@ -148,6 +148,127 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
     }
 }
 
+// The x and y directions of a 3D grid in one launch.  A block of 512
+// threads owns a TX x TY tile of one z plane: it stages the node quantities
+// of the tile plus a 3-node halo along x and y (a plus-shaped patch; the
+// corners are never read) and the halved metrics of both directions in LDS
+// once, then waves 0-3 build the x fluxes of the tile's TY rows and waves
+// 4-7 the y fluxes of its TX columns at the same time, each with the
+// interface scheme of interface_fluxes.  A node's output is the x
+// difference plus the y difference, each rounded on its own as the two
+// separate sweeps round them, so the sum equals the x-sweep-then-y-sweep
+// accumulation bit for bit; the z sweep then adds its own term.  Against the
+// two separate sweeps this loads 1.8 instead of 2.6 nodes per owned node and
+// skips the accumulator's round trip through memory.  LDS: 70 KB at
+// 16 x 15 with two species, two blocks (four waves per SIMD) per compute
+// unit.
+template <int N, int TX, int TY, int RC>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_rhs_xy(Phys ph, Geo g, const double* __restrict__ JU, const double* __restrict__ Jv,
+         const double* __restrict__ jxx, const double* __restrict__ jxt, double* __restrict__ accU,
+         double* __restrict__ accJ, const double* __restrict__ tdiv, unsigned* __restrict__ status)
+{
+    using R = double;
+    constexpr int D = 3;
+    constexpr int NT = 512;
+    constexpr int NC = N + D + 1;
+    constexpr int NEX = TX + 6, NEY = TY + 6;
+    constexpr int NN = NEX * NEY;
+    constexpr int XSX = (TX + 4) * TY, XSY = (TY + 4) * TX;    // exchange slots per component
+    constexpr int XS = XSX > XSY ? XSX : XSY;
+    static_assert((TX + 1) * TY <= NT / 2 && (TY + 1) * TX <= NT / 2 && 3 * TX <= 64 && 3 * TY <= 64,
+                  "tile does not fit the block");
+    __shared__ NodeTile<N, D, NN> S;     // S.m: the x metrics
+    __shared__ double My[D + 1][NN];     // the y metrics
+    static_assert(sizeof(R) * 2 * NC * XS <= sizeof(S) - sizeof(S.m), "exchange does not fit the tile");
+    R (*Xb)[XS] = reinterpret_cast<R (*)[XS]>(&S.rho[0][0]);   // x rows 0..NC-1, y rows NC..2NC-1
+
+    const long P = g.P;
+    const int ng = g.ng, np0 = g.np[0], np1 = g.np[1];
+    const int nx = g.n[0], ny = g.n[1];
+    int bx, by, bz;
+    xcd_tile(bx, by, bz);
+    const int ox = bx * TX, oy = by * TY;
+    // padded index of patch node (0, 0), at interior (ox - 3, oy - 3) of plane bz
+    const long base = ((long)(ng + bz) * np1 + (oy + ng - 3)) * np0 + (ox + ng - 3);
+    const int t = threadIdx.x;
+
+    // ---- node quantities and metrics of the patch -------------------------
+    unsigned bad = 0;
+    for (int q = t; q < NN; q += NT) {
+        const int lx = q % NEX, ly = q / NEX;
+        const bool cx = lx >= 3 && lx < 3 + TX, cy = ly >= 3 && ly < 3 + TY;
+        if (!(cx || cy)) continue;                                        // corners
+        if (ox + lx - 3 + ng >= np0 || oy + ly - 3 + ng >= np1) continue;  // beyond a ragged tile
+        bad |= node_state<N, D, NN>(ph, S, q, JU, Jv, P, base + (long)ly * np0 + lx);
+    }
+    if (bad) atomicOr(status, bad);
+    const double itd = tdiv ? 1.0 / *tdiv : 1.0;
+    for (int q = t; q < NEX * TY + TX * NEY; q += NT) {
+        const bool ydir = q >= NEX * TY;
+        const int u = ydir ? q - NEX * TY : q;
+        const int lx = ydir ? 3 + u % TX : u % NEX;
+        const int ly = ydir ? u / TX : 3 + u / NEX;
+        if (ox + lx - 3 + ng >= np0 || oy + ly - 3 + ng >= np1) continue;
+        const long gi = base + (long)ly * np0 + lx;
+        const int K = ydir ? 1 : 0;
+        double (*Mk)[NN] = ydir ? My : S.m;
+        const int li = lx + NEX * ly;
+        Mk[0][li] = jxt ? 0.5 * (jxt[(long)K * P + gi] * itd) : 0.0;
+#pragma unroll
+        for (int j = 0; j < D; j++) Mk[1 + j][li] = 0.5 * jxx[(long)(K * D + j) * P + gi];
+    }
+    __syncthreads();
+
+    // ---- interface fluxes: x in waves 0-3, y in waves 4-7 ------------------
+    // x: interface fi of row fc (along-fastest, so a wave reads consecutive
+    // nodes of a row); y: interface fi of column fc (column-fastest)
+    // the direction is uniform over a wave: read it from the first lane so
+    // that everything derived from it lives in scalar registers
+    const bool ydir = __builtin_amdgcn_readfirstlane(t / (NT / 2)) != 0;
+    const int u = t & (NT / 2 - 1);
+    const int TL = ydir ? TY : TX, TC = ydir ? TX : TY;
+    const int fi = ydir ? u / TX : u % (TX + 1);
+    const int fc = ydir ? u % TX : u / (TX + 1);
+    const int o_along = ydir ? oy : ox, o_line = ydir ? ox : oy;
+    const int n_line = ydir ? nx : ny, np_along = ydir ? np1 : np0;
+    const bool f_ok = (u < (TL + 1) * TC) && (o_line + fc < n_line) && (o_along + fi + 2 + ng < np_along);
+    const int sl = ydir ? NEX : 1, sc = ydir ? 1 : NEX, l0 = ydir ? 3 : 3 * NEX;
+    const int xl = ydir ? TX : 1, xc = ydir ? 1 : TX + 4;
+    interface_fluxes_m<N, D, NN, XS, true, RC, R, 2>(
+        ph, S, ydir ? My : S.m, ydir ? Xb + NC : Xb, [=](int l, int c) { return l0 + l * sl + c * sc; },
+        [=](int s, int c) { return s * xl + c * xc; }, [=](int c) { return o_line + c < n_line; }, fi, fc,
+        f_ok, u - (int)(blockIdx.x & 3) * 64, TL, TC);
+
+    // ---- node outputs: x difference + y difference -------------------------
+    if (t < TX * TY) {
+        const int ni = t % TX, nj = t / TX;
+        if (ox + ni < nx && oy + nj < ny) {
+            const long gi = base + (long)(nj + 3) * np0 + (ni + 3);
+            auto lx_ = [](int l, int c) { return l + NEX * (c + 3); };
+            auto ly_ = [](int l, int c) { return (c + 3) + NEX * l; };
+            double gx = 0.0, gy = 0.0;
+#pragma unroll
+            for (int m = 1; m <= 3; m++) {
+                gx += ph.alpha[m - 1] * (S.m[0][lx_(ni + 3 + m, nj)] - S.m[0][lx_(ni + 3 - m, nj)]);
+                gy += ph.alpha[m - 1] * (My[0][ly_(nj + 3 + m, ni)] - My[0][ly_(nj + 3 - m, ni)]);
+            }
+            const double hx = g.idxi[0], hy = g.idxi[1];
+            const R (*Xx)[XS] = Xb;
+            const R (*Xy)[XS] = Xb + NC;
+#pragma unroll
+            for (int cc = 0; cc < NC; cc++) {
+                const double dx = -(double)(Xx[cc][(ni + 2) + (TX + 4) * nj] - Xx[cc][(ni + 1) + (TX + 4) * nj]) * hx;
+                const double dy = -(double)(Xy[cc][ni + TX * (nj + 2)] - Xy[cc][ni + TX * (nj + 1)]) * hy;
+                accU[cc * P + gi] = dx + dy;
+            }
+            const double dJx = -gx * hx;   // S.m and My hold half the metrics
+            const double dJy = -gy * hy;
+            accJ[gi] = dJx + dJy;
+        }
+    }
+}
+
 // --------------------------------------------------------------------------
 // host-side launch
 // --------------------------------------------------------------------------
@@ -175,6 +296,20 @@ static hipError_t launch_dir(const Phys& ph, const Geo& g, const double* JU, con
     return hipGetLastError();
 }
 
+// the x and y directions of a 3D grid in one launch (k_rhs_xy)
+template <int N, int RC>
+static hipError_t launch_xy(const Phys& ph, const Geo& g, const double* JU, const double* J,
+                            const double* jxx, const double* jxt, double* accU, double* accJ,
+                            const double* tdiv, unsigned* status, hipStream_t s)
+{
+    constexpr int TX = 16, TY = 15;
+    const long gx = (g.n[0] + TX - 1) / TX, gy = (g.n[1] + TY - 1) / TY, gz = g.n[2];
+    if (g.ng < 3 || gx * gy * gz > 0x7fffffffL || gy > 65535 || gz > 65535) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((k_rhs_xy<N, TX, TY, RC>), dim3((unsigned)gx, (unsigned)gy, (unsigned)gz), dim3(512), 0, s,
+                       ph, g, JU, J, jxx, jxt, accU, accJ, tdiv, status);
+    return hipGetLastError();
+}
+
 template <int N, int D, typename R, int RC>
 static hipError_t rhs_all(const Phys& ph, const Geo& g, const double* JU, const double* J,
                           const double* jxx, const double* jxt, double* outU, double* outJ,
@@ -182,6 +317,14 @@ static hipError_t rhs_all(const Phys& ph, const Geo& g, const double* JU, const 
 {
     RkArgs none{nullptr, nullptr, nullptr, 0.0, 0.0};
     if (rk) none.tdiv = rk->tdiv;
+    // FP64 3D: x and y in one launch, then the z sweep (bitwise the three
+    // sweeps' result)
+    if constexpr (D == 3 && sizeof(R) == 8) {
+        hipError_t e = launch_xy<N, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none.tdiv, status, s);
+        if (e != hipSuccess) return e;
+        if (rk) return launch_dir<N, D, 2, MODE_RK, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, *rk, status, s);
+        return launch_dir<N, D, 2, MODE_ADD, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
+    }
     hipError_t e = launch_dir<N, D, 0, MODE_WRITE, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none,
                                                       status, s);
     if (e != hipSuccess) return e;
