@@ -233,6 +233,10 @@ k_rhs_xy(Phys ph, Geo g, const double* __restrict__ JU, const double* __restrict
     const int o_along = ydir ? oy : ox, o_line = ydir ? ox : oy;
     const int n_line = ydir ? nx : ny, np_along = ydir ? np1 : np0;
     const bool f_ok = (u < (TL + 1) * TC) && (o_line + fc < n_line) && (o_along + fi + 2 + ng < np_along);
+    // one copy of the arithmetic for both directions, the tile strides,
+    // metric array and exchange rows picked per wave (compiling each
+    // direction's arithmetic on its own under a branch took 4 % longer: the
+    // join spills registers)
     const int sl = ydir ? NEX : 1, sc = ydir ? 1 : NEX, l0 = ydir ? 3 : 3 * NEX;
     const int xl = ydir ? TX : 1, xc = ydir ? 1 : TX + 4;
     interface_fluxes_m<N, D, NN, XS, true, RC, R, 2>(
@@ -324,18 +328,19 @@ static hipError_t rhs_all(const Phys& ph, const Geo& g, const double* JU, const 
         if (e != hipSuccess) return e;
         if (rk) return launch_dir<N, D, 2, MODE_RK, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, *rk, status, s);
         return launch_dir<N, D, 2, MODE_ADD, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
-    }
-    hipError_t e = launch_dir<N, D, 0, MODE_WRITE, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none,
-                                                      status, s);
-    if (e != hipSuccess) return e;
-    if constexpr (D == 2) {
-        if (rk) return launch_dir<N, D, 1, MODE_RK, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, *rk, status, s);
-        return launch_dir<N, D, 1, MODE_ADD, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
     } else {
-        e = launch_dir<N, D, 1, MODE_ADD, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
+        hipError_t e = launch_dir<N, D, 0, MODE_WRITE, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none,
+                                                          status, s);
         if (e != hipSuccess) return e;
-        if (rk) return launch_dir<N, D, 2, MODE_RK, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, *rk, status, s);
-        return launch_dir<N, D, 2, MODE_ADD, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
+        if constexpr (D == 2) {
+            if (rk) return launch_dir<N, D, 1, MODE_RK, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, *rk, status, s);
+            return launch_dir<N, D, 1, MODE_ADD, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
+        } else {
+            e = launch_dir<N, D, 1, MODE_ADD, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
+            if (e != hipSuccess) return e;
+            if (rk) return launch_dir<N, D, 2, MODE_RK, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, *rk, status, s);
+            return launch_dir<N, D, 2, MODE_ADD, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
+        }
     }
 }
 
