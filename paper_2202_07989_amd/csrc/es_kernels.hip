@@ -303,10 +303,9 @@ __device__ __forceinline__ double xs_at(const double* xn, const double* disp, do
 //   current plane with a 3-node halo in LDS for the x/y-differences (two
 //   loads per value, each used by up to 13 nodes).
 //   Pass 2 (64 x 4 columns, so a wavefront reads 64 consecutive doubles of a
-//   row) reads the in-plane neighbours of the products straight from memory:
-//   the neighbouring rows are read by other waves at the same time and come
-//   from the caches, and with no LDS and no barrier every wave walks at its
-//   own pace.  Both shapes were the faster of the two designs for their pass.
+//   row) stages the in-plane neighbours of the products of the current plane
+//   in LDS (Pr[2] along x and y, Pr[0] along y, Pr[1] along x, 3-node
+//   halos): 1011 us at 256^3 against 1195 us reading them from the caches.
 constexpr int MT = 16;
 constexpr int MH = MT + 6;
 constexpr int MX = 64, MY = 4;
@@ -401,78 +400,122 @@ k_metric_prod3(Geo g, Phys ph, const double* __restrict__ xn, const double* __re
     }
 }
 
-__global__ void __launch_bounds__(MX * MY)
+__global__ void __launch_bounds__(MX * MY) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_metric3(Geo g, Phys ph, const double* __restrict__ disp, const double* __restrict__ Pr,
           const double* __restrict__ dt_dev, double* __restrict__ jxx, double* __restrict__ jxt,
           int zchunk, const int* __restrict__ reuse)
 {
     if (reuse && *reuse) return;
+    // the in-plane neighbours of plane z: Pr[2][j] along x and y, Pr[0][j]
+    // along y, Pr[1][j] along x (the tile plus a 3-node halo; the corners of
+    // the Pr[2] patch are never read)
+    __shared__ double L2[3][MY + 6][MX + 6];
+    __shared__ double L0[3][MY + 6][MX];
+    __shared__ double L1[3][MY][MX + 6];
     const long P = g.P;
     const int np0 = g.np[0], np1 = g.np[1];
     int bx, by, bz;
     xcd_tile(bx, by, bz);
-    const int x = g.ng + bx * MX + threadIdx.x, y = g.ng + by * MY + threadIdx.y;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int xt = g.ng + bx * MX, yt = g.ng + by * MY;
+    const int x = xt + tx, y = yt + ty;
     const int zc0 = g.ng + bz * zchunk, zc1 = min(zc0 + zchunk, g.ng + g.n[2]);
-    if (x >= g.ng + g.n[0] || y >= g.ng + g.n[1]) return;
+    const bool in = x < g.ng + g.n[0] && y < g.ng + g.n[1];
     const double dt = dt_dev ? *dt_dev : 0.0;
     const double idt = dt > 0.0 ? 1.0 / dt : 0.0;   // mesh velocity = disp / dt
     const double al[3] = {ph.alpha[0], ph.alpha[1], ph.alpha[2]};
     const double s01 = g.idxi[0] * g.idxi[1], s12 = g.idxi[1] * g.idxi[2], s20 = g.idxi[2] * g.idxi[0];
-    const long sy = np0;
+    const int t = tx + MX * ty;
     double ring[6][7];   // Pr[0][j] (0..2) and Pr[1][j] (3..5) at the own node, planes zl-6..zl
 #pragma unroll
     for (int c = 0; c < 6; c++)
 #pragma unroll
         for (int r = 0; r < 7; r++) ring[c][r] = 0.0;
-    for (int zl = zc0 - 3; zl < zc1 + 3; zl++) {
-        const long il = ((long)zl * np1 + y) * np0 + x;
+    // the ring advances on every thread (a column beyond a ragged tile reads
+    // the last padded node instead): a shift under a branch would keep two
+    // copies of the ring live
+    const int xr = min(x, np0 - 1), yr = min(y, np1 - 1);
+    auto advance = [&](int zl) {   // ring slot r then holds plane zl - 6 + r
+        const long il = ((long)zl * np1 + yr) * np0 + xr;
 #pragma unroll
         for (int c = 0; c < 6; c++) {
 #pragma unroll
             for (int r = 0; r < 6; r++) ring[c][r] = ring[c][r + 1];
             ring[c][6] = Pr[(long)c * P + il];
         }
-        const int z = zl - 3;
-        if (z < zc0) continue;
-        const long i = ((long)z * np1 + y) * np0 + x;
-        double M[3][3];
+    };
+    for (int zl = zc0 - 3; zl < zc0 + 3; zl++) advance(zl);
+    for (int z = zc0; z < zc1; z++) {
+        advance(z + 3);
+        const long pz = (long)z * np1;
+#pragma unroll 1
+        for (int q = t; q < (MY + 6) * (MX + 6); q += MX * MY) {
+            const int hx = q % (MX + 6), hy = q / (MX + 6);
+            const bool cx = hx >= 3 && hx < MX + 3, cy = hy >= 3 && hy < MY + 3;
+            const int gx = xt - 3 + hx, gy = yt - 3 + hy;
+            if (!(cx || cy) || gx >= np0 || gy >= np1) continue;
+            const long gi = (pz + gy) * np0 + gx;
 #pragma unroll
-        for (int j = 0; j < 3; j++) {
-            const double* P0 = Pr + (long)j * P + i;
-            const double* P1 = Pr + (long)(3 + j) * P + i;
-            const double* P2 = Pr + (long)(6 + j) * P + i;
-            // k = 0 (a = 1, b = 2): delta_2 Pr[1][j] - delta_1 Pr[2][j]
-            const double* r1 = ring[3 + j];
-            const double t1 = cdiff(al, r1[4], r1[2], r1[5], r1[1], r1[6], r1[0]);
-            const double t2 = cdiff(al, P2[sy], P2[-sy], P2[2 * sy], P2[-2 * sy], P2[3 * sy], P2[-3 * sy]);
-            M[0][j] = (t1 - t2) * s12;
-            // k = 1 (a = 2, b = 0): delta_0 Pr[2][j] - delta_2 Pr[0][j]
-            const double* r0 = ring[j];
-            const double u1 = cdiff(al, P2[1], P2[-1], P2[2], P2[-2], P2[3], P2[-3]);
-            const double u2 = cdiff(al, r0[4], r0[2], r0[5], r0[1], r0[6], r0[0]);
-            M[1][j] = (u1 - u2) * s20;
-            // k = 2 (a = 0, b = 1): delta_1 Pr[0][j] - delta_0 Pr[1][j]
-            const double v1 = cdiff(al, P0[sy], P0[-sy], P0[2 * sy], P0[-2 * sy], P0[3 * sy], P0[-3 * sy]);
-            const double v2 = cdiff(al, P1[1], P1[-1], P1[2], P1[-2], P1[3], P1[-3]);
-            M[2][j] = (v1 - v2) * s01;
-        }
+            for (int j = 0; j < 3; j++) L2[j][hy][hx] = Pr[(long)(6 + j) * P + gi];
+            if (cx) {
 #pragma unroll
-        for (int k = 0; k < 3; k++)
+                for (int j = 0; j < 3; j++) L0[j][hy][hx - 3] = Pr[(long)j * P + gi];
+            }
+            if (cy) {
 #pragma unroll
-            for (int j = 0; j < 3; j++) __builtin_nontemporal_store(M[k][j], &jxx[(k * 3 + j) * P + i]);
-        if (jxt) {
-            double w[3] = {0.0, 0.0, 0.0};
-            if (disp && dt > 0.0)
-#pragma unroll
-                for (int j = 0; j < 3; j++) w[j] = disp[j * P + i] * idt;
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                double nt = 0.0;
-#pragma unroll
-                for (int j = 0; j < 3; j++) nt -= w[j] * M[k][j];
-                __builtin_nontemporal_store(nt, &jxt[k * P + i]);
+                for (int j = 0; j < 3; j++) L1[j][hy - 3][hx] = Pr[(long)(3 + j) * P + gi];
             }
         }
+        __syncthreads();
+        if (in) {
+            const long i = (pz + y) * np0 + x;
+            const int cx = tx + 3, cy = ty + 3;
+            // one j at a time: its three metrics are stored and folded into
+            // the time metrics at once (the sum over j in the same order)
+            double w[3] = {0.0, 0.0, 0.0};
+            if (jxt && disp && dt > 0.0)
+#pragma unroll
+                for (int j = 0; j < 3; j++) w[j] = disp[j * P + i] * idt;
+            double nt[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                // each difference reads its six LDS values after a point that
+                // no LDS read moves across, so few of them are live beside
+                // the ring (four waves per SIMD without spills)
+                double M[3];
+                // k = 0 (a = 1, b = 2): delta_2 Pr[1][j] - delta_1 Pr[2][j]
+                const double* r1 = ring[3 + j];
+                const double t1 = cdiff(al, r1[4], r1[2], r1[5], r1[1], r1[6], r1[0]);
+                asm volatile("" ::: "memory");
+                const double t2 = cdiff(al, L2[j][cy + 1][cx], L2[j][cy - 1][cx], L2[j][cy + 2][cx],
+                                        L2[j][cy - 2][cx], L2[j][cy + 3][cx], L2[j][cy - 3][cx]);
+                M[0] = (t1 - t2) * s12;
+                // k = 1 (a = 2, b = 0): delta_0 Pr[2][j] - delta_2 Pr[0][j]
+                const double* r0 = ring[j];
+                asm volatile("" ::: "memory");
+                const double u1 = cdiff(al, L2[j][cy][cx + 1], L2[j][cy][cx - 1], L2[j][cy][cx + 2],
+                                        L2[j][cy][cx - 2], L2[j][cy][cx + 3], L2[j][cy][cx - 3]);
+                const double u2 = cdiff(al, r0[4], r0[2], r0[5], r0[1], r0[6], r0[0]);
+                M[1] = (u1 - u2) * s20;
+                // k = 2 (a = 0, b = 1): delta_1 Pr[0][j] - delta_0 Pr[1][j]
+                asm volatile("" ::: "memory");
+                const double v1 = cdiff(al, L0[j][cy + 1][tx], L0[j][cy - 1][tx], L0[j][cy + 2][tx],
+                                        L0[j][cy - 2][tx], L0[j][cy + 3][tx], L0[j][cy - 3][tx]);
+                asm volatile("" ::: "memory");
+                const double v2 = cdiff(al, L1[j][ty][cx + 1], L1[j][ty][cx - 1], L1[j][ty][cx + 2],
+                                        L1[j][ty][cx - 2], L1[j][ty][cx + 3], L1[j][ty][cx - 3]);
+                M[2] = (v1 - v2) * s01;
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    __builtin_nontemporal_store(M[k], &jxx[(k * 3 + j) * P + i]);
+                    nt[k] -= w[j] * M[k];
+                }
+            }
+            if (jxt)
+#pragma unroll
+                for (int k = 0; k < 3; k++) __builtin_nontemporal_store(nt[k], &jxt[k * P + i]);
+        }
+        __syncthreads();   // the next plane overwrites the patch
     }
 }
 
