@@ -22,34 +22,36 @@ namespace es {
 // when exactly one of a, b is k: the values the mirrored mesh has.  The
 // state is filled by fill_state.
 // ---------------------------------------------------------------------------
+// (index arithmetic in 32 bits: a grid holds fewer than 2^31 / 9 points,
+// which the context checks at creation, and 64-bit division is a long
+// software sequence on the GPU)
 __device__ __forceinline__ void shell_node(const Geo& g, long t, long nzs, long nys, int d[3])
 {
-    const int ng = g.ng;
-    const int np0 = g.np[0], np1 = g.np[1];
-    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
-    const int z0 = g.dim == 3 ? ng : 0;
+    const unsigned ng = g.ng;
+    const unsigned np0 = g.np[0], np1 = g.np[1];
+    const unsigned n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    const int z0 = g.dim == 3 ? (int)ng : 0;
     if (t < nzs) {                                   // z ghost planes
-        const long pl = (long)np0 * np1;
-        const int k = (int)(t / pl);
-        const int r = (int)(t % pl);
-        d[2] = k < ng ? k : k + n2;
-        d[1] = r / np0;
-        d[0] = r % np0;
+        const unsigned u = (unsigned)t, pl = np0 * np1;
+        const unsigned k = u / pl, r = u - k * pl;
+        d[2] = (int)(k < ng ? k : k + n2);
+        const unsigned y = r / np0;
+        d[1] = (int)y;
+        d[0] = (int)(r - y * np0);
     } else if (t < nzs + nys) {                      // y ghost rows over interior z
-        const long u = t - nzs;
-        const long per = 2L * ng * np0;
-        d[2] = z0 + (int)(u / per);
-        const int r = (int)(u % per);
-        const int k = r / np0;
-        d[1] = k < ng ? k : k + n1;
-        d[0] = r % np0;
+        const unsigned u = (unsigned)(t - nzs), per = 2u * ng * np0;
+        const unsigned zz = u / per, r = u - zz * per;
+        d[2] = z0 + (int)zz;
+        const unsigned k = r / np0;
+        d[1] = (int)(k < ng ? k : k + n1);
+        d[0] = (int)(r - k * np0);
     } else {                                         // x ghost columns over interior y, z
-        const long u = t - nzs - nys;
-        const long row = u / (2 * ng);
-        const int k = (int)(u % (2 * ng));
-        d[0] = k < ng ? k : k + n0;
-        d[1] = ng + (int)(row % n1);
-        d[2] = z0 + (int)(row / n1);
+        const unsigned u = (unsigned)(t - nzs - nys), w = 2u * ng;
+        const unsigned row = u / w, k = u - row * w;
+        d[0] = (int)(k < ng ? k : k + n0);
+        const unsigned zz = row / n1;
+        d[1] = (int)(ng + (row - zz * n1));
+        d[2] = z0 + (int)zz;
     }
 }
 
@@ -204,12 +206,14 @@ hipError_t fill_state(const Geo& g, const InflowStates& in, double* JU, double* 
 }
 
 // interior node q (0 .. nint-1) -> padded index
+// (32-bit index arithmetic, as in shell_node)
 __device__ __forceinline__ long interior_node(const Geo& g, long q, int& i0, int& i1, int& i2)
 {
-    i0 = (int)(q % g.n[0]) + g.ng;
-    const long r = q / g.n[0];
-    i1 = (int)(r % g.n[1]) + g.ng;
-    i2 = (int)(r / g.n[1]) + (g.dim == 3 ? g.ng : 0);
+    const unsigned u = (unsigned)q, n0 = g.n[0], n1 = g.n[1];
+    const unsigned r = u / n0, z = r / n1;
+    i0 = (int)(u - r * n0) + g.ng;
+    i1 = (int)(r - z * n1) + g.ng;
+    i2 = (int)z + (g.dim == 3 ? g.ng : 0);
     return node_index(g, i0, i1, i2);
 }
 
