@@ -30,6 +30,11 @@ def case_spec(name, dissipation=1):
     elif name == "3d-n2-water":
         sp = I.make_spec(3, 2, (17, 16, 19), chi=I.CHI_SHOCK, **WATER)
         init = lambda s: I.init_random(s, seed=16, noise=0.4, p_range=(1e5, 1e9))
+    elif name == "3d-n2-thin":
+        # one ragged tile along x (5 < 16) and z (4), ragged last tiles along
+        # y (33), for the x-y launch and the z-walking stencil kernels
+        sp = I.make_spec(3, 2, (5, 33, 4), chi=I.CHI_SHOCK, **WATER)
+        init = lambda s: I.init_random(s, seed=17, noise=0.4, p_range=(1e5, 1e9))
     elif name == "3d-n2-random":
         sp = I.make_spec(3, 2, (17, 19, 18), gamma=(4.4, 1.4), cv=(1.0, 2.0), pinf=(100.0, 0.0),
                          chi=I.CHI_SHOCK)
@@ -40,7 +45,7 @@ def case_spec(name, dissipation=1):
     return sp, init
 
 
-CASES = ["2d-n1", "2d-n1-stiff", "2d-n2-bubble", "3d-n1", "3d-n2-bubble", "3d-n2-random"]
+CASES = ["2d-n1", "2d-n1-stiff", "2d-n2-bubble", "3d-n1", "3d-n2-bubble", "3d-n2-random", "3d-n2-thin"]
 # noisy random states, one and two species, up to the water stiffness
 RANDOM_CASES = ["2d-n1", "2d-n1-stiff", "2d-n2-random", "3d-n1", "3d-n2-random", "3d-n2-water"]
 

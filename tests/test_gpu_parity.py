@@ -184,7 +184,8 @@ def test_rk_stage_parity(name):
 
 @pytest.mark.parametrize("name,move,nsteps,tol", [("2d-n1", False, 3, TOL_FP64),
                                                   ("2d-n2-bubble", True, 3, TOL_FP64),
-                                                  ("3d-n2-bubble", True, 2, TOL_FP64)])
+                                                  ("3d-n2-bubble", True, 2, TOL_FP64),
+                                                  ("3d-n2-thin", True, 2, TOL_FP64)])
 def test_step_parity(name, move, nsteps, tol):
     say(f"[step parity] {name} move={move} steps={nsteps}")
     sp, o, JU, J, x, disp, jx, jt = prepared(name)
