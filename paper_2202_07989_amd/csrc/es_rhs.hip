@@ -1,7 +1,9 @@
 // es_rhs.hip -- the semi-discrete right-hand side (Sections 3.1-3.4) and the
 // fused SSP-RK3 stage (Section 5) on gfx950.
 //
-// One launch per direction k.  A block of 256 threads owns a tile of TL
+// k_rhs_dir is one launch per direction k; k_rhs_xy (below) builds the x and
+// y directions of a 3D grid in one launch, and FP64 3D stages take it and
+// then the z sweep.  In k_rhs_dir a block of 256 threads owns a tile of TL
 // nodes along k on TC grid lines (consecutive in the line ordering, so the
 // fastest other index runs along the lines and global loads coalesce),
 // stages the node quantities of the tile plus a 3-node halo along k in LDS,
