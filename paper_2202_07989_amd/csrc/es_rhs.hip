@@ -2,8 +2,8 @@
 // fused SSP-RK3 stage (Section 5) on gfx950.
 //
 // k_rhs_dir is one launch per direction k; k_rhs_xy (below) builds the x and
-// y directions of a 3D grid in one launch, and FP64 3D stages take it and
-// then the z sweep.  In k_rhs_dir a block of 256 threads owns a tile of TL
+// y directions of a 3D grid in one launch, and 3D stages take it and then
+// the z sweep.  In k_rhs_dir a block of 256 threads owns a tile of TL
 // nodes along k on TC grid lines (consecutive in the line ordering, so the
 // fastest other index runs along the lines and global loads coalesce),
 // stages the node quantities of the tile plus a 3-node halo along k in LDS,
@@ -164,13 +164,12 @@ k_rhs_dir(Phys ph, Geo g, const double* __restrict__ JU, const double* __restric
 // skips the accumulator's round trip through memory.  LDS: 70 KB at
 // 16 x 15 with two species, two blocks (four waves per SIMD) per compute
 // unit.
-template <int N, int TX, int TY, int RC>
+template <int N, int TX, int TY, typename R, int RC, int MG>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_rhs_xy(Phys ph, Geo g, const double* __restrict__ JU, const double* __restrict__ Jv,
          const double* __restrict__ jxx, const double* __restrict__ jxt, double* __restrict__ accU,
          double* __restrict__ accJ, const double* __restrict__ tdiv, unsigned* __restrict__ status)
 {
-    using R = double;
     constexpr int D = 3;
     constexpr int NT = 512;
     constexpr int NC = N + D + 1;
@@ -241,7 +240,7 @@ k_rhs_xy(Phys ph, Geo g, const double* __restrict__ JU, const double* __restrict
     // join spills registers)
     const int sl = ydir ? NEX : 1, sc = ydir ? 1 : NEX, l0 = ydir ? 3 : 3 * NEX;
     const int xl = ydir ? TX : 1, xc = ydir ? 1 : TX + 4;
-    interface_fluxes_m<N, D, NN, XS, true, RC, R, 2>(
+    interface_fluxes_m<N, D, NN, XS, true, RC, R, MG>(
         ph, S, ydir ? My : S.m, ydir ? Xb + NC : Xb, [=](int l, int c) { return l0 + l * sl + c * sc; },
         [=](int s, int c) { return s * xl + c * xc; }, [=](int c) { return o_line + c < n_line; }, fi, fc,
         f_ok, u - (int)(blockIdx.x & 3) * 64, TL, TC);
@@ -303,7 +302,7 @@ static hipError_t launch_dir(const Phys& ph, const Geo& g, const double* JU, con
 }
 
 // the x and y directions of a 3D grid in one launch (k_rhs_xy)
-template <int N, int RC>
+template <int N, typename R, int RC, int MG>
 static hipError_t launch_xy(const Phys& ph, const Geo& g, const double* JU, const double* J,
                             const double* jxx, const double* jxt, double* accU, double* accJ,
                             const double* tdiv, unsigned* status, hipStream_t s)
@@ -311,7 +310,7 @@ static hipError_t launch_xy(const Phys& ph, const Geo& g, const double* JU, cons
     constexpr int TX = 16, TY = 15;
     const long gx = (g.n[0] + TX - 1) / TX, gy = (g.n[1] + TY - 1) / TY, gz = g.n[2];
     if (g.ng < 3 || gx * gy * gz > 0x7fffffffL || gy > 65535 || gz > 65535) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((k_rhs_xy<N, TX, TY, RC>), dim3((unsigned)gx, (unsigned)gy, (unsigned)gz), dim3(512), 0, s,
+    hipLaunchKernelGGL((k_rhs_xy<N, TX, TY, R, RC, MG>), dim3((unsigned)gx, (unsigned)gy, (unsigned)gz), dim3(512), 0, s,
                        ph, g, JU, J, jxx, jxt, accU, accJ, tdiv, status);
     return hipGetLastError();
 }
@@ -323,10 +322,11 @@ static hipError_t rhs_all(const Phys& ph, const Geo& g, const double* JU, const 
 {
     RkArgs none{nullptr, nullptr, nullptr, 0.0, 0.0};
     if (rk) none.tdiv = rk->tdiv;
-    // FP64 3D: x and y in one launch, then the z sweep (bitwise the three
-    // sweeps' result)
-    if constexpr (D == 3 && sizeof(R) == 8) {
-        hipError_t e = launch_xy<N, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none.tdiv, status, s);
+    // 3D: x and y in one launch, then the z sweep (bitwise the three sweeps'
+    // result, in both precisions; two field groups in the dissipation, which
+    // keeps the FP32 launch at 90 registers)
+    if constexpr (D == 3) {
+        hipError_t e = launch_xy<N, R, RC, 2>(ph, g, JU, J, jxx, jxt, outU, outJ, none.tdiv, status, s);
         if (e != hipSuccess) return e;
         if (rk) return launch_dir<N, D, 2, MODE_RK, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, *rk, status, s);
         return launch_dir<N, D, 2, MODE_ADD, R, RC>(ph, g, JU, J, jxx, jxt, outU, outJ, none, status, s);
