@@ -268,7 +268,9 @@ int es_step(es_ctx *c, const es_monitor *m, double cfl, double dt_fixed,
             double *dtau_dev, void *stream);
 
 /* Synchronise the stream and return the status word (bits ES_ST_*) in
- * *flags; returns ES_ENONPHYS / ES_ETANGLE when a bit is set, else ES_OK.
+ * *flags; returns ES_ETANGLE when ES_ST_TANGLE is set (a node with J <= 0
+ * also has a non-physical U = JU / J, so the mesh is reported as the
+ * cause), else ES_ENONPHYS when ES_ST_NONPHYS is set, else ES_OK.
  * reset != 0 clears the word afterwards. */
 int es_status(es_ctx *c, void *stream, unsigned *flags, int reset);
 

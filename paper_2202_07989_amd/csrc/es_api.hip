@@ -462,8 +462,8 @@ int es_status(es_ctx* c, void* stream, unsigned* flags, int reset)
         if (hipStreamSynchronize(s) != hipSuccess) return ES_EHIP;
     }
     if (flags) *flags = h;
-    if (h & ES_ST_NONPHYS) return ES_ENONPHYS;
     if (h & ES_ST_TANGLE) return ES_ETANGLE;
+    if (h & ES_ST_NONPHYS) return ES_ENONPHYS;
     return ES_OK;
 }
 
@@ -731,8 +731,8 @@ int es_batch_status(es_batch* b, void* stream, unsigned* flags, int reset)
         if (hipStreamSynchronize(s) != hipSuccess) return ES_EHIP;
     }
     if (flags) *flags = h;
-    if (h & ES_ST_NONPHYS) return ES_ENONPHYS;
     if (h & ES_ST_TANGLE) return ES_ETANGLE;
+    if (h & ES_ST_NONPHYS) return ES_ENONPHYS;
     return ES_OK;
 }
 
