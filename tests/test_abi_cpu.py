@@ -109,3 +109,39 @@ def test_face_conditions_checked_before_any_launch(lib):
     grids = (es.EsGrid * 1)(es.make_grid(sp))
     assert es.lib.es_batch_create(C.cast(grids, C.c_void_p), 1, C.byref(h)) == es.ES_EUNSUPPORTED
     assert es.lib.es_fill_ghosts_state(None, None, None, None) == es.ES_EINVAL
+
+
+def test_invalid_grids_rejected_by_library_and_oracle(lib):
+    """The same malformed grids (zero spacing, a half-periodic direction,
+    faces out of order, an unknown face kind, a sign-test tolerance outside
+    [0, 1)) are argument errors of both implementations: es_create returns
+    ES_EINVAL and the oracle's calls return its EINVAL (-1), before any
+    array is read."""
+    import numpy as np
+
+    import oracle
+    from paper_2202_07989_amd import es
+    from paper_2202_07989_amd import inputs as I
+    h = C.c_void_p()
+    base = I.spec_shock_bubble_walled("he", (16, 8))
+    for bad in ("dxi", "half-periodic", "wall-order", "kind", "sign_tol", "sign_tol-big", "sign_tol-nan"):
+        g = es.make_grid(base)
+        o = oracle.Oracle(base)
+        for gg in (g, o.g):
+            if bad == "dxi":
+                gg.dxi[0] = 0.0
+            elif bad == "half-periodic":
+                gg.bc[1][0] = es.ES_BC_PERIODIC
+            elif bad == "wall-order":
+                gg.wall[1][0], gg.wall[1][1] = 1.0, -1.0
+            elif bad == "kind":
+                gg.bc[0][1] = 7
+            elif bad == "sign_tol":
+                gg.sign_tol = -1e-12
+            elif bad == "sign_tol-big":
+                gg.sign_tol = 1.0
+            elif bad == "sign_tol-nan":
+                gg.sign_tol = float("nan")
+        assert es.lib.es_create(C.byref(g), C.byref(h)) == es.ES_EINVAL, bad
+        z = np.zeros(8)
+        assert o.L.orc_rhs(o.gp, *(z.ctypes.data_as(C.POINTER(C.c_double)) for _ in range(6))) == -1, bad
