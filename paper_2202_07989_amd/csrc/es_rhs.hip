@@ -223,9 +223,9 @@ k_rhs_xy(Phys ph, Geo g, const double* __restrict__ JU, const double* __restrict
 
     // ---- interface fluxes: x in waves 0-3, y in waves 4-7 ------------------
     // x: interface fi of row fc (along-fastest, so a wave reads consecutive
-    // nodes of a row); y: interface fi of column fc (column-fastest)
-    // the direction is uniform over a wave: read it from the first lane so
-    // that everything derived from it lives in scalar registers
+    // nodes of a row); y: interface fi of column fc (column-fastest).  The
+    // direction is uniform over a wave; read from the first lane, everything
+    // derived from it lives in scalar registers
     const bool ydir = __builtin_amdgcn_readfirstlane(t / (NT / 2)) != 0;
     const int u = t & (NT / 2 - 1);
     const int TL = ydir ? TY : TX, TC = ydir ? TX : TY;
